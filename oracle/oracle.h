@@ -1,0 +1,100 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of one soft-sphere DEM step for rigid
+ * aggregates of bonded spheres (Marohnic et al., arXiv 2311.11322).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library
+ * against the paper; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  It shares no source with the
+ * GPU library and is deliberately simple: scalar loops, brute-force O(N^2)
+ * pair search and gravity, no blocking, no fusion, no reordering.
+ *
+ * All floating point is IEEE double, compiled without FMA contraction.
+ */
+#ifndef DEM_ORACLE_H
+#define DEM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double dt;          /* fixed leapfrog step h (Sec. 2.1)                       */
+    double G;           /* gravitational constant; 0 disables self-gravity         */
+    double soft_frac;   /* Plummer softening eps_ij = soft_frac*(s_i+s_j)/2        */
+    double k_n, k_t;    /* normal / tangential spring constants (Sec. 2.1)         */
+    double eps_n, eps_t;/* normal / tangential restitution -> dashpot constants    */
+    double mu_s, mu_r, mu_t; /* sliding, rolling, twisting friction coefficients   */
+    double k_r, k_q;    /* rolling / twisting spring constants                     */
+    int32_t periodic;   /* 1: periodic cube of side box[0..2]                      */
+    double box[3];
+    double spin_dw;     /* spin-up forcing: spin increment per step about +z      */
+    int32_t torque_at_centre; /* negative control only: apply contact forces at
+                                 sphere centres instead of the contact point       */
+} ora_params;
+
+typedef struct ora_sim ora_sim;
+
+ora_sim* ora_create(const ora_params* p);
+void     ora_destroy(ora_sim* s);
+
+/* Add all aggregates at once.  Spheres are grouped by aggregate.  evaluate=1
+ * performs the initial force evaluation at t0 (needed before the first step);
+ * evaluate=0 skips it (for sampled checks at sizes where O(N^2) is too slow).
+ * Returns 0 on success, <0 on invalid input. */
+int ora_add(ora_sim* s, int64_t n_agg, const int32_t* counts,
+            const double* pos, const double* radius, const double* mass,
+            const double* agg_vel, const double* agg_spin, int32_t evaluate);
+
+int ora_step(ora_sim* s, int64_t n_steps);
+
+/* State read-out (caller-owned buffers, NULL to skip a field). */
+void ora_get_counts(const ora_sim* s, int64_t* n_agg, int64_t* n_sph, int64_t* n_pairs);
+void ora_get_aggregates(const ora_sim* s, double* M, double* rA, double* vA, double* aA,
+                        double* NA, double* q, double* wb, double* wA, double* I);
+void ora_get_spheres(const ora_sim* s, double* r, double* v, double* F, double* tau,
+                     double* body);
+/* Per-pair output of the last evaluation, canonical (i<j, lexicographic).
+ * hist: 7 per pair (xi_t[3], xi_r[3], xi_q).  force: F on i[3], tau_i[3],
+ * tau_j[3].  diag: f_N, |F_T|, |F_r|, |F_q|, delta, l_i, l_j, sliding flag. */
+void ora_get_pairs(const ora_sim* s, int64_t* pi, int64_t* pj, double* hist,
+                   double* force, double* diag);
+
+/* Diagnostics of the current state: out[0..2] linear momentum, out[3..5]
+ * angular momentum about the origin, out[6] translational KE, out[7]
+ * rotational KE, out[8] normal spring energy, out[9] gravitational energy,
+ * out[10] max overlap, out[11] bulk radius, out[12..14] centre of mass. */
+void ora_diagnostics(ora_sim* s, double* out);
+
+/* Forces and torques on a subset of spheres at the current state, evaluated
+ * one sphere at a time by brute force (contacts with zero spring history,
+ * as at t0, plus direct-sum gravity).  Used for sampled checks at full size. */
+void ora_eval_subset(const ora_sim* s, const int64_t* idx, int64_t n_idx,
+                     double* F, double* tau);
+
+/* Stateless brute-force contact search: all i<j with agg_i != agg_j and
+ * d^2 < (s_i+s_j)^2; box == NULL for open space.  Writes i*2^32+j keys in
+ * lexicographic order.  Returns the number of pairs (may exceed cap; only
+ * the first cap are written). */
+int64_t ora_find_contacts(const double* pos, const double* radius, const int32_t* agg,
+                          int64_t n, const double* box, uint64_t* keys, int64_t cap);
+
+/* Direct-sum softened gravity force on the listed targets. */
+void ora_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
+                 double G, double soft_frac, const int64_t* idx, int64_t n_idx, double* F);
+
+/* One fixed Cash-Karp step of the torque-coupled Euler equations for a single
+ * body (exposed for the rotation pins).  q[4], wb[3] updated in place; err
+ * receives the embedded 4th/5th-order difference norm. */
+void ora_rotate(double* q, double* wb, const double* I, const double* N_space, double h,
+                double* err);
+
+/* Aggregate set-up of one body (exposed for the inertia pins):
+ * M, COM r[3], principal moments I[3], quaternion q[4], body offsets b[3n]. */
+int ora_setup_body(int64_t n, const double* pos, const double* radius, const double* mass,
+                   double* M, double* r, double* I, double* q, double* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,453 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only *places* spheres and draws random numbers.  It contains none
+of the method's arithmetic (no forces, no integration, no aggregate set-up),
+so both the GPU library and the FP64 oracle may consume what it produces.
+
+Workload shapes (all radii U[0.8, 1.2], density 1, aggregates built as random
+touching clusters of equal-density spheres):
+
+* ``periodic_box``  -- aggregates of 1-8 spheres placed by random sequential
+  addition (RSA) in a periodic cube at a target packing fraction, velocities
+  N(0, sigma) per component (the contact-only workload; no gravity).
+* ``collapse_cloud`` -- aggregates of 2-8 spheres placed by RSA in a ball at
+  initial packing fraction phi0 = 0.15, at rest, with self-gravity (the
+  gravitational-collapse workload of Sec. 3.3 / Table 1 of the paper).
+* ``contact_seeded`` -- as either of the above, but every aggregate after the
+  first is put in contact with an already-placed aggregate with a small
+  overlap, so that a single step exercises every branch of the contact model.
+* ``pile_batch`` -- many independent piles with log-uniform sphere counts
+  (the batched spin-up workload).
+
+Every generator takes an explicit seed and uses ``numpy.random.default_rng``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+# Contact constants shared by all workloads (spring constant, restitution and
+# friction coefficients are user parameters of the soft-sphere model, Sec. 2.1).
+CONTACT_PARAMS: Dict[str, float] = dict(
+    k_n=1.0e5,
+    k_t=(2.0 / 7.0) * 1.0e5,
+    eps_n=0.5,
+    eps_t=0.5,
+    mu_s=0.5,
+    mu_r=0.1,
+    mu_t=0.1,
+    k_r=(2.0 / 7.0) * 1.0e5,
+    k_q=(2.0 / 7.0) * 1.0e5,
+)
+
+# Smallest allowed surface gap between spheres of different aggregates when a
+# workload is placed (keeps every candidate pair far from the contact
+# threshold, so the FP64 contact decision is never a rounding coin-flip).
+MIN_GAP = 1.0e-6
+
+
+@dataclasses.dataclass
+class Workload:
+    """One synthetic system, in the layout the C-ABI takes.
+
+    Spheres are grouped by aggregate: aggregate ``a`` owns spheres
+    ``offsets[a] : offsets[a] + counts[a]`` of ``pos``/``radius``/``mass``.
+    """
+
+    name: str
+    counts: np.ndarray      # int32 [n_agg]
+    pos: np.ndarray         # float64 [n_sph, 3], space frame
+    radius: np.ndarray      # float64 [n_sph]
+    mass: np.ndarray        # float64 [n_sph]
+    agg_vel: np.ndarray     # float64 [n_agg, 3]
+    agg_spin: np.ndarray    # float64 [n_agg, 3], space frame
+    params: Dict[str, float]
+    n_steps: int
+    pile_of_agg: Optional[np.ndarray] = None   # int32 [n_agg] for batches
+    notes: str = ""
+
+    @property
+    def n_agg(self) -> int:
+        return int(self.counts.shape[0])
+
+    @property
+    def n_sph(self) -> int:
+        return int(self.pos.shape[0])
+
+    def offsets(self) -> np.ndarray:
+        off = np.zeros(self.n_agg + 1, dtype=np.int64)
+        np.cumsum(self.counts, out=off[1:])
+        return off
+
+    def agg_of_sphere(self) -> np.ndarray:
+        return np.repeat(np.arange(self.n_agg, dtype=np.int32), self.counts)
+
+
+# --------------------------------------------------------------------------
+# random primitives
+# --------------------------------------------------------------------------
+
+def _unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def _random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """Uniformly random proper rotation matrix (from a normalised 4-vector)."""
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def random_cluster(rng: np.random.Generator, n: int,
+                   rmin: float = 0.8, rmax: float = 1.2):
+    """A random touching cluster of ``n`` spheres.
+
+    Each new sphere is placed tangent to a uniformly chosen existing member in
+    a uniform random direction; a placement that would overlap another member
+    is rejected and redrawn.  Returns (offsets from the first sphere, radii).
+    """
+    radii = rng.uniform(rmin, rmax, n)
+    pos = np.zeros((n, 3))
+    for k in range(1, n):
+        for _ in range(10000):
+            a = int(rng.integers(k))
+            u = _unit_vectors(rng, 1)[0]
+            p = pos[a] + (radii[a] + radii[k]) * u
+            d = np.linalg.norm(pos[:k] - p, axis=1)
+            lim = radii[:k] + radii[k]
+            ok = d >= lim * (1.0 - 1e-12)
+            ok[a] = True
+            if ok.all():
+                pos[k] = p
+                break
+        else:  # pragma: no cover - geometrically impossible for n <= 8
+            raise RuntimeError("could not grow cluster")
+    return pos, radii
+
+
+def sphere_mass(radius: np.ndarray, density: float = 1.0) -> np.ndarray:
+    return density * (4.0 / 3.0) * math.pi * radius ** 3
+
+
+# --------------------------------------------------------------------------
+# spatial occupancy grid used only for placement rejection tests
+# --------------------------------------------------------------------------
+
+class _Grid:
+    """Dense cell grid with fixed slots, for O(1) neighbour lookups while
+    placing.  ``periodic`` wraps cell indices."""
+
+    SLOTS = 24
+
+    def __init__(self, lo, hi, cell, periodic=False, box=None):
+        self.lo = np.asarray(lo, dtype=np.float64)
+        self.cell = float(cell)
+        self.periodic = periodic
+        self.box = None if box is None else np.asarray(box, dtype=np.float64)
+        if periodic:
+            self.n = np.maximum((self.box // self.cell).astype(np.int64), 1)
+            self.cell_v = self.box / self.n
+        else:
+            span = np.asarray(hi, dtype=np.float64) - self.lo
+            self.n = np.maximum(np.ceil(span / self.cell).astype(np.int64) + 1, 1)
+            self.cell_v = np.full(3, self.cell)
+        self.slots = -np.ones(tuple(self.n) + (self.SLOTS,), dtype=np.int64)
+        self.fill = np.zeros(tuple(self.n), dtype=np.int32)
+        self.count = 0
+        self._P = np.zeros((1024, 3))
+        self._R = np.zeros(1024)
+
+    def _cells(self, p):
+        c = np.floor((p - self.lo) / self.cell_v).astype(np.int64)
+        if self.periodic:
+            c %= self.n
+        return c
+
+    def neighbours(self, p: np.ndarray) -> np.ndarray:
+        """Indices of stored spheres in the cells touching points ``p``."""
+        c = self._cells(p)
+        lo = c.min(axis=0) - 1
+        hi = c.max(axis=0) + 1
+        if self.periodic:
+            idx = [np.arange(lo[k], hi[k] + 1) % self.n[k] for k in range(3)]
+            idx = [np.unique(ix) for ix in idx]
+            sub = self.slots[np.ix_(idx[0], idx[1], idx[2])]
+        else:
+            lo = np.maximum(lo, 0)
+            hi = np.minimum(hi, self.n - 1)
+            sub = self.slots[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]
+        s = sub.ravel()
+        return s[s >= 0]
+
+    def insert(self, p: np.ndarray, r: np.ndarray):
+        c = self._cells(p)
+        base = self.count
+        k_new = p.shape[0]
+        if base + k_new > self._P.shape[0]:
+            cap = 2 * (base + k_new)
+            self._P = np.concatenate([self._P, np.zeros((cap - self._P.shape[0], 3))])
+            self._R = np.concatenate([self._R, np.zeros(cap - self._R.shape[0])])
+        for k in range(k_new):
+            cx, cy, cz = c[k]
+            f = self.fill[cx, cy, cz]
+            if f >= self.SLOTS:
+                raise RuntimeError("placement grid cell overflow")
+            self.slots[cx, cy, cz, f] = base + k
+            self.fill[cx, cy, cz] = f + 1
+        self._P[base:base + k_new] = p
+        self._R[base:base + k_new] = r
+        self.count = base + k_new
+
+    def arrays(self):
+        return self._P[:self.count], self._R[:self.count]
+
+    def gaps(self, p: np.ndarray, r: np.ndarray):
+        """Surface gaps between candidate spheres and stored neighbours.
+        Returns (gap matrix [k, m], neighbour indices [m])."""
+        nb = self.neighbours(p)
+        if nb.size == 0:
+            return np.zeros((p.shape[0], 0)), nb
+        P, R = self.arrays()
+        d = P[nb][None, :, :] - p[:, None, :]
+        if self.periodic:
+            d -= self.box * np.round(d / self.box)
+        dist = np.sqrt((d * d).sum(axis=2))
+        return dist - (R[nb][None, :] + r[:, None]), nb
+
+
+def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
+           near_after=200):
+    """Random sequential addition of whole aggregates (largest first).
+
+    container: ("ball", R) or ("box", L).  If ``contact_seeded`` every
+    aggregate after the first is put in contact, with overlap drawn from
+    U[1e-5, 1e-3], with a sphere of an already-placed aggregate.  Otherwise,
+    once ``near_after`` uniform draws for one aggregate have failed (close to
+    the jamming limit of RSA), candidates are drawn next to a placed sphere at
+    a surface gap of U[1e-5, 1e-3] instead.
+    Returns positions grouped in the *original* aggregate order.
+    """
+    kind, size = container
+    order = np.argsort(-counts, kind="stable")
+    if kind == "box":
+        L = float(size)
+        grid = _Grid(np.zeros(3), None, 2.4, periodic=True, box=np.full(3, L))
+    else:
+        R = float(size)
+        grid = _Grid(np.full(3, -R - 3.0), np.full(3, R + 3.0), 2.4)
+    placed_pos = [None] * len(counts)
+    sph_owner: List[int] = []
+    for n_done, a in enumerate(order):
+        rel, rad = clusters[a]
+        rel = rel - rel.mean(axis=0)
+        ext = np.linalg.norm(rel, axis=1).max() + rad.max()
+        for tries in range(max_tries):
+            rot = _random_rotation(rng)
+            body = rel @ rot.T
+            seeded = contact_seeded and n_done > 0
+            near = (not seeded) and n_done > 0 and tries >= near_after
+            if seeded or near:
+                # put member m against placed sphere t: overlapping it by
+                # U[1e-5, 1e-3] (contact-seeded) or, when plain random draws
+                # keep failing near jamming, at a gap of U[1e-5, 1e-3]
+                P, Rr = grid.arrays()
+                t = int(rng.integers(P.shape[0]))
+                m = int(rng.integers(body.shape[0]))
+                u = _unit_vectors(rng, 1)[0]
+                delta0 = rng.uniform(1e-5, 1e-3)
+                sep = Rr[t] + rad[m] + (-delta0 if seeded else delta0)
+                centre = P[t] + sep * u - body[m]
+                if not seeded:
+                    t = -1
+            else:
+                t = -1
+                if kind == "box":
+                    centre = rng.uniform(0.0, L, 3)
+                else:
+                    v = _unit_vectors(rng, 1)[0]
+                    centre = v * (R - ext) * rng.uniform() ** (1.0 / 3.0)
+            if kind == "box":
+                # keep the aggregate whole; only its centre is wrapped
+                centre = np.mod(centre, L)
+            elif np.linalg.norm(centre) + ext > R:
+                continue
+            p = centre + body
+            gap, nb = grid.gaps(p, rad)
+            if gap.size:
+                if t >= 0:
+                    # the seeded pair is the only allowed overlap
+                    ok_mask = gap >= MIN_GAP
+                    seeded = nb == t
+                    ok_mask[m, seeded] = True
+                    if not ok_mask.all():
+                        continue
+                elif (gap < MIN_GAP).any():
+                    continue
+            grid.insert(p, rad)
+            sph_owner.extend([a] * len(rad))
+            placed_pos[a] = p
+            break
+        else:
+            raise RuntimeError(f"random sequential addition failed after {n_done} of "
+                               f"{len(counts)} aggregates; lower the packing")
+    pos = np.concatenate([placed_pos[a] for a in range(len(counts))])
+    radius = np.concatenate([clusters[a][1] for a in range(len(counts))])
+    return pos, radius
+
+
+# --------------------------------------------------------------------------
+# public workloads
+# --------------------------------------------------------------------------
+
+def _box_side(counts_total_volume: float, phi: float) -> float:
+    return (counts_total_volume / phi) ** (1.0 / 3.0)
+
+
+def periodic_box(seed: int = 0, n_agg: int = 500, cmin: int = 1, cmax: int = 8,
+                 phi: float = 0.2, vel_sigma: float = 0.05, spin_sigma: float = 0.0,
+                 dt: float = 1e-4, n_steps: int = 200,
+                 contact_seeded: bool = False) -> Workload:
+    """Contact-only workload in a periodic cube (no gravity)."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(cmin, cmax + 1, n_agg).astype(np.int32)
+    clusters = [random_cluster(rng, int(c)) for c in counts]
+    vol = sum(float(sphere_mass(c[1]).sum()) for c in clusters)
+    L = _box_side(vol, phi)
+    pos, radius = _place(rng, counts, clusters, ("box", L), contact_seeded)
+    mass = sphere_mass(radius)
+    agg_vel = rng.normal(0.0, vel_sigma, (n_agg, 3))
+    agg_spin = rng.normal(0.0, spin_sigma, (n_agg, 3)) if spin_sigma > 0 else np.zeros((n_agg, 3))
+    params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=1,
+                  box=(L, L, L))
+    return Workload("periodic_box", counts, pos, radius, mass, agg_vel, agg_spin,
+                    params, n_steps,
+                    notes=f"periodic cube L={L:.4f}, phi={phi}, seed={seed}"
+                    + (", contact-seeded" if contact_seeded else ""))
+
+
+def collapse_radius(sphere_volume: float, phi0: float) -> float:
+    """Radius of the ball whose volume is sphere_volume / phi0."""
+    return (3.0 * sphere_volume / (4.0 * math.pi * phi0)) ** (1.0 / 3.0)
+
+
+def collapse_cloud(seed: int = 1, n_agg: int = 25000, cmin: int = 2, cmax: int = 8,
+                   phi0: float = 0.15, dt: float = 5e-4, n_steps: int = 2000,
+                   G: float = 1.0, soft_frac: float = 0.5,
+                   vel_sigma: float = 0.0, spin_sigma: float = 0.0,
+                   contact_seeded: bool = False) -> Workload:
+    """Self-gravitating cloud of aggregates at rest in a ball.
+
+    The ball radius is sized for an initial packing fraction phi0 (0.15),
+    because random non-overlapping placement cannot reach the packing implied
+    by 125k spheres inside radius 60.
+    """
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(cmin, cmax + 1, n_agg).astype(np.int32)
+    clusters = [random_cluster(rng, int(c)) for c in counts]
+    vol = sum(float(sphere_mass(c[1]).sum()) for c in clusters)
+    R = collapse_radius(vol, phi0)
+    pos, radius = _place(rng, counts, clusters, ("ball", R), contact_seeded)
+    mass = sphere_mass(radius)
+    agg_vel = rng.normal(0.0, vel_sigma, (n_agg, 3)) if vel_sigma > 0 else np.zeros((n_agg, 3))
+    agg_spin = rng.normal(0.0, spin_sigma, (n_agg, 3)) if spin_sigma > 0 else np.zeros((n_agg, 3))
+    params = dict(CONTACT_PARAMS, dt=dt, G=G, soft_frac=soft_frac, periodic=0,
+                  box=(0.0, 0.0, 0.0))
+    return Workload("collapse_cloud", counts, pos, radius, mass, agg_vel, agg_spin,
+                    params, n_steps,
+                    notes=f"ball R={R:.3f}, phi0={phi0}, seed={seed}"
+                    + (", contact-seeded" if contact_seeded else ""))
+
+
+def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 20000,
+               cmin: int = 1, cmax: int = 8, phi0: float = 0.3, dt: float = 5e-4,
+               n_steps: int = 800, spin_rate_per_step2: float = 1e-6,
+               G: float = 1.0, soft_frac: float = 0.5) -> List[Workload]:
+    """Independent piles with log-uniform sphere counts in [nmin, nmax].
+
+    Each pile is a cloud of aggregates packed at phi0 about the origin; the
+    spin-up forcing (constant spin increment per step) is recorded in the
+    params of every pile.
+    """
+    rng = np.random.default_rng(seed)
+    targets = np.floor(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_piles))).astype(int)
+    piles = []
+    for k, nt in enumerate(targets):
+        prng_seed = int(rng.integers(2 ** 31))
+        mean_c = 0.5 * (cmin + cmax)
+        n_agg = max(1, int(round(nt / mean_c)))
+        w = collapse_cloud(seed=prng_seed, n_agg=n_agg, cmin=cmin, cmax=cmax,
+                           phi0=phi0, dt=dt, n_steps=n_steps, G=G, soft_frac=soft_frac)
+        w.name = f"pile{k}"
+        w.params["spin_dw"] = spin_rate_per_step2 / dt   # rad per time unit, per step
+        piles.append(w)
+    return piles
+
+
+def subset(w: Workload, n_agg: int) -> Workload:
+    """First ``n_agg`` aggregates of a workload (for reduced-size checks)."""
+    off = w.offsets()
+    ns = int(off[n_agg])
+    return Workload(w.name + f"[:{n_agg}]", w.counts[:n_agg].copy(), w.pos[:ns].copy(),
+                    w.radius[:ns].copy(), w.mass[:ns].copy(), w.agg_vel[:n_agg].copy(),
+                    w.agg_spin[:n_agg].copy(), dict(w.params), w.n_steps, notes=w.notes)
+
+
+# --------------------------------------------------------------------------
+# symmetric shape fixtures (Fig. 1 of the paper), equal spheres of radius s
+# --------------------------------------------------------------------------
+
+def shape_fixture(name: str, s: float = 1.0) -> np.ndarray:
+    """Sphere centres (relative to the centroid) of the paper's symmetric
+    aggregate shapes built from touching equal spheres of radius ``s``."""
+    if name == "sphere":
+        p = np.zeros((1, 3))
+    elif name == "dumbbell":
+        p = np.array([[-s, 0, 0], [s, 0, 0]], dtype=float)
+    elif name == "rod":
+        p = np.array([[-3 * s, 0, 0], [-s, 0, 0], [s, 0, 0], [3 * s, 0, 0]], dtype=float)
+    elif name == "cube":
+        p = np.array([[x, y, z] for x in (-s, s) for y in (-s, s) for z in (-s, s)], dtype=float)
+    elif name == "tetrahedron":
+        a = 2 * s / math.sqrt(8.0)
+        p = np.array([[a, a, a], [a, -a, -a], [-a, a, -a], [-a, -a, a]], dtype=float)
+    elif name == "diamond":
+        h = math.sqrt(3.0) * s
+        p = np.array([[-s, 0, 0], [s, 0, 0], [0, h, 0], [0, -h, 0]], dtype=float)
+    else:
+        raise KeyError(name)
+    return p - p.mean(axis=0)
+
+
+SHAPES = ("sphere", "dumbbell", "diamond", "tetrahedron", "rod", "cube")
+
+
+def fixture_system(shapes, centres, s=1.0, vel=None, spin=None, rot=None,
+                   params=None, dt=1e-4, n_steps=1, density=1.0) -> Workload:
+    """Build a workload from shape fixtures placed at ``centres``."""
+    pos, counts = [], []
+    for k, (nm, c) in enumerate(zip(shapes, centres)):
+        p = shape_fixture(nm, s)
+        if rot is not None and rot[k] is not None:
+            p = p @ np.asarray(rot[k]).T
+        pos.append(p + np.asarray(c, dtype=float))
+        counts.append(p.shape[0])
+    pos = np.concatenate(pos)
+    radius = np.full(pos.shape[0], float(s))
+    mass = sphere_mass(radius, density)
+    n = len(counts)
+    vel = np.zeros((n, 3)) if vel is None else np.asarray(vel, dtype=float).reshape(n, 3)
+    spin = np.zeros((n, 3)) if spin is None else np.asarray(spin, dtype=float).reshape(n, 3)
+    prm = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=0, box=(0.0, 0.0, 0.0))
+    if params:
+        prm.update(params)
+    return Workload("fixture", np.asarray(counts, dtype=np.int32), pos, radius, mass,
+                    vel, spin, prm, n_steps)
