@@ -1,0 +1,211 @@
+/*
+ * dem.h -- C-ABI of the MI355X soft-sphere DEM step for rigid aggregates of
+ * bonded spheres (Marohnic et al., arXiv 2311.11322).
+ *
+ * The library (libdem.so, HIP for gfx950) integrates systems ("piles") of
+ * rigid aggregates.  Each step: leapfrog kick and drift of aggregate centres
+ * of mass, a fifth-order Runge-Kutta step of Euler's rigid-body equations
+ * (Sec. 2.1-2.2 of the paper), reconstruction of member positions and
+ * predicted velocities (Eq. 3 and the SetSpace* functions of the appendix
+ * table), contact search that skips pairs inside one aggregate, spring-
+ * dashpot contacts with tangential/rolling/twisting spring history applied
+ * at the contact point (Sec. 2.1, Eqs. 8-9), softened direct-sum self-gravity
+ * (Eq. 4) and the reduction onto aggregates (Eqs. 5-7, 9; GetAccelAndTorque).
+ *
+ * Conventions for every call:
+ *  - Every function returns dem_status; nothing aborts or throws across the
+ *    ABI.  On error, dem_last_error(sim) describes it.
+ *  - Pointers documented as host arrays are read (or written) before the
+ *    call returns; the caller keeps ownership.
+ *  - Arrays of 3-vectors are row-major [n][3] (x, y, z), quaternions [n][4]
+ *    (w, x, y, z) mapping body frame to space frame.
+ *  - Sphere ids are input positions (0-based, grouped by aggregate);
+ *    aggregate ids are consecutive in call order.  Both are persistent and
+ *    define the canonical contact order: pairs (i, j), i < j, sorted
+ *    lexicographically, keyed as (uint64)i << 32 | j.
+ *  - Device memory is owned by the library and obtained through the
+ *    caller's allocator (NULL: hipMalloc/hipFree).  All device work is
+ *    issued on the stream given at creation (NULL: the null stream).
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DEM_OK = 0,
+    DEM_ERR_INVALID_ARG = -1,  /* bad pointer, size, non-finite value, radius or mass <= 0 */
+    DEM_ERR_OOM = -2,          /* allocation failed, or an engine's memory budget is exceeded */
+    DEM_ERR_CAPACITY = -3,     /* contact capacity exceeded; state rolled back to the failing step's start */
+    DEM_ERR_UNSTABLE = -4,     /* non-finite force or overlap > max_overlap_frac*radius; rolled back */
+    DEM_ERR_DEVICE = -5,       /* a HIP call failed */
+    DEM_ERR_STATE = -6         /* call out of order (e.g. adding aggregates after stepping) */
+} dem_status;
+
+typedef enum {
+    DEM_PREC_FP64 = 0,         /* every force in FP64 */
+    DEM_PREC_FP32_FORCE = 1    /* pair forces and gravity in FP32 on relative coordinates;
+                                  positions, velocities, quaternions, accumulation in FP64 */
+} dem_precision;
+
+/* Model parameters.  Spring and damping constants are user parameters of
+ * the soft-sphere model (Sec. 2.1); the time step is fixed (Sec. 2.1). */
+typedef struct {
+    double dt;                 /* leapfrog step h > 0 */
+    double G;                  /* gravitational constant; 0 disables self-gravity */
+    double softening_frac;     /* Plummer eps_ij = softening_frac*(s_i+s_j)/2 (>= 0) */
+    double k_n, k_t;           /* normal and tangential spring constants (> 0) */
+    double eps_n, eps_t;       /* restitution coefficients in (0, 1]; set the dashpots */
+    double mu_s, mu_r, mu_t;   /* sliding, rolling, twisting friction coefficients (>= 0) */
+    double k_r, k_q;           /* rolling and twisting spring constants; < 0 means k_t */
+    int32_t periodic;          /* 1: periodic cube box[0..2] (same side on all axes) */
+    double box[3];
+    int32_t precision;         /* dem_precision */
+    int32_t max_contacts_per_sphere; /* contact capacity: the system holds up to this many
+                                        contacts per sphere on average; <= 0: 8 */
+    double max_overlap_frac;   /* > 0: overlap above this fraction of the smaller radius is
+                                  an instability (DEM_ERR_UNSTABLE); <= 0: no check */
+} dem_params;
+
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);  /* returns device memory or NULL */
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} dem_allocator;
+
+/* Optional forcing of one system (spin-up experiment of Sec. 4.1: a constant
+ * spin increment per step about +z through the system's centre of mass). */
+typedef struct {
+    double spin_dw;            /* spin increment per step (rad per time unit); 0: off */
+} dem_forcing;
+
+/* State read-out / restore.  Caller-owned host buffers sized by
+ * dem_get_counts; a NULL field is skipped.  Sphere fields describe the last
+ * force evaluation. */
+typedef struct {
+    double* agg_pos;           /* [n_agg][3] centre of mass r_A */
+    double* agg_vel;           /* [n_agg][3] centre-of-mass velocity v_A */
+    double* agg_acc;           /* [n_agg][3] last evaluated a_A */
+    double* agg_torque;        /* [n_agg][3] last evaluated torque N_A (space frame) */
+    double* agg_quat;          /* [n_agg][4] orientation (body -> space) */
+    double* agg_spin;          /* [n_agg][3] spin, space frame (read only) */
+    double* agg_spin_body;     /* [n_agg][3] spin, body frame */
+    double* agg_mass;          /* [n_agg] total mass M (Eq. 1) (read only) */
+    double* agg_inertia;       /* [n_agg][3] principal moments (read only) */
+    double* sph_pos;           /* [n_sph][3] space-frame centres (read only) */
+    double* sph_vel;           /* [n_sph][3] predicted velocities, Eq. 3 (read only) */
+    double* sph_force;         /* [n_sph][3] contact + gravity force (read only) */
+    double* sph_torque;        /* [n_sph][3] contact torque about the centre (read only) */
+    double* sph_body;          /* [n_sph][3] body-frame offsets (read only) */
+    uint64_t* pair_keys;       /* [n_pairs] canonical contact keys */
+    double* pair_hist;         /* [n_pairs][7] spring history xi_t[3], xi_r[3], xi_q */
+    int64_t n_pairs;           /* out: contacts written; in (restore): contacts given */
+    int64_t step;              /* out: steps taken; in (restore): step counter */
+} dem_state;
+
+typedef struct dem_sim dem_sim;
+typedef struct dem_engine dem_engine;
+
+/* Create an empty system.  Validates parameters (dt > 0, springs > 0,
+ * restitution in (0, 1], frictions >= 0, positive box if periodic). */
+dem_status dem_create(const dem_params* params, const dem_allocator* alloc,
+                      void* hip_stream, dem_sim** out);
+
+/* Add rigid aggregates (Sec. 2.2: spheres fixed into rigid bodies, each with
+ * a unique index).  May be called only once per system, before dem_step.
+ * Spheres are grouped by aggregate: aggregate a owns the next
+ * spheres_per_agg[a] entries.  sphere_pos is space-frame [n_sph][3];
+ * agg_vel ([n_agg][3], centre-of-mass velocity) and agg_spin ([n_agg][3],
+ * space frame) may be NULL (zero).  Performs the aggregate set-up on the
+ * device (Eqs. 1-2, inertia and principal axes, body offsets, aggregate mass
+ * per member) and the initial force evaluation at t0.  first_agg_id (may be
+ * NULL) receives the id of the first aggregate (always 0).
+ * Errors: INVALID_ARG for an empty aggregate, non-finite value, radius or
+ * mass <= 0; STATE if called
+ * twice or after stepping; CAPACITY if the initial contacts do not fit. */
+dem_status dem_add_aggregates(dem_sim* sim, int64_t n_agg, const int32_t* spheres_per_agg,
+                              const double* sphere_pos, const double* sphere_radius,
+                              const double* sphere_mass, const double* agg_vel,
+                              const double* agg_spin, int64_t* first_agg_id);
+
+/* Advance n_steps fixed steps (replays of one captured HIP graph).  Returns
+ * after the work is complete.  On CAPACITY / UNSTABLE the state is that at
+ * the start of the failing step and dem_state.step tells which step it is.
+ * STATE if the system is attached to an engine or has no aggregates. */
+dem_status dem_step(dem_sim* sim, int64_t n_steps);
+
+/* Copy the state to host buffers (synchronises the stream). */
+dem_status dem_read_state(dem_sim* sim, dem_state* out);
+
+/* Counts: aggregates, spheres, contacts of the last evaluation. */
+dem_status dem_get_counts(const dem_sim* sim, int64_t* n_agg, int64_t* n_sph, int64_t* n_pairs);
+
+dem_status dem_set_forcing(dem_sim* sim, const dem_forcing* forcing);
+
+/* Restore aggregate state, contact list and spring history from a checkpoint
+ * written by dem_read_state (fields agg_pos, agg_vel, agg_acc, agg_torque,
+ * agg_quat, agg_spin_body, pair_keys, pair_hist, n_pairs, step).  Resuming
+ * reproduces the uninterrupted run bit for bit. */
+dem_status dem_restore_state(dem_sim* sim, const dem_state* in);
+
+/* Grow the contact capacity (per sphere, each side) after DEM_ERR_CAPACITY. */
+dem_status dem_reserve_contacts(dem_sim* sim, int32_t max_contacts_per_sphere);
+
+/* Stateless contact search on the device (test hook): all i<j with
+ * agg[i] != agg[j] and d^2 < (s_i+s_j)^2, d^2 = (dx*dx + dy*dy) + dz*dz with
+ * the minimum-image rule when box != NULL (cube of side box[0]).  Host arrays
+ * in; canonical keys out (up to cap); *n_out gets the total count.
+ * CAPACITY if more than 64 contacts per sphere are found. */
+dem_status dem_find_contacts(const double* pos, const double* radius, const int32_t* agg,
+                             int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,
+                             int64_t* n_out);
+
+dem_status dem_destroy(dem_sim* sim);
+
+/* Description of the last error on this system (or the last global error if
+ * sim is NULL).  Never NULL. */
+const char* dem_last_error(const dem_sim* sim);
+
+/* ---- batching and serving -------------------------------------------------
+ * An engine steps many independent systems together: every kernel of a step
+ * covers all attached systems in one launch, one HIP graph per step.  State
+ * and contact history stay in each system's own device buffers. */
+
+/* hbm_budget_bytes: total device footprint the attached systems may use. */
+dem_status dem_engine_create(size_t hbm_budget_bytes, void* hip_stream, dem_engine** out);
+/* Attach a system that has aggregates.  OOM if its footprint exceeds the free
+ * budget; INVALID_ARG if its contact parameters or time step differ from
+ * those already attached. */
+dem_status dem_engine_attach(dem_engine* eng, dem_sim* sim);
+/* Advance every attached system by n_steps.  A system that fails stops
+ * (rolled back to its failing step) while the others continue; the return
+ * value is the first failure code, and dem_sim_status tells which. */
+dem_status dem_engine_step(dem_engine* eng, int64_t n_steps);
+dem_status dem_engine_detach(dem_engine* eng, dem_sim* sim);
+dem_status dem_engine_destroy(dem_engine* eng);
+/* Status of one system after an engine step (DEM_OK or the failure code). */
+dem_status dem_sim_status(const dem_sim* sim);
+
+/* Per-kernel timing (measurement aid for benchmarks).  While enabled,
+ * dem_step launches the step's kernels one by one (no graph) with a HIP event
+ * before and after each, on the system's stream, and accumulates the elapsed
+ * time of every kernel family.  dem_get_profile copies up to n_max totals in
+ * milliseconds (order given by dem_profile_names, a ';'-separated list) and
+ * the number of steps they cover.  Enabling or disabling clears the totals. */
+dem_status dem_set_profiling(dem_sim* sim, int32_t enabled);
+dem_status dem_get_profile(const dem_sim* sim, double* kernel_ms, int32_t n_max,
+                           int64_t* n_steps);
+const char* dem_profile_names(void);
+
+/* Device bytes a system of this size uses (for admission control). */
+size_t dem_footprint_bytes(const dem_params* params, int64_t n_agg, int64_t n_sph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1210 @@
+// dem_host.hip -- host runtime behind the C-ABI of include/dem.h.
+//
+// Owns each system's device buffers (through the caller's allocator), the
+// device table of piles, the static work lists, and one captured HIP graph
+// per batch that replays a whole step.  No host synchronisation happens
+// inside a step; dem_step reads back one small status record per call.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dem.h"
+#include "dem_internal.h"
+
+using namespace dem;
+
+namespace {
+
+thread_local std::string g_error = "no error";
+
+constexpr int kDefaultContacts = 8;
+constexpr int kFindContactsCap = 64;
+
+std::string hip_msg(hipError_t e, const char* what) {
+  return std::string(what) + ": " + hipGetErrorString(e);
+}
+
+struct Allocator {
+  dem_allocator user{};
+  bool has_user = false;
+  void* alloc(size_t n) const {
+    if (n == 0) n = 256;
+    n = (n + 255) & ~size_t(255);
+    if (has_user) return user.alloc(n, user.ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+    return p;
+  }
+  void release(void* p) const {
+    if (!p) return;
+    if (has_user) user.free(p, user.ctx);
+    else (void)hipFree(p);
+  }
+};
+
+size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((uint64_t(1) << b) < v) ++b;
+  return b;
+}
+
+// Device footprint of one system, byte for byte what alloc_pile allocates.
+struct Sizes {
+  int64_t na, ns, cap, cells, n_split, n_rblk;
+  bool grav;
+};
+
+int choose_bits(int64_t ns) {
+  // at least two cells per sphere, 2..10 bits per axis
+  int b = (ceil_log2(uint64_t(2 * ns)) + 2) / 3;
+  return std::min(10, std::max(2, b));
+}
+
+int choose_split(int64_t ns, int precision) {
+  const int ipt = gravity_ipt(precision);
+  const int64_t iblk = (ns + int64_t(kBlock) * ipt - 1) / (int64_t(kBlock) * ipt);
+  int64_t s = (4096 + iblk - 1) / iblk;           // aim at >= 4096 blocks
+  s = std::min<int64_t>(s, std::max<int64_t>(1, ns / 256));   // >= 256 sources each
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max) {
+  Sizes z;
+  z.na = na;
+  z.ns = ns;
+  z.cap = int64_t(c_max) * ns;
+  z.cells = int64_t(1) << (3 * choose_bits(ns));
+  z.grav = p.G != 0.0;
+  z.n_split = z.grav ? choose_split(ns, p.precision) : 1;
+  z.n_rblk = (ns + kBlock - 1) / kBlock;
+  return z;
+}
+
+struct BufList {
+  std::vector<std::pair<void**, size_t>> req;
+  template <typename T>
+  void add(T** p, int64_t count) {
+    req.push_back({reinterpret_cast<void**>(p), round256(size_t(std::max<int64_t>(count, 1)) * sizeof(T))});
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& r : req) t += r.second;
+    return t;
+  }
+};
+
+void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
+  const int64_t na = z.na, ns = z.ns, cap = z.cap;
+  L.add(&h.first, na);
+  L.add(&h.count, na);
+  L.add(&h.M, na);
+  L.add(&h.I, 3 * na);
+  for (int k = 0; k < 2; ++k) {
+    L.add(&h.rA[k], 3 * na);
+    L.add(&h.vA[k], 3 * na);
+    L.add(&h.aA[k], 3 * na);
+    L.add(&h.NA[k], 3 * na);
+    L.add(&h.q[k], 4 * na);
+    L.add(&h.wb[k], 3 * na);
+  }
+  L.add(&h.wA, 3 * na);
+  L.add(&h.vpred, 3 * na);
+  L.add(&h.b, 3 * ns);
+  L.add(&h.s, ns);
+  L.add(&h.m, ns);
+  L.add(&h.agg, ns);
+  L.add(&h.r, 3 * ns);
+  L.add(&h.v, 3 * ns);
+  L.add(&h.F, 3 * ns);
+  L.add(&h.tau, 3 * ns);
+  L.add(&h.key, ns);
+  L.add(&h.sidx, ns);
+  L.add(&h.slot, ns);
+  L.add(&h.xs, 4 * ns);
+  L.add(&h.sagg, ns);
+  if (z.grav) {
+    L.add(reinterpret_cast<double**>(&h.jrec), 8 * ns);
+    L.add(&h.gpart, 3 * ns * z.n_split);
+  }
+  L.add(&h.bpart, 10 * z.n_rblk);
+  L.add(&h.grid, 1);
+  L.add(&h.cell_cnt, z.cells);
+  L.add(&h.cell_start, z.cells + 1);
+  L.add(&h.cnt_up, ns);
+  L.add(&h.cnt_lo, ns);
+  L.add(&h.up_off[0], ns + 1);
+  L.add(&h.up_off[1], ns + 1);
+  L.add(&h.lo_off, ns + 1);
+  L.add(&h.pair_j[0], cap);
+  L.add(&h.pair_j[1], cap);
+  L.add(&h.hist[0], kHist * cap);
+  L.add(&h.hist[1], kHist * cap);
+  L.add(&h.lo_nbr, cap);
+  L.add(&h.lo_pair, cap);
+  L.add(&h.pF, 3 * cap);
+  L.add(&h.pTi, 3 * cap);
+  L.add(&h.pTj, 3 * cap);
+}
+
+double dashpot_factor(double eps) {
+  const double le = std::log(eps);
+  return -2.0 * le / std::sqrt(M_PI * M_PI + le * le);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batches: the device table of piles, work lists and the step graph
+// ---------------------------------------------------------------------------
+
+struct Batch {
+  std::vector<dem_sim*> members;
+  PileDev* d_table = nullptr;
+  int table_cap = 0;
+  std::vector<void*> meta;          // hipMalloc'ed work lists (freed on rebuild)
+  WorkItem* wl_agg = nullptr;
+  int n_agg_blk = 0;
+  WorkItem* wl_sph = nullptr;
+  int n_sph_blk = 0;
+  GravItem* gl = nullptr;
+  int n_grav = 0;
+  bool any_grav = false;
+  bool all_soft = true;
+  ScanSeg* seg_cells = nullptr;
+  ScanItem* item_cells = nullptr;
+  uint32_t* sums_cells = nullptr;
+  int n_seg_cells = 0, n_item_cells = 0;
+  ScanSeg* seg_pairs = nullptr;
+  ScanItem* item_pairs = nullptr;
+  uint32_t* sums_pairs = nullptr;
+  int n_seg_pairs = 0, n_item_pairs = 0;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  bool dirty = true;
+  ContactParams cp{};
+  int precision = 0;
+};
+
+struct dem_sim {
+  dem_params prm{};
+  Allocator alloc;
+  hipStream_t stream = nullptr;
+  std::string err = "no error";
+  // device storage
+  PileDev h{};                       // host mirror of this system's table entry
+  std::vector<void*> bufs;
+  size_t bytes = 0;
+  Sizes sz{};
+  int c_max = kDefaultContacts;
+  bool has_aggs = false;
+  bool stepped = false;
+  double spin_dw = 0.0;
+  // where the authoritative copy of the table entry lives
+  Batch own;                         // standalone batch of one
+  dem_engine* engine = nullptr;
+  int engine_slot = -1;
+  dem_status last_status = DEM_OK;
+  // per-kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  std::vector<double> prof_ms;
+  int64_t prof_steps = 0;
+};
+
+struct dem_engine {
+  size_t budget = 0, used = 0;
+  hipStream_t stream = nullptr;
+  Batch batch;
+  std::string err = "no error";
+};
+
+namespace {
+
+dem_status fail(dem_sim* s, dem_status code, const std::string& msg) {
+  g_error = msg;
+  if (s) s->err = msg;
+  return code;
+}
+
+#define HIPCHK(sim, call)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) return fail((sim), DEM_ERR_DEVICE, hip_msg(e_, #call)); \
+  } while (0)
+
+void free_meta(Batch& b) {
+  for (void* p : b.meta) (void)hipFree(p);
+  b.meta.clear();
+  if (b.graph) (void)hipGraphExecDestroy(b.graph);
+  if (b.graph_def) (void)hipGraphDestroy(b.graph_def);
+  b.graph = nullptr;
+  b.graph_def = nullptr;
+}
+
+template <typename T>
+hipError_t upload(Batch& b, T** dst, const std::vector<T>& src, hipStream_t st) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  b.meta.push_back(p);
+  *dst = static_cast<T*>(p);
+  return hipMemcpyAsync(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// Rebuild work lists and scan segments of a batch from its members; the
+// device table entries must already be in place at slots 0..n-1.
+dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
+  free_meta(b);
+  std::vector<WorkItem> wa, wsph;
+  std::vector<GravItem> gl;
+  std::vector<ScanSeg> sc, sp;
+  std::vector<ScanItem> ic, ip;
+  b.any_grav = false;
+  b.all_soft = true;
+  for (int p = 0; p < (int)b.members.size(); ++p) {
+    const dem_sim* s = b.members[p];
+    const PileDev& h = s->h;
+    for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
+    for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
+    if (h.G != 0.0) {
+      b.any_grav = true;
+      if (!(h.soft_frac > 0.0)) b.all_soft = false;
+      const int ipt = gravity_ipt(s->prm.precision);
+      const int tile = kBlock * ipt;
+      const int ns = h.ns;
+      for (int sp_i = 0; sp_i < h.n_split; ++sp_i) {
+        const int j0 = int(int64_t(ns) * sp_i / h.n_split);
+        const int j1 = int(int64_t(ns) * (sp_i + 1) / h.n_split);
+        for (int i = 0; i < ns; i += tile) gl.push_back({p, i, j0, j1, sp_i, 0});
+      }
+    }
+    // cell-count scan of this pile
+    auto add_seg = [](std::vector<ScanSeg>& segs, std::vector<ScanItem>& items, const uint32_t* in,
+                      uint32_t* out0, uint32_t* out1, const int32_t* par, int64_t n) {
+      ScanSeg g{};
+      g.in = in;
+      g.out_pp[0] = out0;
+      g.out_pp[1] = out1;
+      g.parity = par;
+      g.n = (int32_t)n;
+      g.item0 = (int32_t)items.size();
+      g.n_items = (int32_t)((n + kScanChunk - 1) / kScanChunk);
+      for (int c = 0; c < g.n_items; ++c) items.push_back({(int32_t)segs.size(), c});
+      segs.push_back(g);
+    };
+    PileDev* dentry = b.d_table + p;
+    add_seg(sc, ic, h.cell_cnt, h.cell_start, h.cell_start, nullptr, s->sz.cells);
+    add_seg(sp, ip, h.cnt_up, h.up_off[0], h.up_off[1], &dentry->parity, h.ns);
+    add_seg(sp, ip, h.cnt_lo, h.lo_off, h.lo_off, nullptr, h.ns);
+  }
+  HIPCHK(errsim, upload(b, &b.wl_agg, wa, st));
+  HIPCHK(errsim, upload(b, &b.wl_sph, wsph, st));
+  HIPCHK(errsim, upload(b, &b.gl, gl, st));
+  HIPCHK(errsim, upload(b, &b.seg_cells, sc, st));
+  HIPCHK(errsim, upload(b, &b.item_cells, ic, st));
+  HIPCHK(errsim, upload(b, &b.seg_pairs, sp, st));
+  HIPCHK(errsim, upload(b, &b.item_pairs, ip, st));
+  std::vector<uint32_t> zc(std::max<size_t>(ic.size(), 1), 0u), zp(std::max<size_t>(ip.size(), 1), 0u);
+  HIPCHK(errsim, upload(b, &b.sums_cells, zc, st));
+  HIPCHK(errsim, upload(b, &b.sums_pairs, zp, st));
+  b.n_agg_blk = (int)wa.size();
+  b.n_sph_blk = (int)wsph.size();
+  b.n_grav = (int)gl.size();
+  b.n_seg_cells = (int)sc.size();
+  b.n_item_cells = (int)ic.size();
+  b.n_seg_pairs = (int)sp.size();
+  b.n_item_pairs = (int)ip.size();
+  b.dirty = false;
+  return DEM_OK;
+}
+
+// Kernel families of one step, in launch order (profiling names).
+constexpr int kNumStages = 15;
+const char* const kStageNames =
+    "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;sorted_copy;search_count;"
+    "scan_pairs;search_write;pairs;gravity;reduce;finish";
+
+// Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
+// mark(k) is called before stage k and mark(kNumStages) after the last.
+template <typename Mark>
+void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
+  const int np = (int)b.members.size();
+  mark(0);
+  launch_integrate(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
+  mark(1);
+  launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  mark(2);
+  launch_grid(st, b.d_table, np);
+  mark(3);
+  launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  mark(4);
+  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells);
+  mark(5);
+  launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  mark(6);
+  launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  mark(7);
+  launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  mark(8);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
+  mark(9);
+  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs);
+  mark(10);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
+  mark(11);
+  launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
+  mark(12);
+  if (b.any_grav) launch_gravity(st, b.d_table, b.gl, b.n_grav, b.precision, b.all_soft);
+  mark(13);
+  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
+  mark(14);
+  launch_finish(st, b.d_table, np, mode);
+  mark(15);
+}
+
+void enqueue_pass(Batch& b, hipStream_t st, int mode) {
+  enqueue_pass_marked(b, st, mode, [](int) {});
+}
+
+dem_status ensure_graph(Batch& b, hipStream_t st, dem_sim* errsim) {
+  if (b.graph) return DEM_OK;
+  hipStream_t cap = st;
+  bool own_stream = false;
+  if (cap == nullptr) {
+    // capture needs a non-null stream
+    HIPCHK(errsim, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    own_stream = true;
+  }
+  HIPCHK(errsim, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  enqueue_pass(b, cap, kModeStep);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  if (own_stream) (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) return fail(errsim, DEM_ERR_DEVICE, hip_msg(e, "graph capture"));
+  b.graph_def = g;
+  HIPCHK(errsim, hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0));
+  return DEM_OK;
+}
+
+dem_status valid_params(const dem_params* p, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return DEM_ERR_INVALID_ARG;
+  };
+  if (!p) return bad("params is NULL");
+  const double vals[] = {p->dt, p->G, p->softening_frac, p->k_n, p->k_t, p->eps_n, p->eps_t,
+                         p->mu_s, p->mu_r, p->mu_t, p->k_r, p->k_q};
+  for (double v : vals)
+    if (!std::isfinite(v)) return bad("non-finite parameter");
+  if (!(p->dt > 0)) return bad("dt must be > 0");
+  if (p->G < 0 || p->softening_frac < 0) return bad("G and softening_frac must be >= 0");
+  if (!(p->k_n > 0) || !(p->k_t > 0)) return bad("spring constants must be > 0");
+  if (!(p->eps_n > 0 && p->eps_n <= 1) || !(p->eps_t > 0 && p->eps_t <= 1))
+    return bad("restitution coefficients must be in (0, 1]");
+  if (p->mu_s < 0 || p->mu_r < 0 || p->mu_t < 0) return bad("friction coefficients must be >= 0");
+  if (p->periodic) {
+    if (!(p->box[0] > 0) || p->box[1] != p->box[0] || p->box[2] != p->box[0])
+      return bad("periodic box must be a cube with positive side");
+  }
+  if (p->precision != DEM_PREC_FP64 && p->precision != DEM_PREC_FP32_FORCE)
+    return bad("unknown precision");
+  return DEM_OK;
+}
+
+ContactParams contact_params(const dem_params& p) {
+  ContactParams cp{};
+  cp.dt = p.dt;
+  cp.k_n = p.k_n;
+  cp.k_t = p.k_t;
+  cp.k_r = p.k_r < 0 ? p.k_t : p.k_r;
+  cp.k_q = p.k_q < 0 ? p.k_t : p.k_q;
+  cp.mu_s = p.mu_s;
+  cp.mu_r = p.mu_r;
+  cp.mu_t = p.mu_t;
+  cp.damp_n = dashpot_factor(p.eps_n);
+  cp.damp_t = dashpot_factor(p.eps_t);
+  cp.max_overlap_frac = p.max_overlap_frac;
+  return cp;
+}
+
+void release_pile(dem_sim* s) {
+  for (void* p : s->bufs) s->alloc.release(p);
+  s->bufs.clear();
+  s->bytes = 0;
+}
+
+dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
+  PileDev h{};
+  s->sz = pile_sizes(s->prm, na, ns, s->c_max);
+  BufList L;
+  plan_pile(h, s->sz, L);
+  for (auto& r : L.req) {
+    void* p = s->alloc.alloc(r.second);
+    if (!p) {
+      release_pile(s);
+      return fail(s, DEM_ERR_OOM, "device allocation failed");
+    }
+    s->bufs.push_back(p);
+    s->bytes += r.second;
+    *r.first = p;
+  }
+  h.na = (int32_t)na;
+  h.ns = (int32_t)ns;
+  h.cap_pairs = (int32_t)s->sz.cap;
+  h.bits = choose_bits(ns);
+  h.periodic = s->prm.periodic ? 1 : 0;
+  h.n_split = (int32_t)s->sz.n_split;
+  h.n_rblk = (int32_t)s->sz.n_rblk;
+  h.box = s->prm.box[0];
+  h.G = s->prm.G;
+  h.soft_frac = s->prm.softening_frac;
+  h.spin_dw = s->spin_dw;
+  h.parity = 0;
+  h.status = 0;
+  h.step = 0;
+  h.fail_step = -1;
+  s->h = h;
+  return DEM_OK;
+}
+
+// Upload the host mirror into a batch table slot.
+hipError_t put_entry(const dem_sim* s, PileDev* dst, hipStream_t st) {
+  return hipMemcpyAsync(dst, &s->h, sizeof(PileDev), hipMemcpyHostToDevice, st);
+}
+
+// Read back a table entry into the host mirror (after the stream is idle).
+hipError_t get_entry(dem_sim* s, const PileDev* src, hipStream_t st) {
+  PileDev tmp;
+  hipError_t e = hipMemcpyAsync(&tmp, src, sizeof(PileDev), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  s->h.parity = tmp.parity;
+  s->h.status = tmp.status;
+  s->h.step = tmp.step;
+  s->h.fail_step = tmp.fail_step;
+  s->h.n_pairs = tmp.n_pairs;
+  return hipSuccess;
+}
+
+const PileDev* entry_of(const dem_sim* s) {
+  if (s->engine) return s->engine->batch.d_table + s->engine_slot;
+  return s->own.d_table;
+}
+
+hipStream_t stream_of(const dem_sim* s) { return s->engine ? s->engine->stream : s->stream; }
+
+dem_status status_code(int st) {
+  if (st & kStCapacity) return DEM_ERR_CAPACITY;
+  if (st & kStUnstable) return DEM_ERR_UNSTABLE;
+  return DEM_OK;
+}
+
+dem_status ensure_own_table(dem_sim* s) {
+  Batch& b = s->own;
+  if (!b.d_table) {
+    HIPCHK(s, hipMalloc(&b.d_table, sizeof(PileDev)));
+    b.table_cap = 1;
+  }
+  b.members.assign(1, s);
+  b.cp = contact_params(s->prm);
+  b.precision = s->prm.precision;
+  return DEM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* dem_last_error(const dem_sim* sim) {
+  if (sim) return sim->err.c_str();
+  return g_error.c_str();
+}
+
+size_t dem_footprint_bytes(const dem_params* params, int64_t n_agg, int64_t n_sph) {
+  if (!params || n_agg <= 0 || n_sph <= 0) return 0;
+  int c = params->max_contacts_per_sphere > 0 ? params->max_contacts_per_sphere : kDefaultContacts;
+  PileDev h{};
+  BufList L;
+  plan_pile(h, pile_sizes(*params, n_agg, n_sph, c), L);
+  return L.total();
+}
+
+dem_status dem_create(const dem_params* params, const dem_allocator* alloc, void* hip_stream,
+                      dem_sim** out) {
+  if (!out) return fail(nullptr, DEM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (valid_params(params, &why) != DEM_OK) return fail(nullptr, DEM_ERR_INVALID_ARG, why);
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "allocator needs alloc and free");
+  dem_sim* s = new dem_sim();
+  s->prm = *params;
+  if (alloc) {
+    s->alloc.user = *alloc;
+    s->alloc.has_user = true;
+  }
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->c_max = params->max_contacts_per_sphere > 0 ? params->max_contacts_per_sphere : kDefaultContacts;
+  *out = s;
+  return DEM_OK;
+}
+
+dem_status dem_destroy(dem_sim* s) {
+  if (!s) return DEM_OK;
+  if (s->engine) dem_engine_detach(s->engine, s);
+  (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
+  free_meta(s->own);
+  if (s->own.d_table) (void)hipFree(s->own.d_table);
+  release_pile(s);
+  delete s;
+  return DEM_OK;
+}
+
+dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, const double* pos,
+                              const double* radius, const double* mass, const double* agg_vel,
+                              const double* agg_spin, int64_t* first_agg_id) {
+  if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
+  if (s->has_aggs || s->stepped) return fail(s, DEM_ERR_STATE, "aggregates already added");
+  if (s->engine) return fail(s, DEM_ERR_STATE, "system is attached to an engine");
+  if (n_agg <= 0 || !spa || !pos || !radius || !mass)
+    return fail(s, DEM_ERR_INVALID_ARG, "empty input or NULL array");
+  int64_t ns = 0;
+  for (int64_t a = 0; a < n_agg; ++a) {
+    if (spa[a] <= 0) return fail(s, DEM_ERR_INVALID_ARG, "aggregate with no spheres");
+    ns += spa[a];
+  }
+  if (ns > (int64_t(1) << 30)) return fail(s, DEM_ERR_INVALID_ARG, "too many spheres");
+  double smax = 0.0;
+  for (int64_t i = 0; i < ns; ++i) {
+    if (!std::isfinite(radius[i]) || !std::isfinite(mass[i]) || radius[i] <= 0 || mass[i] <= 0)
+      return fail(s, DEM_ERR_INVALID_ARG, "radius and mass must be finite and > 0");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(pos[3 * i + k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite position");
+    smax = std::max(smax, radius[i]);
+  }
+  for (int64_t k = 0; k < 3 * n_agg; ++k) {
+    if (agg_vel && !std::isfinite(agg_vel[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite velocity");
+    if (agg_spin && !std::isfinite(agg_spin[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite spin");
+  }
+  int nb_periodic = 0;
+  if (s->prm.periodic) {
+    // cells per axis: the largest power of two whose cell still spans the
+    // largest sphere diameter (one cell if the box is smaller than that)
+    const double ratio = s->prm.box[0] / (2.0 * smax);
+    nb_periodic = ratio >= 1.0 ? (int)std::floor(std::log2(ratio)) : 0;
+  }
+  dem_status st = alloc_pile(s, n_agg, ns);
+  if (st != DEM_OK) return st;
+  s->h.cell_min = 2.0 * smax;
+  // the Morton table must hold every periodic cell: larger cells if needed
+  s->h.nb_periodic = std::min(nb_periodic, s->h.bits);
+  hipStream_t str = s->stream;
+  // constants: membership, radius, mass
+  std::vector<int32_t> first(n_agg), agg(ns);
+  int64_t off = 0;
+  for (int64_t a = 0; a < n_agg; ++a) {
+    first[a] = (int32_t)off;
+    for (int64_t k = 0; k < spa[a]; ++k) agg[off + k] = (int32_t)a;
+    off += spa[a];
+  }
+  HIPCHK(s, hipMemcpyAsync(s->h.first, first.data(), n_agg * 4, hipMemcpyHostToDevice, str));
+  HIPCHK(s, hipMemcpyAsync(s->h.count, spa, n_agg * 4, hipMemcpyHostToDevice, str));
+  HIPCHK(s, hipMemcpyAsync(s->h.agg, agg.data(), ns * 4, hipMemcpyHostToDevice, str));
+  HIPCHK(s, hipMemcpyAsync(s->h.s, radius, ns * 8, hipMemcpyHostToDevice, str));
+  HIPCHK(s, hipMemcpyAsync(s->h.m, mass, ns * 8, hipMemcpyHostToDevice, str));
+  // staging for the set-up kernel
+  double *d_pos = nullptr, *d_vel = nullptr, *d_spin = nullptr;
+  HIPCHK(s, hipMalloc(&d_pos, ns * 24));
+  HIPCHK(s, hipMemcpyAsync(d_pos, pos, ns * 24, hipMemcpyHostToDevice, str));
+  if (agg_vel) {
+    HIPCHK(s, hipMalloc(&d_vel, n_agg * 24));
+    HIPCHK(s, hipMemcpyAsync(d_vel, agg_vel, n_agg * 24, hipMemcpyHostToDevice, str));
+  }
+  if (agg_spin) {
+    HIPCHK(s, hipMalloc(&d_spin, n_agg * 24));
+    HIPCHK(s, hipMemcpyAsync(d_spin, agg_spin, n_agg * 24, hipMemcpyHostToDevice, str));
+  }
+  // zero the contact lists (empty history) and cell counts
+  launch_fill_u32(str, s->h.up_off[0], 0u, ns + 1);
+  launch_fill_u32(str, s->h.up_off[1], 0u, ns + 1);
+  launch_fill_u32(str, s->h.lo_off, 0u, ns + 1);
+  launch_fill_u32(str, s->h.cell_cnt, 0u, s->sz.cells);
+  st = ensure_own_table(s);
+  if (st != DEM_OK) return st;
+  HIPCHK(s, put_entry(s, s->own.d_table, str));
+  st = rebuild(s->own, str, s);
+  if (st != DEM_OK) return st;
+  launch_setup(str, s->own.d_table, s->own.wl_agg, s->own.n_agg_blk, d_pos, d_vel, d_spin);
+  // initial evaluation at t0 (forces, torques and accelerations)
+  enqueue_pass(s->own, str, kModeInit);
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, get_entry(s, s->own.d_table, str));
+  (void)hipFree(d_pos);
+  if (d_vel) (void)hipFree(d_vel);
+  if (d_spin) (void)hipFree(d_spin);
+  s->has_aggs = true;
+  if (first_agg_id) *first_agg_id = 0;
+  if (s->h.status != 0) {
+    dem_status code = status_code(s->h.status);
+    return fail(s, code, code == DEM_ERR_CAPACITY ? "initial contacts exceed capacity"
+                                                  : "initial state unstable");
+  }
+  return DEM_OK;
+}
+
+dem_status dem_step(dem_sim* s, int64_t n_steps) {
+  if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
+  if (s->engine) return fail(s, DEM_ERR_STATE, "system is attached to an engine");
+  if (!s->has_aggs) return fail(s, DEM_ERR_STATE, "no aggregates");
+  if (n_steps < 0) return fail(s, DEM_ERR_INVALID_ARG, "negative step count");
+  if (s->h.status != 0) return fail(s, status_code(s->h.status), "system has failed; restore it");
+  s->stepped = true;
+  if (n_steps == 0) return DEM_OK;
+  if (s->profiling) {
+    // eager launches with an event between consecutive kernels
+    const size_t need = size_t(n_steps) * (kNumStages + 1);
+    while (s->events.size() < need) {
+      hipEvent_t ev;
+      HIPCHK(s, hipEventCreate(&ev));
+      s->events.push_back(ev);
+    }
+    hipError_t rec = hipSuccess;
+    for (int64_t k = 0; k < n_steps; ++k) {
+      hipEvent_t* ev = &s->events[size_t(k) * (kNumStages + 1)];
+      enqueue_pass_marked(s->own, s->stream, kModeStep, [&](int m) {
+        if (rec == hipSuccess) rec = hipEventRecord(ev[m], s->stream);
+      });
+    }
+    HIPCHK(s, rec);
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->prof_ms.resize(kNumStages, 0.0);
+    for (int64_t k = 0; k < n_steps; ++k) {
+      hipEvent_t* ev = &s->events[size_t(k) * (kNumStages + 1)];
+      for (int m = 0; m < kNumStages; ++m) {
+        float ms = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&ms, ev[m], ev[m + 1]));
+        s->prof_ms[m] += ms;
+      }
+    }
+    s->prof_steps += n_steps;
+  } else {
+    dem_status st = ensure_graph(s->own, s->stream, s);
+    if (st != DEM_OK) return st;
+    for (int64_t k = 0; k < n_steps; ++k) HIPCHK(s, hipGraphLaunch(s->own.graph, s->stream));
+  }
+  HIPCHK(s, get_entry(s, s->own.d_table, s->stream));
+  if (s->h.status != 0) {
+    dem_status code = status_code(s->h.status);
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s at step %lld; state is that at the start of that step",
+             code == DEM_ERR_CAPACITY ? "contact capacity exceeded" : "unstable contact",
+             (long long)s->h.fail_step);
+    return fail(s, code, buf);
+  }
+  return DEM_OK;
+}
+
+dem_status dem_get_counts(const dem_sim* s, int64_t* n_agg, int64_t* n_sph, int64_t* n_pairs) {
+  if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
+  if (n_agg) *n_agg = s->has_aggs ? s->h.na : 0;
+  if (n_sph) *n_sph = s->has_aggs ? s->h.ns : 0;
+  if (n_pairs) *n_pairs = s->has_aggs ? s->h.n_pairs : 0;
+  return DEM_OK;
+}
+
+namespace {
+
+// Copy a component-major device array [k][n] into row-major host [n][k].
+dem_status fetch_rows(dem_sim* s, const double* d, int k, int64_t n, double* host, hipStream_t st) {
+  std::vector<double> tmp(size_t(k) * n);
+  HIPCHK(s, hipMemcpyAsync(tmp.data(), d, tmp.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < k; ++c) host[i * k + c] = tmp[size_t(c) * n + i];
+  return DEM_OK;
+}
+
+dem_status store_rows(dem_sim* s, double* d, int k, int64_t n, const double* host, hipStream_t st) {
+  std::vector<double> tmp(size_t(k) * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < k; ++c) tmp[size_t(c) * n + i] = host[i * k + c];
+  HIPCHK(s, hipMemcpyAsync(d, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  return DEM_OK;
+}
+
+}  // namespace
+
+dem_status dem_read_state(dem_sim* s, dem_state* out) {
+  if (!s || !out) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (!s->has_aggs) return fail(s, DEM_ERR_STATE, "no aggregates");
+  hipStream_t st = stream_of(s);
+  HIPCHK(s, get_entry(s, entry_of(s), st));
+  const PileDev& h = s->h;
+  const int cur = h.parity;
+  const int64_t na = h.na, ns = h.ns;
+  dem_status r = DEM_OK;
+  auto rows = [&](const double* d, int k, int64_t n, double* host) {
+    if (host && r == DEM_OK) r = fetch_rows(s, d, k, n, host, st);
+  };
+  rows(h.rA[cur], 3, na, out->agg_pos);
+  rows(h.vA[cur], 3, na, out->agg_vel);
+  rows(h.aA[cur], 3, na, out->agg_acc);
+  rows(h.NA[cur], 3, na, out->agg_torque);
+  rows(h.q[cur], 4, na, out->agg_quat);
+  rows(h.wb[cur], 3, na, out->agg_spin_body);
+  rows(h.M, 1, na, out->agg_mass);
+  rows(h.I, 3, na, out->agg_inertia);
+  rows(h.r, 3, ns, out->sph_pos);
+  rows(h.v, 3, ns, out->sph_vel);
+  rows(h.F, 3, ns, out->sph_force);
+  rows(h.tau, 3, ns, out->sph_torque);
+  rows(h.b, 3, ns, out->sph_body);
+  if (r != DEM_OK) return r;
+  if (out->agg_spin) {
+    // space-frame spin R(q) w_b of the current state
+    std::vector<double> q(4 * na), wb(3 * na);
+    r = fetch_rows(s, h.q[cur], 4, na, q.data(), st);
+    if (r == DEM_OK) r = fetch_rows(s, h.wb[cur], 3, na, wb.data(), st);
+    if (r != DEM_OK) return r;
+    for (int64_t a = 0; a < na; ++a) {
+      const double w = q[4 * a], x = q[4 * a + 1], y = q[4 * a + 2], z = q[4 * a + 3];
+      const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                           2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                           2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+      const double* o = &wb[3 * a];
+      for (int c = 0; c < 3; ++c)
+        out->agg_spin[3 * a + c] = R[3 * c] * o[0] + R[3 * c + 1] * o[1] + R[3 * c + 2] * o[2];
+    }
+  }
+  out->n_pairs = h.n_pairs;
+  out->step = h.step;
+  if (out->pair_keys || out->pair_hist) {
+    const int64_t np = h.n_pairs;
+    std::vector<uint32_t> off(ns + 1), pj(std::max<int64_t>(np, 1));
+    HIPCHK(s, hipMemcpyAsync(off.data(), h.up_off[cur], (ns + 1) * 4, hipMemcpyDeviceToHost, st));
+    if (np) HIPCHK(s, hipMemcpyAsync(pj.data(), h.pair_j[cur], np * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    if (out->pair_keys)
+      for (int64_t i = 0; i < ns; ++i)
+        for (uint32_t p = off[i]; p < off[i + 1]; ++p)
+          out->pair_keys[p] = (uint64_t(i) << 32) | pj[p];
+    if (out->pair_hist && np) {
+      std::vector<double> hh(size_t(kHist) * h.cap_pairs);
+      HIPCHK(s, hipMemcpyAsync(hh.data(), h.hist[cur], hh.size() * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(s, hipStreamSynchronize(st));
+      for (int64_t p = 0; p < np; ++p)
+        for (int c = 0; c < kHist; ++c) out->pair_hist[p * kHist + c] = hh[size_t(c) * h.cap_pairs + p];
+    }
+  }
+  return DEM_OK;
+}
+
+dem_status dem_restore_state(dem_sim* s, const dem_state* in) {
+  if (!s || !in) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (!s->has_aggs) return fail(s, DEM_ERR_STATE, "no aggregates");
+  if (s->engine) return fail(s, DEM_ERR_STATE, "system is attached to an engine");
+  if (!in->agg_pos || !in->agg_vel || !in->agg_acc || !in->agg_torque || !in->agg_quat ||
+      !in->agg_spin_body)
+    return fail(s, DEM_ERR_INVALID_ARG, "restore needs the aggregate state fields");
+  if (in->n_pairs < 0 || (in->n_pairs > 0 && (!in->pair_keys || !in->pair_hist)))
+    return fail(s, DEM_ERR_INVALID_ARG, "restore needs pair keys and history");
+  if (in->n_pairs > s->h.cap_pairs) return fail(s, DEM_ERR_CAPACITY, "checkpoint has more contacts than capacity");
+  hipStream_t st = s->stream;
+  HIPCHK(s, hipStreamSynchronize(st));
+  PileDev& h = s->h;
+  const int cur = h.parity;
+  const int64_t na = h.na, ns = h.ns, np = in->n_pairs;
+  dem_status r = store_rows(s, h.rA[cur], 3, na, in->agg_pos, st);
+  if (r == DEM_OK) r = store_rows(s, h.vA[cur], 3, na, in->agg_vel, st);
+  if (r == DEM_OK) r = store_rows(s, h.aA[cur], 3, na, in->agg_acc, st);
+  if (r == DEM_OK) r = store_rows(s, h.NA[cur], 3, na, in->agg_torque, st);
+  if (r == DEM_OK) r = store_rows(s, h.q[cur], 4, na, in->agg_quat, st);
+  if (r == DEM_OK) r = store_rows(s, h.wb[cur], 3, na, in->agg_spin_body, st);
+  if (r != DEM_OK) return r;
+  // contact list as CSR of the canonical keys
+  std::vector<uint32_t> off(ns + 1, 0), pj(std::max<int64_t>(np, 1));
+  for (int64_t p = 0; p < np; ++p) {
+    const uint64_t key = in->pair_keys[p];
+    const int64_t i = int64_t(key >> 32), j = int64_t(key & 0xffffffffu);
+    if (i < 0 || i >= ns || j <= i || j >= ns || (p > 0 && key <= in->pair_keys[p - 1]))
+      return fail(s, DEM_ERR_INVALID_ARG, "pair keys must be canonical and sorted");
+    off[i + 1]++;
+    pj[p] = uint32_t(j);
+  }
+  for (int64_t i = 0; i < ns; ++i) off[i + 1] += off[i];
+  HIPCHK(s, hipMemcpyAsync(h.up_off[cur], off.data(), (ns + 1) * 4, hipMemcpyHostToDevice, st));
+  if (np) {
+    HIPCHK(s, hipMemcpyAsync(h.pair_j[cur], pj.data(), np * 4, hipMemcpyHostToDevice, st));
+    std::vector<double> col(np);
+    for (int c = 0; c < kHist; ++c) {
+      for (int64_t p = 0; p < np; ++p) col[p] = in->pair_hist[p * kHist + c];
+      HIPCHK(s, hipMemcpyAsync(h.hist[cur] + size_t(c) * h.cap_pairs, col.data(), np * 8,
+                               hipMemcpyHostToDevice, st));
+      HIPCHK(s, hipStreamSynchronize(st));
+    }
+  }
+  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells);
+  h.status = 0;
+  h.fail_step = -1;
+  h.step = in->step;
+  h.n_pairs = uint32_t(np);
+  HIPCHK(s, put_entry(s, s->own.d_table, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  return DEM_OK;
+}
+
+dem_status dem_set_forcing(dem_sim* s, const dem_forcing* f) {
+  if (!s || !f) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(f->spin_dw)) return fail(s, DEM_ERR_INVALID_ARG, "non-finite forcing");
+  s->spin_dw = f->spin_dw;
+  if (!s->has_aggs) return DEM_OK;
+  hipStream_t st = stream_of(s);
+  HIPCHK(s, get_entry(s, entry_of(s), st));
+  s->h.spin_dw = f->spin_dw;
+  HIPCHK(s, put_entry(s, const_cast<PileDev*>(entry_of(s)), st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  return DEM_OK;
+}
+
+dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
+  if (!s || per_sphere <= 0) return fail(s, DEM_ERR_INVALID_ARG, "bad argument");
+  if (s->engine) return fail(s, DEM_ERR_STATE, "system is attached to an engine");
+  if (!s->has_aggs) {
+    s->c_max = per_sphere;
+    return DEM_OK;
+  }
+  if (per_sphere <= s->c_max) return DEM_OK;
+  // checkpoint the state, reallocate with the larger capacity, restore
+  hipStream_t st = s->stream;
+  HIPCHK(s, get_entry(s, s->own.d_table, st));
+  const int64_t na = s->h.na, ns = s->h.ns, np = s->h.n_pairs;
+  std::vector<double> rA(3 * na), vA(3 * na), aA(3 * na), NA(3 * na), q(4 * na), wb(3 * na),
+      b(3 * ns), hist(kHist * std::max<int64_t>(np, 1));
+  std::vector<uint64_t> keys(std::max<int64_t>(np, 1));
+  dem_state io{};
+  io.agg_pos = rA.data();
+  io.agg_vel = vA.data();
+  io.agg_acc = aA.data();
+  io.agg_torque = NA.data();
+  io.agg_quat = q.data();
+  io.agg_spin_body = wb.data();
+  io.pair_keys = keys.data();
+  io.pair_hist = hist.data();
+  dem_status r = dem_read_state(s, &io);
+  if (r != DEM_OK) return r;
+  // constants that survive: copy them to host too
+  std::vector<int32_t> first(na), count(na), agg(ns);
+  std::vector<double> M(na), I(3 * na), rad(ns), mass(ns);
+  const PileDev old = s->h;
+  HIPCHK(s, hipMemcpyAsync(first.data(), old.first, na * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(count.data(), old.count, na * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(agg.data(), old.agg, ns * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(M.data(), old.M, na * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(I.data(), old.I, 3 * na * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(b.data(), old.b, 3 * ns * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(rad.data(), old.s, ns * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(mass.data(), old.m, ns * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  const double cell_min = old.cell_min;
+  const int nbp = old.nb_periodic;
+  const int64_t step = old.step;
+  free_meta(s->own);
+  release_pile(s);
+  s->c_max = per_sphere;
+  r = alloc_pile(s, na, ns);
+  if (r != DEM_OK) return r;
+  PileDev& h = s->h;
+  h.cell_min = cell_min;
+  h.nb_periodic = nbp;
+  h.step = step;
+  HIPCHK(s, hipMemcpyAsync(h.first, first.data(), na * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.count, count.data(), na * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.agg, agg.data(), ns * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.M, M.data(), na * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.I, I.data(), 3 * na * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.b, b.data(), 3 * ns * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.s, rad.data(), ns * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.m, mass.data(), ns * 8, hipMemcpyHostToDevice, st));
+  launch_fill_u32(st, h.up_off[0], 0u, ns + 1);
+  launch_fill_u32(st, h.up_off[1], 0u, ns + 1);
+  launch_fill_u32(st, h.lo_off, 0u, ns + 1);
+  r = ensure_own_table(s);
+  if (r != DEM_OK) return r;
+  HIPCHK(s, put_entry(s, s->own.d_table, st));
+  r = rebuild(s->own, st, s);
+  if (r != DEM_OK) return r;
+  io.n_pairs = np;
+  io.step = step;
+  return dem_restore_state(s, &io);
+}
+
+dem_status dem_set_profiling(dem_sim* s, int32_t enabled) {
+  if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
+  s->profiling = enabled != 0;
+  s->prof_ms.assign(kNumStages, 0.0);
+  s->prof_steps = 0;
+  return DEM_OK;
+}
+
+dem_status dem_get_profile(const dem_sim* s, double* kernel_ms, int32_t n_max, int64_t* n_steps) {
+  if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
+  for (int k = 0; k < n_max && k < kNumStages; ++k)
+    kernel_ms[k] = k < (int)s->prof_ms.size() ? s->prof_ms[k] : 0.0;
+  if (n_steps) *n_steps = s->prof_steps;
+  return DEM_OK;
+}
+
+const char* dem_profile_names(void) { return kStageNames; }
+
+dem_status dem_sim_status(const dem_sim* s) {
+  if (!s) return DEM_ERR_INVALID_ARG;
+  return status_code(s->h.status);
+}
+
+// ---------------------------------------------------------------------------
+// stateless contact search
+// ---------------------------------------------------------------------------
+
+dem_status dem_find_contacts(const double* pos, const double* radius, const int32_t* agg,
+                             int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,
+                             int64_t* n_out) {
+  if (!pos || !radius || !agg || n <= 0 || !n_out || (cap > 0 && !pairs_out))
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  if (n > (int64_t(1) << 28)) return fail(nullptr, DEM_ERR_INVALID_ARG, "too many spheres");
+  double smax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(radius[i] > 0) || !std::isfinite(radius[i])) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad radius");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(pos[3 * i + k])) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad position");
+    smax = std::max(smax, radius[i]);
+  }
+  dem_params p{};
+  p.dt = 1.0;
+  p.k_n = p.k_t = 1.0;
+  p.eps_n = p.eps_t = 1.0;
+  p.periodic = box ? 1 : 0;
+  if (box) {
+    p.box[0] = p.box[1] = p.box[2] = box[0];
+    if (!(box[0] > 0)) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad box");
+  }
+  p.max_contacts_per_sphere = kFindContactsCap;
+  dem_sim* s = nullptr;
+  dem_status r = dem_create(&p, nullptr, nullptr, &s);
+  if (r != DEM_OK) return r;
+  struct Guard {
+    dem_sim* s;
+    ~Guard() { dem_destroy(s); }
+  } guard{s};
+  int nbp = 0;
+  if (box) {
+    const double ratio = box[0] / (2.0 * smax);
+    nbp = ratio >= 1.0 ? (int)std::floor(std::log2(ratio)) : 0;
+  }
+  // one sphere per pseudo-aggregate; the given ids decide which pairs count
+  r = alloc_pile(s, n, n);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  PileDev& h = s->h;
+  h.na = 0;   // positions are given: reconstruction only measures the bbox
+  h.cell_min = 2.0 * smax;
+  h.nb_periodic = std::min(nbp, h.bits);
+  hipStream_t st = nullptr;
+  std::vector<double> col(3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) col[k * n + i] = pos[3 * i + k];
+  std::vector<double> ones(n, 1.0);
+  HIPCHK(s, hipMemcpyAsync(h.r, col.data(), 3 * n * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.s, radius, n * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.m, ones.data(), n * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(h.agg, agg, n * 4, hipMemcpyHostToDevice, st));
+  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells);
+  r = ensure_own_table(s);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  HIPCHK(s, put_entry(s, s->own.d_table, st));
+  r = rebuild(s->own, st, s);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  Batch& b = s->own;
+  launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_grid(st, b.d_table, 1);
+  launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells);
+  launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
+  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
+  HIPCHK(s, hipGetLastError());
+  PileDev tmp;
+  HIPCHK(s, hipMemcpyAsync(&tmp, b.d_table, sizeof(PileDev), hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> off(n + 1);
+  HIPCHK(s, hipMemcpyAsync(off.data(), h.up_off[1], (n + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  const int64_t total = off[n];
+  *n_out = total;
+  if (tmp.status & kStCapacity) return fail(nullptr, DEM_ERR_CAPACITY, "more than 64 contacts per sphere");
+  if (tmp.status != 0) return fail(nullptr, DEM_ERR_INVALID_ARG, "non-finite positions");
+  std::vector<uint32_t> pj(std::max<int64_t>(total, 1));
+  if (total) HIPCHK(s, hipMemcpy(pj.data(), h.pair_j[1], total * 4, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i)
+    for (uint32_t q = off[i]; q < off[i + 1] && q < cap; ++q)
+      pairs_out[q] = (uint64_t(i) << 32) | pj[q];
+  return DEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// engine
+// ---------------------------------------------------------------------------
+
+dem_status dem_engine_create(size_t budget, void* hip_stream, dem_engine** out) {
+  if (!out) return fail(nullptr, DEM_ERR_INVALID_ARG, "out is NULL");
+  dem_engine* e = new dem_engine();
+  e->budget = budget;
+  e->stream = static_cast<hipStream_t>(hip_stream);
+  *out = e;
+  return DEM_OK;
+}
+
+namespace {
+
+bool same_contact_model(const dem_params& a, const dem_params& b) {
+  return a.dt == b.dt && a.k_n == b.k_n && a.k_t == b.k_t && a.eps_n == b.eps_n &&
+         a.eps_t == b.eps_t && a.mu_s == b.mu_s && a.mu_r == b.mu_r && a.mu_t == b.mu_t &&
+         a.k_r == b.k_r && a.k_q == b.k_q && a.precision == b.precision &&
+         a.max_overlap_frac == b.max_overlap_frac;
+}
+
+dem_status engine_table(dem_engine* e, dem_sim* errsim) {
+  Batch& b = e->batch;
+  const int n = (int)b.members.size();
+  if (n > b.table_cap) {
+    int nc = std::max(16, b.table_cap * 2);
+    while (nc < n) nc *= 2;
+    PileDev* t = nullptr;
+    HIPCHK(errsim, hipMalloc(&t, size_t(nc) * sizeof(PileDev)));
+    if (b.d_table) {
+      HIPCHK(errsim, hipMemcpyAsync(t, b.d_table, size_t(b.table_cap) * sizeof(PileDev),
+                                    hipMemcpyDeviceToDevice, e->stream));
+      HIPCHK(errsim, hipStreamSynchronize(e->stream));
+      (void)hipFree(b.d_table);
+    }
+    b.d_table = t;
+    b.table_cap = nc;
+  }
+  return DEM_OK;
+}
+
+}  // namespace
+
+dem_status dem_engine_attach(dem_engine* e, dem_sim* s) {
+  if (!e || !s) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (s->engine) return fail(s, DEM_ERR_STATE, "already attached");
+  if (!s->has_aggs) return fail(s, DEM_ERR_STATE, "no aggregates");
+  if (s->h.status != 0) return fail(s, DEM_ERR_STATE, "system has failed; restore it first");
+  if (!e->batch.members.empty() && !same_contact_model(e->batch.members[0]->prm, s->prm))
+    return fail(s, DEM_ERR_INVALID_ARG, "contact model or time step differs from the engine's");
+  if (e->used + s->bytes > e->budget) return fail(s, DEM_ERR_OOM, "engine memory budget exceeded");
+  // settle the system's own work, then move its table entry into the engine
+  HIPCHK(s, get_entry(s, s->own.d_table, s->stream));
+  Batch& b = e->batch;
+  b.members.push_back(s);
+  dem_status r = engine_table(e, s);
+  if (r != DEM_OK) {
+    b.members.pop_back();
+    return r;
+  }
+  const int slot = (int)b.members.size() - 1;
+  HIPCHK(s, put_entry(s, b.d_table + slot, e->stream));
+  s->engine = e;
+  s->engine_slot = slot;
+  e->used += s->bytes;
+  b.cp = contact_params(b.members[0]->prm);
+  b.precision = b.members[0]->prm.precision;
+  b.dirty = true;
+  return DEM_OK;
+}
+
+dem_status dem_engine_detach(dem_engine* e, dem_sim* s) {
+  if (!e || !s) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (s->engine != e) return fail(s, DEM_ERR_STATE, "not attached to this engine");
+  Batch& b = e->batch;
+  HIPCHK(s, hipStreamSynchronize(e->stream));
+  HIPCHK(s, get_entry(s, b.d_table + s->engine_slot, e->stream));
+  // compact the table: move later entries down by one
+  const int slot = s->engine_slot;
+  for (int k = slot + 1; k < (int)b.members.size(); ++k) {
+    dem_sim* o = b.members[k];
+    HIPCHK(s, get_entry(o, b.d_table + k, e->stream));
+    HIPCHK(s, put_entry(o, b.d_table + k - 1, e->stream));
+    o->engine_slot = k - 1;
+  }
+  b.members.erase(b.members.begin() + slot);
+  e->used -= s->bytes;
+  s->engine = nullptr;
+  s->engine_slot = -1;
+  HIPCHK(s, put_entry(s, s->own.d_table, s->stream));
+  HIPCHK(s, hipStreamSynchronize(e->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  b.dirty = true;
+  return DEM_OK;
+}
+
+dem_status dem_engine_step(dem_engine* e, int64_t n_steps) {
+  if (!e) return fail(nullptr, DEM_ERR_INVALID_ARG, "engine is NULL");
+  Batch& b = e->batch;
+  if (b.members.empty() || n_steps <= 0) return DEM_OK;
+  if (b.dirty) {
+    dem_status r = rebuild(b, e->stream, b.members[0]);
+    if (r != DEM_OK) return r;
+  }
+  dem_status r = ensure_graph(b, e->stream, b.members[0]);
+  if (r != DEM_OK) return r;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    hipError_t he = hipGraphLaunch(b.graph, e->stream);
+    if (he != hipSuccess) return fail(b.members[0], DEM_ERR_DEVICE, hip_msg(he, "hipGraphLaunch"));
+  }
+  // one read-back of every entry's bookkeeping
+  std::vector<PileDev> tab(b.members.size());
+  hipError_t he = hipMemcpyAsync(tab.data(), b.d_table, tab.size() * sizeof(PileDev),
+                                 hipMemcpyDeviceToHost, e->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+  if (he != hipSuccess) return fail(b.members[0], DEM_ERR_DEVICE, hip_msg(he, "engine read-back"));
+  dem_status first = DEM_OK;
+  for (size_t k = 0; k < b.members.size(); ++k) {
+    dem_sim* s = b.members[k];
+    s->h.parity = tab[k].parity;
+    s->h.status = tab[k].status;
+    s->h.step = tab[k].step;
+    s->h.fail_step = tab[k].fail_step;
+    s->h.n_pairs = tab[k].n_pairs;
+    s->stepped = true;
+    const dem_status c = status_code(s->h.status);
+    if (c != DEM_OK && first == DEM_OK) first = c;
+  }
+  return first;
+}
+
+dem_status dem_engine_destroy(dem_engine* e) {
+  if (!e) return DEM_OK;
+  while (!e->batch.members.empty()) dem_engine_detach(e, e->batch.members.back());
+  free_meta(e->batch);
+  if (e->batch.d_table) (void)hipFree(e->batch.d_table);
+  delete e;
+  return DEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+// dem_internal.h -- device-side layout of the DEM step (gfx950).
+//
+// Every kernel covers a *batch* of independent systems ("piles").  Each pile
+// owns its device buffers; a device-resident table of PileDev entries holds
+// their pointers, and static work lists map each launch block to
+// (pile, first element).  A standalone system is a batch of one pile.
+//
+// Layout in HBM: structure-of-arrays, FP64, 3-vectors stored component-major
+// ([3][n]) so that consecutive lanes read consecutive addresses.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dem {
+
+constexpr int kBlock = 256;        // threads per block (4 wave64)
+constexpr int kHist = 7;           // spring history per contact: xi_t[3], xi_r[3], xi_q
+constexpr int kScanItems = 8;      // elements per thread in the batched scan
+constexpr int kScanChunk = kBlock * kScanItems;
+
+// status bits of a pile (device-written)
+constexpr int kStCapacity = 1;
+constexpr int kStUnstable = 2;
+
+// modes of one pass through the step graph
+constexpr int kModeStep = 0;       // kick, drift, rotate, evaluate, kick
+constexpr int kModeInit = 1;       // evaluate at t0 only (no motion, no kick)
+
+// Contact model constants shared by every pile of a batch.
+struct ContactParams {
+  double dt;
+  double k_n, k_t, k_r, k_q;
+  double mu_s, mu_r, mu_t;
+  double damp_n, damp_t;     // -2 ln(eps) / sqrt(pi^2 + ln^2 eps): C = damp * sqrt(k mu)
+  double max_overlap_frac;   // <= 0: no check
+};
+
+// Per-pile cell grid, written on the device every step.
+struct Grid {
+  double lo[3];              // origin of cell (0,0,0)
+  double cell;               // cell side (>= largest sphere diameter)
+  double inv_cell;
+  double com[3];             // centre of mass of the pile (spin-up forcing)
+  int32_t nb;                // cells per axis = 1 << nb
+  int32_t pad;
+};
+
+struct PileDev {
+  // sizes (host-set)
+  int32_t na, ns;
+  int32_t cap_pairs;         // capacity of each contact list (upper and lower)
+  int32_t bits;              // cell table is (1 << bits)^3 Morton codes
+  int32_t periodic;
+  int32_t n_split;           // gravity j-splits
+  int32_t n_rblk;            // reconstruct blocks (bbox partials)
+  int32_t nb_periodic;       // cells per axis = 1 << nb_periodic for a periodic pile
+  double box;                // periodic cube side
+  double G, soft_frac, spin_dw;
+  double cell_min;           // largest sphere diameter of the pile
+
+  // device-updated bookkeeping
+  int32_t parity;            // which half of each ping-pong pair is current
+  int32_t status;            // kSt* bits; a failed pile is frozen
+  int64_t step;              // steps completed
+  int64_t fail_step;         // step index at which it failed
+  uint32_t n_pairs;          // contacts of the last evaluation
+  uint32_t pad0;
+
+  // aggregate constants (written once by the set-up kernel)
+  int32_t* first;            // [na] first member sphere
+  int32_t* count;            // [na]
+  double* M;                 // [na]
+  double* I;                 // [3][na] principal moments
+  // aggregate state, ping-pong [2]
+  double* rA[2];             // [3][na]
+  double* vA[2];
+  double* aA[2];
+  double* NA[2];
+  double* q[2];              // [4][na]
+  double* wb[2];             // [3][na]
+  double* wA;                // [3][na] spin in space frame (this step)
+  double* vpred;             // [3][na] predicted COM velocity (Eq. 3, first bracket)
+
+  // sphere constants (set-up)
+  double* b;                 // [3][ns] body offsets
+  double* s;                 // [ns] radius
+  double* m;                 // [ns] mass
+  int32_t* agg;              // [ns] aggregate of each sphere
+  // sphere per-step
+  double* r;                 // [3][ns]
+  double* v;                 // [3][ns]
+  double* F;                 // [3][ns]
+  double* tau;               // [3][ns]
+  uint32_t* key;             // [ns] Morton cell code
+  uint32_t* sidx;            // [ns] sphere at sorted slot
+  uint32_t* slot;            // [ns] sorted slot of sphere
+  double* xs;                // [4][ns] sorted x, y, z, radius
+  int32_t* sagg;             // [ns] sorted aggregate id
+  void* jrec;                // gravity source records in sorted order
+  double* gpart;             // [n_split][3][ns] gravity partial sums (sorted slots)
+  double* bpart;             // [n_rblk][10] bbox min/max + mass moments
+  Grid* grid;
+  uint32_t* cell_cnt;        // [cells]
+  uint32_t* cell_start;      // [cells + 1]
+  uint32_t* cnt_up;          // [ns]
+  uint32_t* cnt_lo;          // [ns]
+  uint32_t* up_off[2];       // [ns + 1] CSR of contacts (i, j>i) by i
+  uint32_t* lo_off;          // [ns + 1] CSR of contacts (j<i, i) by i
+  uint32_t* pair_j[2];       // [cap]
+  double* hist[2];           // [kHist][cap]
+  uint32_t* lo_nbr;          // [cap] lower neighbour ids
+  uint32_t* lo_pair;         // [cap] index of (j, i) in the upper list
+  double* pF;                // [3][cap] force on i of contact (i, j)
+  double* pTi;               // [3][cap] torque on i about its centre
+  double* pTj;               // [3][cap] torque on j about its centre
+};
+
+// One block of a per-element kernel: pile p, elements base .. base+255.
+struct WorkItem {
+  int32_t pile;
+  int32_t base;
+};
+
+// One block of the gravity kernel.
+struct GravItem {
+  int32_t pile;
+  int32_t ibase;             // first target slot
+  int32_t j0, j1;            // source slots [j0, j1)
+  int32_t split;
+  int32_t pad;
+};
+
+// One segment of the batched exclusive scan (out[n] receives the total).
+// When parity is set, the output is out_pp[*parity ^ 1] (the next half of a
+// ping-pong pair), else out_pp[0].
+struct ScanSeg {
+  const uint32_t* in;
+  uint32_t* out_pp[2];
+  const int32_t* parity;
+  int32_t n;
+  int32_t item0;             // first work item of this segment
+  int32_t n_items;
+  int32_t pad;
+};
+
+struct ScanItem {
+  int32_t seg;
+  int32_t chunk;             // chunk index inside the segment
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each defined next to its kernels)
+// ---------------------------------------------------------------------------
+void launch_setup(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                  const double* pos_in, const double* vel_in, const double* spin_in);
+void launch_integrate(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                      ContactParams cp, int mode);
+void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+void launch_grid(hipStream_t st, const PileDev* piles, int n_piles);
+void launch_bin(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+void launch_scatter(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
+void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                  ContactParams cp, int precision);
+void launch_gravity(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
+                    int precision, bool softened);
+int gravity_ipt(int precision);
+void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                   ContactParams cp, int mode);
+void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode);
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
+void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
+                 int n_items, uint32_t* item_sums);
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+  const double x = a[1] * b[2] - a[2] * b[1];
+  const double y = a[2] * b[0] - a[0] * b[2];
+  const double z = a[0] * b[1] - a[1] * b[0];
+  c[0] = x;
+  c[1] = y;
+  c[2] = z;
+}
+
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Rotation matrix (body -> space, row-major) of quaternion (w, x, y, z),
+// the unit-quaternion formula applied to q as given.
+__device__ __forceinline__ void quat_rot(const double q[4], double R[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ __forceinline__ void rot_apply(const double R[9], const double a[3], double c[3]) {
+  c[0] = R[0] * a[0] + R[1] * a[1] + R[2] * a[2];
+  c[1] = R[3] * a[0] + R[4] * a[1] + R[5] * a[2];
+  c[2] = R[6] * a[0] + R[7] * a[1] + R[8] * a[2];
+}
+
+__device__ __forceinline__ void rot_apply_T(const double R[9], const double a[3], double c[3]) {
+  c[0] = R[0] * a[0] + R[3] * a[1] + R[6] * a[2];
+  c[1] = R[1] * a[0] + R[4] * a[1] + R[7] * a[2];
+  c[2] = R[2] * a[0] + R[5] * a[1] + R[8] * a[2];
+}
+
+// Spread the low 10 bits of v to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Cell coordinate of a position on one axis.  Periodic piles wrap the
+// coordinate into [0, L) first (sphere centres are not wrapped; only the
+// aggregate centres are).
+__device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, int n,
+                                          int periodic, double L) {
+  if (periodic) {
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+  }
+  int c = (int)floor((x - lo) * inv_cell);
+  c = c < 0 ? 0 : c;
+  c = c > n - 1 ? n - 1 : c;
+  return c;
+}
+
+}  // namespace dem

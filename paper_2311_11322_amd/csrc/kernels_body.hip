@@ -1,0 +1,540 @@
+// kernels_body.hip -- rigid-body kernels: aggregate set-up, kick/drift/rotate,
+// member reconstruction, reduction onto aggregates, end-of-step bookkeeping.
+//
+// Paper references: aggregate mass and centre of mass (Eqs. 1-2); the
+// appendix table of aggregate functions (CountPart, GetCOM, GetAxesAndSpin,
+// SetBodyPos, SetMassDEM, SetSpacePos/Spin/Vel, GetAccelAndTorque); leapfrog
+// for centres of mass and a fifth-order Runge-Kutta step for orientation and
+// spin (Sec. 2.1-2.2); predicted member velocity (Eq. 3); aggregate
+// acceleration and torque (Eqs. 5-7, 9).
+#include "dem_internal.h"
+
+namespace dem {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// set-up of one aggregate
+// ---------------------------------------------------------------------------
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi plane rotations.  a is
+// overwritten (eigenvalues on the diagonal); columns of V are eigenvectors.
+__device__ void jacobi_eig3(double a[3][3], double V[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off == 0.0 || off <= 1e-34 * dia) break;
+    for (int k = 0; k < 3; ++k) {
+      const int p = P[k], q = Q[k];
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double zeta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + t * t);
+      const double s = t * c;
+      a[p][p] -= t * apq;
+      a[q][q] += t * apq;
+      a[p][q] = a[q][p] = 0.0;
+      const int r = 3 - p - q;
+      const double arp = a[r][p], arq = a[r][q];
+      a[r][p] = a[p][r] = c * arp - s * arq;
+      a[r][q] = a[q][r] = s * arp + c * arq;
+      for (int i = 0; i < 3; ++i) {
+        const double vip = V[i][p], viq = V[i][q];
+        V[i][p] = c * vip - s * viq;
+        V[i][q] = s * vip + c * viq;
+      }
+    }
+  }
+}
+
+// Unit quaternion of a proper rotation matrix (largest-component branch).
+__device__ void rot_to_quat(const double R[3][3], double q[4]) {
+  const double t0 = R[0][0] + R[1][1] + R[2][2];
+  double w, x, y, z;
+  if (t0 >= R[0][0] && t0 >= R[1][1] && t0 >= R[2][2]) {
+    const double f = 2.0 * sqrt(1.0 + t0);
+    w = 0.25 * f;
+    x = (R[2][1] - R[1][2]) / f;
+    y = (R[0][2] - R[2][0]) / f;
+    z = (R[1][0] - R[0][1]) / f;
+  } else if (R[0][0] >= R[1][1] && R[0][0] >= R[2][2]) {
+    const double f = 2.0 * sqrt(1.0 + R[0][0] - R[1][1] - R[2][2]);
+    w = (R[2][1] - R[1][2]) / f;
+    x = 0.25 * f;
+    y = (R[0][1] + R[1][0]) / f;
+    z = (R[0][2] + R[2][0]) / f;
+  } else if (R[1][1] >= R[2][2]) {
+    const double f = 2.0 * sqrt(1.0 + R[1][1] - R[0][0] - R[2][2]);
+    w = (R[0][2] - R[2][0]) / f;
+    x = (R[0][1] + R[1][0]) / f;
+    y = 0.25 * f;
+    z = (R[1][2] + R[2][1]) / f;
+  } else {
+    const double f = 2.0 * sqrt(1.0 + R[2][2] - R[0][0] - R[1][1]);
+    w = (R[1][0] - R[0][1]) / f;
+    x = (R[0][2] + R[2][0]) / f;
+    y = (R[1][2] + R[2][1]) / f;
+    z = 0.25 * f;
+  }
+  const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  q[0] = w * inv;
+  q[1] = x * inv;
+  q[2] = y * inv;
+  q[3] = z * inv;
+}
+
+// One thread per aggregate: CountPart/GetCOM (Eqs. 1-2), the inertia tensor
+// about the centre of mass with each sphere's own 2/5 m s^2, its principal
+// axes (GetAxesAndSpin) as a proper rotation and quaternion, body offsets
+// (SetBodyPos) and the body-frame spin.  pos_in/vel_in/spin_in are the
+// caller's row-major arrays copied to the device.
+__global__ __launch_bounds__(kBlock) void k_setup(const PileDev* __restrict__ piles,
+                                                  const WorkItem* __restrict__ wl,
+                                                  const double* __restrict__ pos_in,
+                                                  const double* __restrict__ vel_in,
+                                                  const double* __restrict__ spin_in) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  const int A = w.base + threadIdx.x;
+  if (A >= P.na) return;
+  const int i0 = P.first[A], n = P.count[A];
+  double M = 0.0, c[3] = {0.0, 0.0, 0.0};
+  for (int i = i0; i < i0 + n; ++i) M += P.m[i];
+  for (int i = i0; i < i0 + n; ++i)
+    for (int k = 0; k < 3; ++k) c[k] += P.m[i] * pos_in[3 * i + k];
+  for (int k = 0; k < 3; ++k) c[k] /= M;
+  double T[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = i0; i < i0 + n; ++i) {
+    const double d[3] = {pos_in[3 * i] - c[0], pos_in[3 * i + 1] - c[1], pos_in[3 * i + 2] - c[2]};
+    const double mi = P.m[i];
+    const double tr = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 0.4 * P.s[i] * P.s[i];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) T[a][b] += mi * ((a == b ? tr : 0.0) - d[a] * d[b]);
+  }
+  double V[3][3];
+  jacobi_eig3(T, V);
+  // right-handed axes
+  const double c0[3] = {V[0][0], V[1][0], V[2][0]}, c1[3] = {V[0][1], V[1][1], V[2][1]},
+               c2[3] = {V[0][2], V[1][2], V[2][2]};
+  double x01[3];
+  cross3(c0, c1, x01);
+  if (dot3(x01, c2) < 0.0)
+    for (int a = 0; a < 3; ++a) V[a][2] = -V[a][2];
+  double q[4], R[9];
+  rot_to_quat(V, q);
+  quat_rot(q, R);
+  for (int i = i0; i < i0 + n; ++i) {
+    const double d[3] = {pos_in[3 * i] - c[0], pos_in[3 * i + 1] - c[1], pos_in[3 * i + 2] - c[2]};
+    double bb[3];
+    rot_apply_T(R, d, bb);
+    for (int k = 0; k < 3; ++k) P.b[k * P.ns + i] = bb[k];
+  }
+  const int cur = P.parity;
+  P.M[A] = M;
+  for (int k = 0; k < 3; ++k) {
+    P.I[k * P.na + A] = T[k][k];
+    double x = c[k];
+    if (P.periodic) {
+      const double L = P.box;
+      x = x - L * floor(x / L);
+      if (x >= L) x -= L;
+    }
+    P.rA[cur][k * P.na + A] = x;
+    P.vA[cur][k * P.na + A] = vel_in ? vel_in[3 * A + k] : 0.0;
+    P.aA[cur][k * P.na + A] = 0.0;
+    P.NA[cur][k * P.na + A] = 0.0;
+  }
+  double ws[3] = {0.0, 0.0, 0.0}, wbv[3];
+  if (spin_in)
+    for (int k = 0; k < 3; ++k) ws[k] = spin_in[3 * A + k];
+  rot_apply_T(R, ws, wbv);
+  for (int k = 0; k < 3; ++k) P.wb[cur][k * P.na + A] = wbv[k];
+  for (int k = 0; k < 4; ++k) P.q[cur][k * P.na + A] = q[k];
+}
+
+// ---------------------------------------------------------------------------
+// rotation: Euler's equations with quaternion kinematics, Cash-Karp RK5
+// ---------------------------------------------------------------------------
+
+// y = (q0..q3, w1..w3); body-frame principal moments I; torque N fixed in
+// the space frame.  dq/dt = q (x) (0, w) / 2; I dw/dt = R^T N - w x (I w).
+__device__ __forceinline__ void euler_deriv(const double y[7], const double I[3],
+                                            const double N[3], double f[7]) {
+  double R[9], Nb[3];
+  quat_rot(y, R);
+  rot_apply_T(R, N, Nb);
+  const double w = y[0], x = y[1], yy = y[2], z = y[3];
+  const double o1 = y[4], o2 = y[5], o3 = y[6];
+  f[0] = 0.5 * (-x * o1 - yy * o2 - z * o3);
+  f[1] = 0.5 * (w * o1 + yy * o3 - z * o2);
+  f[2] = 0.5 * (w * o2 + z * o1 - x * o3);
+  f[3] = 0.5 * (w * o3 + x * o2 - yy * o1);
+  f[4] = (Nb[0] - (I[2] - I[1]) * o2 * o3) / I[0];
+  f[5] = (Nb[1] - (I[0] - I[2]) * o3 * o1) / I[1];
+  f[6] = (Nb[2] - (I[1] - I[0]) * o1 * o2) / I[2];
+}
+
+// Cash & Karp (1990) fifth-order weights and stage matrix.
+__constant__ double ck_a[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+__constant__ double ck_b[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0,
+                               512.0 / 1771.0};
+
+__device__ void rk5_rotate(double y[7], const double I[3], const double N[3], double h) {
+  double k[6][7];
+  for (int st = 0; st < 6; ++st) {
+    double ys[7];
+    for (int c = 0; c < 7; ++c) {
+      double acc = 0.0;
+      for (int j = 0; j < st; ++j) acc += ck_a[st][j] * k[j][c];
+      ys[c] = y[c] + h * acc;
+    }
+    euler_deriv(ys, I, N, k[st]);
+  }
+  for (int c = 0; c < 7; ++c) {
+    double acc = 0.0;
+    for (int st = 0; st < 6; ++st) acc += ck_b[st] * k[st][c];
+    y[c] = y[c] + h * acc;
+  }
+  const double inv = 1.0 / sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+  for (int c = 0; c < 4; ++c) y[c] *= inv;
+}
+
+// One thread per aggregate.  Step mode: v_A += h/2 a_A, r_A += h v_A (wrapped
+// in a periodic cube), one RK5 step of (q, w_b) with the last torque.  Writes
+// the next state, the space-frame spin w_A = R w_b and the predicted
+// centre-of-mass velocity v_A + h/2 a_A (first bracket of Eq. 3).  Init mode
+// copies the state unchanged (evaluation at t0).
+__global__ __launch_bounds__(kBlock) void k_integrate(const PileDev* __restrict__ piles,
+                                                      const WorkItem* __restrict__ wl,
+                                                      ContactParams cp, int mode) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  const int A = w.base + threadIdx.x;
+  if (A >= P.na || P.status != 0) return;
+  const int na = P.na, cur = P.parity, nxt = cur ^ 1;
+  const double h = cp.dt;
+  double v[3], r[3], a[3], y[7];
+  for (int k = 0; k < 3; ++k) {
+    v[k] = P.vA[cur][k * na + A];
+    r[k] = P.rA[cur][k * na + A];
+    a[k] = P.aA[cur][k * na + A];
+  }
+  for (int k = 0; k < 4; ++k) y[k] = P.q[cur][k * na + A];
+  for (int k = 0; k < 3; ++k) y[4 + k] = P.wb[cur][k * na + A];
+  if (mode == kModeStep) {
+    for (int k = 0; k < 3; ++k) {
+      v[k] += 0.5 * h * a[k];
+      r[k] += h * v[k];
+    }
+    if (P.periodic) {
+      const double L = P.box;
+      for (int k = 0; k < 3; ++k) {
+        if (r[k] >= L) r[k] -= L;
+        if (r[k] < 0.0) r[k] += L;
+      }
+    }
+    const double I[3] = {P.I[A], P.I[na + A], P.I[2 * na + A]};
+    const double N[3] = {P.NA[cur][A], P.NA[cur][na + A], P.NA[cur][2 * na + A]};
+    rk5_rotate(y, I, N, h);
+  }
+  double R[9], ws[3];
+  quat_rot(y, R);
+  rot_apply(R, &y[4], ws);
+  const double hh = (mode == kModeStep) ? 0.5 * h : 0.0;
+  for (int k = 0; k < 3; ++k) {
+    P.vA[nxt][k * na + A] = v[k];
+    P.rA[nxt][k * na + A] = r[k];
+    P.wA[k * na + A] = ws[k];
+    P.vpred[k * na + A] = v[k] + hh * a[k];
+    P.wb[nxt][k * na + A] = y[4 + k];
+  }
+  for (int k = 0; k < 4; ++k) P.q[nxt][k * na + A] = y[k];
+}
+
+// ---------------------------------------------------------------------------
+// member reconstruction (SetSpacePos / SetSpaceSpin / SetSpaceVel, Eq. 3)
+// ---------------------------------------------------------------------------
+
+// One thread per sphere: r_i = r_A + R b_i and v_i = vpred_A + w_A x (R b_i)
+// (a pile without aggregates keeps the positions it was given).  Each block
+// also writes the bounding box and mass moments of its spheres
+// for the per-pile cell grid.
+__global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restrict__ piles,
+                                                        const WorkItem* __restrict__ wl) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0) return;
+  const int i = w.base + threadIdx.x;
+  const int ns = P.ns, na = P.na, nxt = P.parity ^ 1;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double mom[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < ns && na == 0) {
+    // positions given directly (stateless contact search): bbox only
+    for (int k = 0; k < 3; ++k) {
+      const double x = P.r[k * ns + i];
+      lo[k] = x;
+      hi[k] = x;
+      mom[k + 1] = x;
+    }
+    mom[0] = 1.0;
+  } else if (i < ns) {
+    const int A = P.agg[i];
+    double q[4], R[9];
+    for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
+    quat_rot(q, R);
+    const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
+    double d[3], wxd[3];
+    rot_apply(R, bb, d);
+    const double wa[3] = {P.wA[A], P.wA[na + A], P.wA[2 * na + A]};
+    cross3(wa, d, wxd);
+    const double mi = P.m[i];
+    for (int k = 0; k < 3; ++k) {
+      const double x = P.rA[nxt][k * na + A] + d[k];
+      P.r[k * ns + i] = x;
+      P.v[k * ns + i] = P.vpred[k * na + A] + wxd[k];
+      lo[k] = x;
+      hi[k] = x;
+      mom[k + 1] = mi * x;
+    }
+    mom[0] = mi;
+  }
+  // block reduction (wave shuffles, then across the 4 waves through LDS)
+  __shared__ double red[4][10];
+  double vals[10] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], mom[0], mom[1], mom[2], mom[3]};
+  for (int off = 32; off > 0; off >>= 1) {
+    for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], __shfl_xor(vals[k], off));
+    for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
+    for (int k = 6; k < 10; ++k) vals[k] += __shfl_xor(vals[k], off);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+    for (int k = 0; k < 10; ++k) red[wave][k] = vals[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* out = P.bpart + (size_t)(w.base / kBlock) * 10;
+    for (int k = 0; k < 10; ++k) {
+      double x = red[0][k];
+      for (int j = 1; j < 4; ++j) {
+        const double y = red[j][k];
+        x = (k < 3) ? fmin(x, y) : (k < 6 ? fmax(x, y) : x + y);
+      }
+      out[k] = x;
+    }
+  }
+}
+
+// One block per pile: combine the block partials into the cell grid and the
+// pile's centre of mass.  Cells are at least one largest-sphere diameter;
+// an open pile's grid spans its bounding box with (1 << bits) cells per axis.
+__global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles) {
+  PileDev& P = piles[blockIdx.x];
+  if (P.status != 0) return;
+  double vals[10] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
+                     0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < P.n_rblk; b += kBlock) {
+    const double* p = P.bpart + (size_t)b * 10;
+    for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], p[k]);
+    for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], p[k]);
+    for (int k = 6; k < 10; ++k) vals[k] += p[k];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], __shfl_xor(vals[k], off));
+    for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
+    for (int k = 6; k < 10; ++k) vals[k] += __shfl_xor(vals[k], off);
+  }
+  __shared__ double red[4][10];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+    for (int k = 0; k < 10; ++k) red[wave][k] = vals[k];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 10; ++k) {
+    double x = red[0][k];
+    for (int j = 1; j < 4; ++j) {
+      const double y = red[j][k];
+      x = (k < 3) ? fmin(x, y) : (k < 6 ? fmax(x, y) : x + y);
+    }
+    vals[k] = x;
+  }
+  Grid g;
+  bool finite = true;
+  for (int k = 0; k < 10; ++k) finite = finite && isfinite(vals[k]);
+  if (!finite) {
+    atomicOr(&P.status, kStUnstable);
+    return;
+  }
+  if (P.periodic) {
+    g.nb = P.nb_periodic;
+    g.lo[0] = g.lo[1] = g.lo[2] = 0.0;
+    g.cell = P.box / (double)(1 << g.nb);
+  } else {
+    g.nb = P.bits;
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      g.lo[k] = vals[k];
+      ext = fmax(ext, vals[3 + k] - vals[k]);
+    }
+    const double fit = ext * (1.0 + 1e-12) / (double)(1 << g.nb) + 1e-300;
+    g.cell = fmax(P.cell_min, fit);
+  }
+  g.inv_cell = 1.0 / g.cell;
+  for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
+  g.pad = 0;
+  *P.grid = g;
+}
+
+// ---------------------------------------------------------------------------
+// GetAccelAndTorque (Eqs. 5-7, 9) and the closing half kick
+// ---------------------------------------------------------------------------
+
+// One thread per aggregate.  For each member sphere (in order): its contact
+// force and torque gathered in canonical contact order -- contacts (j, i)
+// with j < i by increasing j, then (i, j) by increasing j -- plus its
+// gravity G m_i sum_s partial_s.  Then F_A = sum F_i, a_A = F_A / M,
+// N_A = sum [ (R b_i) x F_i + tau_i ], and in step mode v_A += h/2 a_A
+// followed by the spin-up increment about +z through the pile's centre.
+__global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
+                                                   const WorkItem* __restrict__ wl,
+                                                   ContactParams cp, int mode) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  const int A = w.base + threadIdx.x;
+  if (A >= P.na || P.status != 0) return;
+  const int na = P.na, ns = P.ns, nxt = P.parity ^ 1;
+  const int cap = P.cap_pairs;
+  const uint32_t* __restrict__ up_off = P.up_off[nxt];
+  double q[4], R[9];
+  for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
+  quat_rot(q, R);
+  double FA[3] = {0.0, 0.0, 0.0}, NA[3] = {0.0, 0.0, 0.0};
+  const int i0 = P.first[A], n = P.count[A];
+  const bool grav = P.G != 0.0;
+  for (int i = i0; i < i0 + n; ++i) {
+    double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+    for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
+      const uint32_t p = P.lo_pair[e];
+      for (int k = 0; k < 3; ++k) {
+        f[k] -= P.pF[k * cap + p];
+        t[k] += P.pTj[k * cap + p];
+      }
+    }
+    for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
+      for (int k = 0; k < 3; ++k) {
+        f[k] += P.pF[k * cap + p];
+        t[k] += P.pTi[k * cap + p];
+      }
+    }
+    if (grav) {
+      const uint32_t sl = P.slot[i];
+      double g[3] = {0.0, 0.0, 0.0};
+      for (int sp = 0; sp < P.n_split; ++sp)
+        for (int k = 0; k < 3; ++k) g[k] += P.gpart[((size_t)sp * 3 + k) * ns + sl];
+      const double gm = P.G * P.m[i];
+      for (int k = 0; k < 3; ++k) f[k] += gm * g[k];
+    }
+    const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
+    double d[3], dxf[3];
+    rot_apply(R, bb, d);
+    cross3(d, f, dxf);
+    for (int k = 0; k < 3; ++k) {
+      P.F[k * ns + i] = f[k];
+      P.tau[k * ns + i] = t[k];
+      FA[k] += f[k];
+      NA[k] += dxf[k] + t[k];
+    }
+  }
+  const double M = P.M[A];
+  double a[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = FA[k] / M;
+    P.aA[nxt][k * na + A] = a[k];
+    P.NA[nxt][k * na + A] = NA[k];
+  }
+  if (mode == kModeStep) {
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = P.vA[nxt][k * na + A] + 0.5 * cp.dt * a[k];
+    if (P.spin_dw != 0.0) {
+      // spin-up: w += dw z-hat about the pile's centre of mass
+      const Grid g = *P.grid;
+      const double dw = P.spin_dw;
+      const double rel[3] = {P.rA[nxt][A] - g.com[0], P.rA[nxt][na + A] - g.com[1],
+                             P.rA[nxt][2 * na + A] - g.com[2]};
+      const double z[3] = {0.0, 0.0, dw};
+      double dv[3], dwb[3];
+      cross3(z, rel, dv);
+      for (int k = 0; k < 3; ++k) v[k] += dv[k];
+      rot_apply_T(R, z, dwb);
+      for (int k = 0; k < 3; ++k) P.wb[nxt][k * na + A] += dwb[k];
+    }
+    for (int k = 0; k < 3; ++k) P.vA[nxt][k * na + A] = v[k];
+  }
+}
+
+// One thread per pile: commit the step (flip the ping-pong halves) unless
+// the pile failed during it, in which case its state stays at the failing
+// step's start and the step index is recorded.
+__global__ void k_finish(PileDev* __restrict__ piles, int n_piles, int mode) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_piles) return;
+  PileDev& P = piles[p];
+  if (P.status != 0) {
+    if (P.fail_step < 0) P.fail_step = P.step;
+    return;
+  }
+  const int nxt = P.parity ^ 1;
+  P.n_pairs = P.up_off[nxt][P.ns];
+  P.parity = nxt;
+  if (mode == kModeStep) P.step += 1;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+}  // namespace
+
+void launch_setup(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                  const double* pos_in, const double* vel_in, const double* spin_in) {
+  hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(kBlock), 0, st, piles, wl, pos_in, vel_in, spin_in);
+}
+
+void launch_integrate(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                      ContactParams cp, int mode) {
+  hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode);
+}
+
+void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
+  hipLaunchKernelGGL(k_reconstruct, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+}
+
+void launch_grid(hipStream_t st, const PileDev* piles, int n_piles) {
+  hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles));
+}
+
+void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                   ContactParams cp, int mode) {
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode);
+}
+
+void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode) {
+  hipLaunchKernelGGL(k_finish, dim3((n_piles + 63) / 64), dim3(64), 0, st, piles, n_piles, mode);
+}
+
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                     p, value, n);
+}
+
+}  // namespace dem

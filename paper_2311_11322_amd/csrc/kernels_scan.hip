@@ -1,0 +1,109 @@
+// kernels_scan.hip -- batched exclusive prefix sum of uint32 arrays.
+//
+// Many independent segments (the cell counts and contact counts of every
+// pile) are scanned by the same three launches: per-chunk totals, a scan of
+// each segment's chunk totals (one block per segment), and the chunk-local
+// scans with their offsets.  out[n] of each segment receives its total.
+// Integer arithmetic, so the result does not depend on the order of work.
+#include "dem_internal.h"
+
+namespace dem {
+
+namespace {
+
+// Exclusive scan of one value per thread across a 256-thread block; returns
+// the exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const uint32_t s = wsum[k];
+    if (k < wave) before += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const ScanSeg* __restrict__ segs,
+                                                        const ScanItem* __restrict__ items,
+                                                        uint32_t* __restrict__ sums) {
+  const ScanItem it = items[blockIdx.x];
+  const ScanSeg sg = segs[it.seg];
+  const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + k;
+    if (e < sg.n) acc += sg.in[e];
+  }
+  uint32_t total;
+  block_exclusive(acc, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block per segment: exclusive scan of the segment's chunk totals in
+// place, and the segment total into out[n].
+__global__ __launch_bounds__(kBlock) void k_scan_chunks(const ScanSeg* __restrict__ segs,
+                                                        uint32_t* __restrict__ sums) {
+  const ScanSeg sg = segs[blockIdx.x];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < sg.n_items; c0 += kBlock) {
+    const int c = c0 + threadIdx.x;
+    const uint32_t v = c < sg.n_items ? sums[sg.item0 + c] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive(v, &total);
+    if (c < sg.n_items) sums[sg.item0 + c] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    uint32_t* out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
+    out[sg.n] = carry;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict__ segs,
+                                                      const ScanItem* __restrict__ items,
+                                                      const uint32_t* __restrict__ sums) {
+  const ScanItem it = items[blockIdx.x];
+  const ScanSeg sg = segs[it.seg];
+  uint32_t* __restrict__ out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
+  const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + k;
+    v[k] = e < sg.n ? sg.in[e] : 0u;
+    acc += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive(acc, &total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + k;
+    if (e < sg.n) out[e] = run;
+    run += v[k];
+  }
+}
+
+}  // namespace
+
+void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
+                 int n_items, uint32_t* item_sums) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(n_segs), dim3(kBlock), 0, st, segs, item_sums);
+  hipLaunchKernelGGL(k_scan_down, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
+}
+
+}  // namespace dem

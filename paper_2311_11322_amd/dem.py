@@ -1,0 +1,357 @@
+"""Thin ctypes binding of the C-ABI in ``include/dem.h`` (same names).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  PyTorch, when used, only provides device memory (through the
+library's allocator callback) and the HIP stream.  Importing this module
+loads ``libdem.so`` and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Iterable, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdem.so")
+
+DEM_OK = 0
+DEM_ERR_INVALID_ARG = -1
+DEM_ERR_OOM = -2
+DEM_ERR_CAPACITY = -3
+DEM_ERR_UNSTABLE = -4
+DEM_ERR_DEVICE = -5
+DEM_ERR_STATE = -6
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "CAPACITY", -4: "UNSTABLE",
+                -5: "DEVICE", -6: "STATE"}
+
+PREC_FP64 = 0
+PREC_FP32_FORCE = 1
+
+_PD = C.POINTER(C.c_double)
+_PU64 = C.POINTER(C.c_uint64)
+_PI32 = C.POINTER(C.c_int32)
+_PI64 = C.POINTER(C.c_int64)
+
+
+class DemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class dem_params(C.Structure):
+    _fields_ = [
+        ("dt", C.c_double), ("G", C.c_double), ("softening_frac", C.c_double),
+        ("k_n", C.c_double), ("k_t", C.c_double), ("eps_n", C.c_double), ("eps_t", C.c_double),
+        ("mu_s", C.c_double), ("mu_r", C.c_double), ("mu_t", C.c_double),
+        ("k_r", C.c_double), ("k_q", C.c_double),
+        ("periodic", C.c_int32), ("box", C.c_double * 3),
+        ("precision", C.c_int32), ("max_contacts_per_sphere", C.c_int32),
+        ("max_overlap_frac", C.c_double),
+    ]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class dem_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+class dem_forcing(C.Structure):
+    _fields_ = [("spin_dw", C.c_double)]
+
+
+class dem_state(C.Structure):
+    _fields_ = [(n, _PD) for n in ("agg_pos", "agg_vel", "agg_acc", "agg_torque", "agg_quat",
+                                  "agg_spin", "agg_spin_body", "agg_mass", "agg_inertia",
+                                  "sph_pos", "sph_vel", "sph_force", "sph_torque", "sph_body")] + [
+        ("pair_keys", _PU64), ("pair_hist", _PD), ("n_pairs", C.c_int64), ("step", C.c_int64)]
+
+
+_AGG_FIELDS = {"agg_pos": 3, "agg_vel": 3, "agg_acc": 3, "agg_torque": 3, "agg_quat": 4,
+               "agg_spin": 3, "agg_spin_body": 3, "agg_mass": 1, "agg_inertia": 3}
+_SPH_FIELDS = {"sph_pos": 3, "sph_vel": 3, "sph_force": 3, "sph_torque": 3, "sph_body": 3}
+
+_LIB = None
+
+
+def lib():
+    """The loaded HIP library.  Raises if it was never built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2311_11322_amd.build_lib` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.dem_create.argtypes = [C.POINTER(dem_params), C.POINTER(dem_allocator), vp, C.POINTER(vp)]
+        L.dem_add_aggregates.argtypes = [vp, C.c_int64, _PI32, _PD, _PD, _PD, _PD, _PD, _PI64]
+        L.dem_step.argtypes = [vp, C.c_int64]
+        L.dem_read_state.argtypes = [vp, C.POINTER(dem_state)]
+        L.dem_get_counts.argtypes = [vp, _PI64, _PI64, _PI64]
+        L.dem_set_forcing.argtypes = [vp, C.POINTER(dem_forcing)]
+        L.dem_restore_state.argtypes = [vp, C.POINTER(dem_state)]
+        L.dem_reserve_contacts.argtypes = [vp, C.c_int32]
+        L.dem_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64, _PI64]
+        L.dem_destroy.argtypes = [vp]
+        L.dem_last_error.argtypes = [vp]
+        L.dem_last_error.restype = C.c_char_p
+        L.dem_engine_create.argtypes = [C.c_size_t, vp, C.POINTER(vp)]
+        L.dem_engine_attach.argtypes = [vp, vp]
+        L.dem_engine_step.argtypes = [vp, C.c_int64]
+        L.dem_engine_detach.argtypes = [vp, vp]
+        L.dem_engine_destroy.argtypes = [vp]
+        L.dem_sim_status.argtypes = [vp]
+        L.dem_set_profiling.argtypes = [vp, C.c_int32]
+        L.dem_get_profile.argtypes = [vp, _PD, C.c_int32, _PI64]
+        L.dem_profile_names.restype = C.c_char_p
+        L.dem_footprint_bytes.argtypes = [C.POINTER(dem_params), C.c_int64, C.c_int64]
+        L.dem_footprint_bytes.restype = C.c_size_t
+        for name in ("dem_create", "dem_add_aggregates", "dem_step", "dem_read_state",
+                     "dem_get_counts", "dem_set_forcing", "dem_restore_state",
+                     "dem_reserve_contacts", "dem_find_contacts", "dem_destroy",
+                     "dem_engine_create", "dem_engine_attach", "dem_engine_step",
+                     "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
+                     "dem_set_profiling", "dem_get_profile"):
+            getattr(L, name).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, handle=None):
+    if code != DEM_OK:
+        msg = lib().dem_last_error(handle).decode()
+        raise DemError(code, msg)
+
+
+def _p(a, t=_PD):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def make_params(d: Dict, precision: int = PREC_FP64, max_contacts: int = 0,
+                max_overlap_frac: float = 0.0) -> dem_params:
+    p = dem_params()
+    p.dt = float(d["dt"])
+    p.G = float(d.get("G", 0.0))
+    p.softening_frac = float(d.get("soft_frac", d.get("softening_frac", 0.5)))
+    for k in ("k_n", "k_t", "eps_n", "eps_t", "mu_s", "mu_r", "mu_t"):
+        setattr(p, k, float(d[k]))
+    p.k_r = float(d.get("k_r", -1.0))
+    p.k_q = float(d.get("k_q", -1.0))
+    p.periodic = int(d.get("periodic", 0))
+    box = d.get("box", (0.0, 0.0, 0.0))
+    for c in range(3):
+        p.box[c] = float(box[c])
+    p.precision = int(d.get("precision", precision))
+    p.max_contacts_per_sphere = int(d.get("max_contacts_per_sphere", max_contacts))
+    p.max_overlap_frac = float(d.get("max_overlap_frac", max_overlap_frac))
+    return p
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self._alloc = _ALLOC_FN(self._do_alloc)
+        self._free = _FREE_FN(self._do_free)
+        self.struct = dem_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, ctx):
+        try:
+            return int(self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device))
+        except Exception:  # noqa: BLE001 - report OOM to the library as NULL
+            return None
+
+    def _do_free(self, ptr, ctx):
+        self._torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def torch_stream():
+    """The HIP stream handle of torch's current stream on cuda:0."""
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Sim:
+    """One system (a pile of rigid aggregates) held on the device."""
+
+    def __init__(self, params: Dict, precision: int = PREC_FP64, max_contacts: int = 0,
+                 max_overlap_frac: float = 0.0, allocator: Optional[TorchAllocator] = None,
+                 stream=None):
+        self.params = make_params(params, precision, max_contacts, max_overlap_frac)
+        self._allocator = allocator
+        h = C.c_void_p()
+        _check(lib().dem_create(C.byref(self.params),
+                                C.byref(allocator.struct) if allocator else None,
+                                stream, C.byref(h)))
+        self.h = h
+        self.n_agg = 0
+        self.n_sph = 0
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().dem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def add_aggregates(self, counts, pos, radius, mass, agg_vel=None, agg_spin=None):
+        counts = np.ascontiguousarray(counts, dtype=np.int32)
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        radius = np.ascontiguousarray(radius, dtype=np.float64)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        v = None if agg_vel is None else np.ascontiguousarray(agg_vel, dtype=np.float64)
+        w = None if agg_spin is None else np.ascontiguousarray(agg_spin, dtype=np.float64)
+        first = C.c_int64()
+        _check(lib().dem_add_aggregates(self.h, counts.shape[0], _p(counts, _PI32), _p(pos),
+                                        _p(radius), _p(mass), _p(v), _p(w), C.byref(first)),
+               self.h)
+        self.n_agg = int(counts.shape[0])
+        self.n_sph = int(radius.shape[0])
+        return self
+
+    def add_workload(self, w):
+        return self.add_aggregates(w.counts, w.pos, w.radius, w.mass, w.agg_vel, w.agg_spin)
+
+    def step(self, n: int = 1):
+        _check(lib().dem_step(self.h, int(n)), self.h)
+
+    def counts(self):
+        a, s, p = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().dem_get_counts(self.h, C.byref(a), C.byref(s), C.byref(p)), self.h)
+        return a.value, s.value, p.value
+
+    def read_state(self, fields: Optional[Iterable[str]] = None, pairs: bool = False) -> Dict:
+        na, ns, np_ = self.counts()
+        names = list(_AGG_FIELDS) + list(_SPH_FIELDS) if fields is None else list(fields)
+        st = dem_state()
+        out = {}
+        for n in names:
+            if n in _AGG_FIELDS:
+                k = _AGG_FIELDS[n]
+                a = np.zeros((na, k) if k > 1 else na)
+            else:
+                a = np.zeros((ns, _SPH_FIELDS[n]))
+            out[n] = a
+            setattr(st, n, _p(a))
+        if pairs:
+            keys = np.zeros(max(np_, 1), dtype=np.uint64)
+            hist = np.zeros((max(np_, 1), 7))
+            st.pair_keys = _p(keys, _PU64)
+            st.pair_hist = _p(hist)
+        _check(lib().dem_read_state(self.h, C.byref(st)), self.h)
+        if pairs:
+            out["pair_keys"] = keys[:st.n_pairs].copy()
+            out["pair_hist"] = hist[:st.n_pairs].copy()
+        out["n_pairs"] = int(st.n_pairs)
+        out["step"] = int(st.step)
+        return out
+
+    def checkpoint(self) -> Dict:
+        return self.read_state(["agg_pos", "agg_vel", "agg_acc", "agg_torque", "agg_quat",
+                                "agg_spin_body"], pairs=True)
+
+    def restore(self, ck: Dict):
+        st = dem_state()
+        keep = {}
+        for n in ("agg_pos", "agg_vel", "agg_acc", "agg_torque", "agg_quat", "agg_spin_body"):
+            a = np.ascontiguousarray(ck[n], dtype=np.float64)
+            keep[n] = a
+            setattr(st, n, _p(a))
+        keys = np.ascontiguousarray(ck["pair_keys"], dtype=np.uint64)
+        hist = np.ascontiguousarray(ck["pair_hist"], dtype=np.float64)
+        st.pair_keys = _p(keys, _PU64)
+        st.pair_hist = _p(hist)
+        st.n_pairs = int(keys.shape[0])
+        st.step = int(ck.get("step", 0))
+        _check(lib().dem_restore_state(self.h, C.byref(st)), self.h)
+
+    def set_forcing(self, spin_dw: float):
+        f = dem_forcing(float(spin_dw))
+        _check(lib().dem_set_forcing(self.h, C.byref(f)), self.h)
+
+    def reserve_contacts(self, per_sphere: int):
+        _check(lib().dem_reserve_contacts(self.h, int(per_sphere)), self.h)
+
+    def status(self) -> int:
+        return int(lib().dem_sim_status(self.h))
+
+    def set_profiling(self, on: bool):
+        _check(lib().dem_set_profiling(self.h, int(bool(on))), self.h)
+
+    def profile(self) -> Dict[str, float]:
+        """Accumulated per-kernel milliseconds and the steps they cover."""
+        names = lib().dem_profile_names().decode().split(";")
+        ms = np.zeros(len(names))
+        n = C.c_int64()
+        _check(lib().dem_get_profile(self.h, _p(ms), len(names), C.byref(n)), self.h)
+        out = dict(zip(names, ms.tolist()))
+        out["_steps"] = int(n.value)
+        return out
+
+
+class Engine:
+    """Steps many systems together (one graph per step covering all)."""
+
+    def __init__(self, hbm_budget_bytes: int, stream=None):
+        h = C.c_void_p()
+        _check(lib().dem_engine_create(int(hbm_budget_bytes), stream, C.byref(h)))
+        self.h = h
+        self.sims = []
+
+    def attach(self, sim: Sim):
+        _check(lib().dem_engine_attach(self.h, sim.h), sim.h)
+        self.sims.append(sim)
+
+    def detach(self, sim: Sim):
+        _check(lib().dem_engine_detach(self.h, sim.h), sim.h)
+        self.sims.remove(sim)
+
+    def step(self, n: int = 1) -> int:
+        """Advance every attached system; returns the first failure code
+        (failed systems stop, the rest continue)."""
+        return int(lib().dem_engine_step(self.h, int(n)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().dem_engine_destroy(self.h)
+            self.h = C.c_void_p()
+            self.sims = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def find_contacts(pos, radius, agg, box=None) -> np.ndarray:
+    """Device contact search (stateless); canonical keys (i << 32 | j)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    n = radius.shape[0]
+    bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    cap = 64 * n
+    keys = np.zeros(cap, dtype=np.uint64)
+    nout = C.c_int64()
+    _check(lib().dem_find_contacts(_p(pos), _p(radius), _p(agg, _PI32), n, _p(bx),
+                                   _p(keys, _PU64), cap, C.byref(nout)))
+    return keys[:nout.value].copy()
+
+
+def footprint_bytes(params: Dict, n_agg: int, n_sph: int, precision: int = PREC_FP64,
+                    max_contacts: int = 0) -> int:
+    p = make_params(params, precision, max_contacts)
+    return int(lib().dem_footprint_bytes(C.byref(p), int(n_agg), int(n_sph)))

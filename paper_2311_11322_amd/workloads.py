@@ -228,7 +228,8 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
            near_after=200):
     """Random sequential addition of whole aggregates (largest first).
 
-    container: ("ball", R) or ("box", L).  If ``contact_seeded`` every
+    container: ("ball", R): aggregate centres uniform in the ball; or
+    ("box", L): centres uniform in the periodic cube.  If ``contact_seeded`` every
     aggregate after the first is put in contact, with overlap drawn from
     U[1e-5, 1e-3], with a sphere of an already-placed aggregate.  Otherwise,
     once ``near_after`` uniform draws for one aggregate have failed (close to
@@ -249,7 +250,6 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
     for n_done, a in enumerate(order):
         rel, rad = clusters[a]
         rel = rel - rel.mean(axis=0)
-        ext = np.linalg.norm(rel, axis=1).max() + rad.max()
         for tries in range(max_tries):
             rot = _random_rotation(rng)
             body = rel @ rot.T
@@ -274,12 +274,12 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
                     centre = rng.uniform(0.0, L, 3)
                 else:
                     v = _unit_vectors(rng, 1)[0]
-                    centre = v * (R - ext) * rng.uniform() ** (1.0 / 3.0)
+                    centre = v * R * rng.uniform() ** (1.0 / 3.0)
             if kind == "box":
                 # keep the aggregate whole; only its centre is wrapped
                 centre = np.mod(centre, L)
-            elif np.linalg.norm(centre) + ext > R:
-                continue
+            elif np.linalg.norm(centre) > R:
+                continue        # centres of mass uniform in the ball
             p = centre + body
             gap, nb = grid.gaps(p, rad)
             if gap.size:
@@ -368,7 +368,7 @@ def collapse_cloud(seed: int = 1, n_agg: int = 25000, cmin: int = 2, cmax: int =
 
 
 def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 20000,
-               cmin: int = 1, cmax: int = 8, phi0: float = 0.3, dt: float = 5e-4,
+               cmin: int = 1, cmax: int = 8, phi0: float = 0.2, dt: float = 5e-4,
                n_steps: int = 800, spin_rate_per_step2: float = 1e-6,
                G: float = 1.0, soft_frac: float = 0.5) -> List[Workload]:
     """Independent piles with log-uniform sphere counts in [nmin, nmax].
