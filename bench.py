@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -76,6 +78,17 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # a plain copy kernel of known size, for scaling the HBM byte counters
+        x = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": args.calibrate_copy, "copies": 3}))
+        return
     from paper_2311_11322_amd import dem
     from paper_2311_11322_amd import workloads as W
 

@@ -56,22 +56,15 @@ int ceil_log2(uint64_t v) {
 
 // Device footprint of one system, byte for byte what alloc_pile allocates.
 struct Sizes {
-  int64_t na, ns, cap, cells, n_split, n_rblk;
+  int64_t na, ns, cap, cells, g_tile, g_nt, n_rblk;
   bool grav;
+  int precision;
 };
 
 int choose_bits(int64_t ns) {
   // at least two cells per sphere, 2..10 bits per axis
   int b = (ceil_log2(uint64_t(2 * ns)) + 2) / 3;
   return std::min(10, std::max(2, b));
-}
-
-int choose_split(int64_t ns, int precision) {
-  const int ipt = gravity_ipt(precision);
-  const int64_t iblk = (ns + int64_t(kBlock) * ipt - 1) / (int64_t(kBlock) * ipt);
-  int64_t s = (4096 + iblk - 1) / iblk;           // aim at >= 4096 blocks
-  s = std::min<int64_t>(s, std::max<int64_t>(1, ns / 256));   // >= 256 sources each
-  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
 }
 
 Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max) {
@@ -81,7 +74,9 @@ Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max) {
   z.cap = int64_t(c_max) * ns;
   z.cells = int64_t(1) << (3 * choose_bits(ns));
   z.grav = p.G != 0.0;
-  z.n_split = z.grav ? choose_split(ns, p.precision) : 1;
+  z.precision = p.precision;
+  z.g_tile = gravity_tile(p.precision);
+  z.g_nt = (ns + z.g_tile - 1) / z.g_tile;
   z.n_rblk = (ns + kBlock - 1) / kBlock;
   return z;
 }
@@ -129,8 +124,12 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.xs, 4 * ns);
   L.add(&h.sagg, ns);
   if (z.grav) {
+    // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
+    const int64_t part_vals = z.g_nt * 3 * ns;
     L.add(reinterpret_cast<double**>(&h.jrec), 8 * ns);
-    L.add(&h.gpart, 3 * ns * z.n_split);
+    L.add(&h.ganchor, 4 * z.g_nt);
+    L.add(reinterpret_cast<double**>(&h.gpart), z.precision == 1 ? (part_vals + 1) / 2 : part_vals);
+    L.add(&h.gacc, 3 * ns);
   }
   L.add(&h.bpart, 10 * z.n_rblk);
   L.add(&h.grid, 1);
@@ -277,14 +276,9 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
     if (h.G != 0.0) {
       b.any_grav = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
-      const int ipt = gravity_ipt(s->prm.precision);
-      const int tile = kBlock * ipt;
-      const int ns = h.ns;
-      for (int sp_i = 0; sp_i < h.n_split; ++sp_i) {
-        const int j0 = int(int64_t(ns) * sp_i / h.n_split);
-        const int j1 = int(int64_t(ns) * (sp_i + 1) / h.n_split);
-        for (int i = 0; i < ns; i += tile) gl.push_back({p, i, j0, j1, sp_i, 0});
-      }
+      // every tile pair (ti <= tj) of the pile: each unordered pair once
+      for (int ti = 0; ti < h.g_nt; ++ti)
+        for (int tj = ti; tj < h.g_nt; ++tj) gl.push_back({p, ti, tj, 0});
     }
     // cell-count scan of this pile
     auto add_seg = [](std::vector<ScanSeg>& segs, std::vector<ScanItem>& items, const uint32_t* in,
@@ -362,7 +356,8 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(11);
   launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   mark(12);
-  if (b.any_grav) launch_gravity(st, b.d_table, b.gl, b.n_grav, b.precision, b.all_soft);
+  if (b.any_grav)
+    launch_gravity(st, b.d_table, b.wl_sph, b.n_sph_blk, b.gl, b.n_grav, b.precision, b.all_soft);
   mark(13);
   launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
   mark(14);
@@ -461,7 +456,8 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.cap_pairs = (int32_t)s->sz.cap;
   h.bits = choose_bits(ns);
   h.periodic = s->prm.periodic ? 1 : 0;
-  h.n_split = (int32_t)s->sz.n_split;
+  h.g_tile = (int32_t)s->sz.g_tile;
+  h.g_nt = (int32_t)s->sz.g_nt;
   h.n_rblk = (int32_t)s->sz.n_rblk;
   h.box = s->prm.box[0];
   h.G = s->prm.G;

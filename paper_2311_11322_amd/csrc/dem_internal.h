@@ -51,7 +51,8 @@ struct PileDev {
   int32_t cap_pairs;         // capacity of each contact list (upper and lower)
   int32_t bits;              // cell table is (1 << bits)^3 Morton codes
   int32_t periodic;
-  int32_t n_split;           // gravity j-splits
+  int32_t g_tile;            // gravity tile (slots per tile)
+  int32_t g_nt;              // gravity tiles
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
   int32_t nb_periodic;       // cells per axis = 1 << nb_periodic for a periodic pile
   double box;                // periodic cube side
@@ -96,8 +97,10 @@ struct PileDev {
   uint32_t* slot;            // [ns] sorted slot of sphere
   double* xs;                // [4][ns] sorted x, y, z, radius
   int32_t* sagg;             // [ns] sorted aggregate id
-  void* jrec;                // gravity source records in sorted order
-  double* gpart;             // [n_split][3][ns] gravity partial sums (sorted slots)
+  void* jrec;                // gravity records in sorted order (64 B FP64 / 32 B FP32)
+  double* ganchor;           // [g_nt][4] FP64 anchor of each tile (relative coordinates)
+  void* gpart;               // [g_nt][3][ns] per-tile partial sums (sorted slots)
+  double* gacc;              // [3][ns] gravity force G m_i sum_j (by sphere id)
   double* bpart;             // [n_rblk][10] bbox min/max + mass moments
   Grid* grid;
   uint32_t* cell_cnt;        // [cells]
@@ -121,12 +124,10 @@ struct WorkItem {
   int32_t base;
 };
 
-// One block of the gravity kernel.
+// One block of the gravity kernel: the tile pair (ti, tj), ti <= tj, of a pile.
 struct GravItem {
   int32_t pile;
-  int32_t ibase;             // first target slot
-  int32_t j0, j1;            // source slots [j0, j1)
-  int32_t split;
+  int32_t ti, tj;
   int32_t pad;
 };
 
@@ -164,9 +165,9 @@ void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
 void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                   ContactParams cp, int precision);
-void launch_gravity(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
-                    int precision, bool softened);
-int gravity_ipt(int precision);
+void launch_gravity(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                    const GravItem* gl, int nitems, int precision, bool softened);
+int gravity_tile(int precision);
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode);

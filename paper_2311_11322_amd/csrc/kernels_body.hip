@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles) {
 // One thread per aggregate.  For each member sphere (in order): its contact
 // force and torque gathered in canonical contact order -- contacts (j, i)
 // with j < i by increasing j, then (i, j) by increasing j -- plus its
-// gravity G m_i sum_s partial_s.  Then F_A = sum F_i, a_A = F_A / M,
+// gravity force.  Then F_A = sum F_i, a_A = F_A / M,
 // N_A = sum [ (R b_i) x F_i + tau_i ], and in step mode v_A += h/2 a_A
 // followed by the spin-up increment about +z through the pile's centre.
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
@@ -434,14 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
         t[k] += P.pTi[k * cap + p];
       }
     }
-    if (grav) {
-      const uint32_t sl = P.slot[i];
-      double g[3] = {0.0, 0.0, 0.0};
-      for (int sp = 0; sp < P.n_split; ++sp)
-        for (int k = 0; k < 3; ++k) g[k] += P.gpart[((size_t)sp * 3 + k) * ns + sl];
-      const double gm = P.G * P.m[i];
-      for (int k = 0; k < 3; ++k) f[k] += gm * g[k];
-    }
+    if (grav)
+      for (int k = 0; k < 3; ++k) f[k] += P.gacc[k * ns + i];
     const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
     double d[3], dxf[3];
     rot_apply(R, bb, d);

@@ -77,8 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict_
 }
 
 // Sorted copies of positions, radii and aggregate ids (spatially coherent
-// reads in the search), the inverse permutation, and the gravity source
-// records (x, y, z, m, eps_j) in sorted order.
+// reads in the search and in gravity) and the inverse permutation.
 __global__ __launch_bounds__(kBlock) void k_sorted_copy(const PileDev* __restrict__ piles,
                                                         const WorkItem* __restrict__ wl) {
   const WorkItem w = wl[blockIdx.x];
@@ -94,17 +93,6 @@ __global__ __launch_bounds__(kBlock) void k_sorted_copy(const PileDev* __restric
   P.xs[2 * ns + k] = z;
   P.xs[3 * ns + k] = s;
   P.sagg[k] = P.agg[i];
-  if (P.G != 0.0) {
-    double* rec = (double*)P.jrec + (size_t)k * 8;
-    rec[0] = x;
-    rec[1] = y;
-    rec[2] = z;
-    rec[3] = P.m[i];
-    rec[4] = 0.5 * P.soft_frac * s;
-    rec[5] = 0.0;
-    rec[6] = 0.0;
-    rec[7] = 0.0;
-  }
 }
 
 // Contact test exactly as written d^2 = (dx*dx + dy*dy) + dz*dz < S*S, each

@@ -1,100 +1,314 @@
 // kernels_gravity.hip -- softened all-pairs self-gravity (Eq. 4 of the
 // paper, with Plummer softening eps_ij = soft_frac (s_i + s_j) / 2).
 //
-// The sum runs over spheres in cell-sorted order.  Each block owns up to
-// IPT*256 consecutive target slots and one contiguous range of source slots
-// (a j-split); every lane keeps IPT targets in registers.  The source loop
-// index is uniform across the block, so source records are fetched with
-// scalar loads and broadcast to the lanes from SGPRs (no LDS traffic).
-// Each split writes its partial acceleration sum sum_j m_j d_ij / r^3; the
-// aggregate reduction adds the splits in a fixed order and multiplies by
-// G m_i, so the result is deterministic.
+// Spheres are taken in cell-sorted (Morton) order and cut into tiles of B
+// slots.  One wave computes one tile pair (I, J), I <= J, so every unordered
+// pair of spheres is evaluated once (Newton's third law):
+//  * each lane holds IPT targets of tile I in registers;
+//  * the sources of tile J enter 64 at a time, one per lane, together with
+//    a reaction accumulator, and rotate one lane per step (DPP wave_ror:1)
+//    so that after 64 steps every source has met every target of the wave
+//    and is back in its own lane holding its complete reaction sum;
+//  * a diagonal pair (I, I) evaluates the ordered pairs i != j one way only,
+//    with the sources walked by a uniform index (scalar loads).
+// Each sphere receives exactly one partial sum per tile (its own tile's row
+// or column), stored per tile; the combine kernel adds them in tile order,
+// so the result is deterministic and independent of other piles.
 //
-// FP64 form: the reciprocal square root comes from the hardware estimate
-// refined by one third-order step y (1 + e/2 + 3e^2/8), e = 1 - r^2 y^2,
-// which brings it to full double precision.
+// FP64 form: rsqrt from the hardware estimate y0 and one third-order
+// correction folded into the cube: r^-3 = y0^3 (1 + 3e/2 + 15e^2/8),
+// e = 1 - r^2 y0^2.  FP32-force form: coordinates relative to an FP64 anchor
+// per tile (the first sphere of the tile); the tile-pair anchor offset is
+// formed in FP64 once per block; FP32 partial sums per tile, FP64 across
+// tiles.
 #include "dem_internal.h"
 
 namespace dem {
 
 namespace {
 
+constexpr int kIptF64 = 4;
+constexpr int kIptF32 = 8;
+
 struct alignas(64) Rec64 {
   double x, y, z, m, e, p0, p1, p2;
 };
+struct alignas(32) Rec32 {
+  float x, y, z, m, e, p0, p1, p2;
+};
 
-// Source records are read through the constant address space: the loop
-// index is uniform, so these become scalar loads into SGPRs.
+// Records are read through the constant address space: with a uniform index
+// these become scalar loads into SGPRs.
 typedef const __attribute__((address_space(4))) Rec64* ConstRec64;
+typedef const __attribute__((address_space(4))) Rec32* ConstRec32;
 
-__device__ __forceinline__ double rsqrt_f64(double r2) {
-  const double y = __builtin_amdgcn_rsq(r2);
-  const double e = fma(-r2, y * y, 1.0);
-  const double p = fma(e, 0.375, 0.5);
-  return fma(y * e, p, y);
+// One thread per sorted slot: the source record of the sphere in that slot.
+__global__ __launch_bounds__(kBlock) void k_grav_records(const PileDev* __restrict__ piles,
+                                                         const WorkItem* __restrict__ wl,
+                                                         int precision) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  const int k = w.base + threadIdx.x;
+  if (k >= P.ns || P.status != 0 || P.G == 0.0) return;
+  const int ns = P.ns;
+  const double x = P.xs[k], y = P.xs[ns + k], z = P.xs[2 * ns + k];
+  const double e = 0.5 * P.soft_frac * P.xs[3 * ns + k];
+  const double m = P.m[P.sidx[k]];
+  if (precision == 1) {
+    const int a = (k / P.g_tile) * P.g_tile;
+    const double ax = P.xs[a], ay = P.xs[ns + a], az = P.xs[2 * ns + a];
+    Rec32 r;
+    r.x = (float)(x - ax);
+    r.y = (float)(y - ay);
+    r.z = (float)(z - az);
+    r.m = (float)m;
+    r.e = (float)e;
+    r.p0 = r.p1 = r.p2 = 0.f;
+    ((Rec32*)P.jrec)[k] = r;
+    if (k == a) {
+      double* an = P.ganchor + (size_t)(k / P.g_tile) * 4;
+      an[0] = ax;
+      an[1] = ay;
+      an[2] = az;
+      an[3] = 0.0;
+    }
+  } else {
+    Rec64 r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.m = m;
+    r.e = e;
+    r.p0 = r.p1 = r.p2 = 0.0;
+    ((Rec64*)P.jrec)[k] = r;
+  }
 }
 
-template <int IPT, bool SOFT>
-__global__ __launch_bounds__(kBlock) void k_gravity64(const PileDev* __restrict__ piles,
-                                                      const GravItem* __restrict__ gl) {
+// Rotate a value by one lane across the whole wave (DPP wave_ror:1): after
+// 64 rotations every value is back in its own lane.
+__device__ __forceinline__ float ror1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double ror1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x13C, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x13C, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Series coefficients of the rsqrt correction, read from memory so that the
+// compiler keeps them in registers instead of re-materialising literals.
+__constant__ double kSeries[2] = {1.5, 1.875};
+
+// r^-3 of a softened squared distance, FP64.
+template <bool SOFT>
+__device__ __forceinline__ double inv_cube(double r2, double c15, double c1875) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double p = fma(e, c1875, c15);
+  const double y3 = y2 * y;
+  const double c3 = fma(y3 * e, p, y3);
+  if (!SOFT) return r2 > 0.0 ? c3 : 0.0;
+  return c3;
+}
+
+template <bool SOFT>
+__device__ __forceinline__ float inv_cube(float r2, double, double) {
+  const float y = __builtin_amdgcn_rsqf(r2);
+  const float c3 = (y * y) * y;
+  if (!SOFT) return r2 > 0.f ? c3 : 0.f;
+  return c3;
+}
+
+template <typename T, int IPT, bool SOFT>
+__global__ __launch_bounds__(64) void k_grav_tiles(const PileDev* __restrict__ piles,
+                                                   const GravItem* __restrict__ gl) {
+  constexpr int B = 64 * IPT;
+  constexpr bool F32 = sizeof(T) == 4;
   const GravItem it = gl[blockIdx.x];
   const PileDev& P = piles[it.pile];
   if (P.status != 0) return;
-  const int ns = P.ns;
-  const Rec64* __restrict__ rec = (const Rec64*)P.jrec;
-  ConstRec64 crec = (ConstRec64)P.jrec;
-  double xi[IPT], yi[IPT], zi[IPT], ei[IPT], ax[IPT], ay[IPT], az[IPT];
+  const int ns = P.ns, lane = threadIdx.x;
+  const int i0 = it.ti * B, j0 = it.tj * B;
+  const int j1 = min(j0 + B, ns);
+  const bool diag = it.ti == it.tj;
+  const double c15 = kSeries[0], c1875 = kSeries[1];
+
+  // tile-pair anchor offset (FP32 form): d = (x_j - A_J) - ((x_i - A_I) - (A_J - A_I))
+  T sx = 0, sy = 0, sz = 0;
+  if (F32) {
+    const double* aI = P.ganchor + (size_t)it.ti * 4;
+    const double* aJ = P.ganchor + (size_t)it.tj * 4;
+    sx = (T)(aJ[0] - aI[0]);
+    sy = (T)(aJ[1] - aI[1]);
+    sz = (T)(aJ[2] - aI[2]);
+  }
+
+  T xi[IPT], yi[IPT], zi[IPT], ei[IPT], mi[IPT], ax[IPT], ay[IPT], az[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    const int k = it.ibase + u * kBlock + threadIdx.x;
+    const int k = i0 + u * 64 + lane;
     const int kk = k < ns ? k : ns - 1;
-    xi[u] = rec[kk].x;
-    yi[u] = rec[kk].y;
-    zi[u] = rec[kk].z;
-    ei[u] = rec[kk].e;
-    ax[u] = ay[u] = az[u] = 0.0;
+    if (F32) {
+      const Rec32 r = ((const Rec32*)P.jrec)[kk];
+      xi[u] = (T)r.x - sx;
+      yi[u] = (T)r.y - sy;
+      zi[u] = (T)r.z - sz;
+      ei[u] = (T)r.e;
+      mi[u] = k < ns ? (T)r.m : (T)0;
+    } else {
+      const Rec64 r = ((const Rec64*)P.jrec)[kk];
+      xi[u] = (T)r.x;
+      yi[u] = (T)r.y;
+      zi[u] = (T)r.z;
+      ei[u] = (T)r.e;
+      mi[u] = k < ns ? (T)r.m : (T)0;
+    }
+    ax[u] = ay[u] = az[u] = (T)0;
   }
-  const int j1 = it.j1;
-#pragma unroll 2
-  for (int j = it.j0; j < j1; ++j) {
-    const double xj = crec[j].x, yj = crec[j].y, zj = crec[j].z, mj = crec[j].m, ej = crec[j].e;
+
+  T* __restrict__ part = (T*)P.gpart;
+  if (diag) {
+    // ordered pairs inside one tile, one way only; sources via scalar loads
+    for (int j = j0; j < j1; ++j) {
+      T xj, yj, zj, mj, ej;
+      if (F32) {
+        const ConstRec32 cr = (ConstRec32)P.jrec;
+        xj = cr[j].x;
+        yj = cr[j].y;
+        zj = cr[j].z;
+        mj = cr[j].m;
+        ej = cr[j].e;
+      } else {
+        const ConstRec64 cr = (ConstRec64)P.jrec;
+        xj = (T)cr[j].x;
+        yj = (T)cr[j].y;
+        zj = (T)cr[j].z;
+        mj = (T)cr[j].m;
+        ej = (T)cr[j].e;
+      }
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const double dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
-      const double t = ei[u] + ej;
-      const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
-      double inv = rsqrt_f64(r2);
-      if (!SOFT) inv = r2 > 0.0 ? inv : 0.0;
-      const double w = (mj * inv) * (inv * inv);
-      ax[u] = fma(w, dx, ax[u]);
-      ay[u] = fma(w, dy, ay[u]);
-      az[u] = fma(w, dz, az[u]);
+      for (int u = 0; u < IPT; ++u) {
+        const T dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+        const T t = ei[u] + ej;
+        const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
+        const T w = mj * inv_cube<SOFT>(r2, c15, c1875);
+        ax[u] = fma(w, dx, ax[u]);
+        ay[u] = fma(w, dy, ay[u]);
+        az[u] = fma(w, dz, az[u]);
+      }
+    }
+  } else {
+    // sources of tile J travel around the wave 64 at a time, each carrying
+    // its own reaction sum; after 64 one-lane rotations it is back home
+    for (int jc = j0; jc < j1; jc += 64) {
+      const int jx = jc + lane;
+      const int jk = jx < j1 ? jx : j1 - 1;
+      T xj, yj, zj, mj, ej;
+      if (F32) {
+        const Rec32 r = ((const Rec32*)P.jrec)[jk];
+        xj = r.x;
+        yj = r.y;
+        zj = r.z;
+        mj = jx < j1 ? r.m : 0.f;
+        ej = r.e;
+      } else {
+        const Rec64 r = ((const Rec64*)P.jrec)[jk];
+        xj = (T)r.x;
+        yj = (T)r.y;
+        zj = (T)r.z;
+        mj = jx < j1 ? (T)r.m : (T)0;
+        ej = (T)r.e;
+      }
+      T bx = 0, by = 0, bz = 0;
+      for (int step = 0; step < 64; ++step) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+          const T dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          const T t = ei[u] + ej;
+          const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
+          const T c3 = inv_cube<SOFT>(r2, c15, c1875);
+          const T wi = mj * c3, wj = mi[u] * c3;
+          ax[u] = fma(wi, dx, ax[u]);
+          ay[u] = fma(wi, dy, ay[u]);
+          az[u] = fma(wi, dz, az[u]);
+          bx = fma(wj, dx, bx);
+          by = fma(wj, dy, by);
+          bz = fma(wj, dz, bz);
+        }
+        xj = ror1(xj);
+        yj = ror1(yj);
+        zj = ror1(zj);
+        mj = ror1(mj);
+        ej = ror1(ej);
+        bx = ror1(bx);
+        by = ror1(by);
+        bz = ror1(bz);
+      }
+      if (jx < j1) {
+        part[((size_t)it.ti * 3 + 0) * ns + jx] = -bx;
+        part[((size_t)it.ti * 3 + 1) * ns + jx] = -by;
+        part[((size_t)it.ti * 3 + 2) * ns + jx] = -bz;
+      }
     }
   }
-  double* __restrict__ out = P.gpart + (size_t)it.split * 3 * ns;
+  // targets of tile I store under "other tile" J (J = I on the diagonal)
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    const int k = it.ibase + u * kBlock + threadIdx.x;
+    const int k = i0 + u * 64 + lane;
     if (k < ns) {
-      out[k] = ax[u];
-      out[ns + k] = ay[u];
-      out[2 * ns + k] = az[u];
+      part[((size_t)it.tj * 3 + 0) * ns + k] = ax[u];
+      part[((size_t)it.tj * 3 + 1) * ns + k] = ay[u];
+      part[((size_t)it.tj * 3 + 2) * ns + k] = az[u];
     }
   }
+}
+
+// One thread per sorted slot: add the per-tile partials in tile order (FP64)
+// and store the gravity force G m_i sum under the sphere's id.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restrict__ piles,
+                                                         const WorkItem* __restrict__ wl) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  const int k = w.base + threadIdx.x;
+  if (k >= P.ns || P.status != 0 || P.G == 0.0) return;
+  const int ns = P.ns, nt = P.g_nt;
+  const T* __restrict__ part = (const T*)P.gpart;
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int t = 0; t < nt; ++t)
+    for (int c = 0; c < 3; ++c) g[c] += (double)part[((size_t)t * 3 + c) * ns + k];
+  const uint32_t i = P.sidx[k];
+  const double gm = P.G * P.m[i];
+  for (int c = 0; c < 3; ++c) P.gacc[c * ns + i] = gm * g[c];
 }
 
 }  // namespace
 
-// Targets per lane of the gravity kernel (the host sizes its work list with it).
-int gravity_ipt(int precision) { return 2; }
+int gravity_tile(int precision) { return 64 * (precision == 1 ? kIptF32 : kIptF64); }
 
-void launch_gravity(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
-                    int precision, bool softened) {
+void launch_gravity(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                    const GravItem* gl, int nitems, int precision, bool softened) {
   if (nitems <= 0) return;
-  if (softened)
-    hipLaunchKernelGGL((k_gravity64<2, true>), dim3(nitems), dim3(kBlock), 0, st, piles, gl);
-  else
-    hipLaunchKernelGGL((k_gravity64<2, false>), dim3(nitems), dim3(kBlock), 0, st, piles, gl);
+  hipLaunchKernelGGL(k_grav_records, dim3(nblk), dim3(kBlock), 0, st, piles, wl, precision);
+  if (precision == 1) {
+    if (softened)
+      hipLaunchKernelGGL((k_grav_tiles<float, kIptF32, true>), dim3(nitems), dim3(64), 0, st,
+                         piles, gl);
+    else
+      hipLaunchKernelGGL((k_grav_tiles<float, kIptF32, false>), dim3(nitems), dim3(64), 0, st,
+                         piles, gl);
+    hipLaunchKernelGGL(k_grav_combine<float>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+  } else {
+    if (softened)
+      hipLaunchKernelGGL((k_grav_tiles<double, kIptF64, true>), dim3(nitems), dim3(64), 0, st,
+                         piles, gl);
+    else
+      hipLaunchKernelGGL((k_grav_tiles<double, kIptF64, false>), dim3(nitems), dim3(64), 0, st,
+                         piles, gl);
+    hipLaunchKernelGGL(k_grav_combine<double>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+  }
 }
 
 }  // namespace dem
