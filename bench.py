@@ -31,6 +31,23 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}     # MI355X vector peaks
 GRAVITY_FLOP_PER_PAIR = 20                      # 3 sub, 3 fma, rsqrt, 2 mul, 1 mul, 3 fma
 
 
+# HBM traffic of the gravity stage per launch (bytes), from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (see the
+# profile summaries); valid only for the gravity source it was measured on.
+MEASURED_TRAFFIC = {
+    # (precision, spheres, default tile): (bytes per launch, sha256[:16] of kernels_gravity.hip)
+    ("fp64", 124958, 512): (2300.8e6, "833efd3db34c079e"),
+    ("fp32", 124958, 1024): (539.8e6, "833efd3db34c079e"),
+}
+
+
+def gravity_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2311_11322_amd", "csrc", "kernels_gravity.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -66,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--n-agg", type=int, default=25000)
+    ap.add_argument("--gravity-tile", type=int, default=0, help="0: library default")
+    ap.add_argument("--cell-scale", type=float, default=1.0)
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -99,6 +118,7 @@ def main():
     torch.cuda.init()
     alloc = dem.TorchAllocator(0)
     sim = dem.Sim(w.params, precision=prec, allocator=alloc, stream=dem.torch_stream())
+    sim.set_tuning(args.gravity_tile, args.cell_scale)
     sim.add_workload(w)
     log("added; warmup", args.warmup)
     sim.step(args.warmup)
@@ -130,9 +150,12 @@ def main():
     flop = GRAVITY_FLOP_PER_PAIR * n * (n - 1)
     achieved = flop / (grav_ms * 1e-3) / 1e12
     dt_key = "fp32" if prec == dem.PREC_FP32_FORCE else "fp64"
+    tile = args.gravity_tile or dem.gravity_tiles(prec)[0]
+    meas = MEASURED_TRAFFIC.get((dt_key, n, tile))
+    traffic = meas[0] if meas and meas[1] == gravity_source_hash() else None
     roofline = {"kernel": "gravity", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS[dt_key], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[dt_key], 4), "traffic": None,
+                "frac": round(achieved / PEAK_TFLOPS[dt_key], 4), "traffic": traffic,
                 "avg_ms": round(grav_ms, 4),
                 "algorithmic": f"{GRAVITY_FLOP_PER_PAIR} FLOP x N(N-1) ordered pairs per launch"}
     per_kernel = {k: round(v / prof["_steps"], 4) for k, v in prof.items() if not k.startswith("_")}

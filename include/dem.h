@@ -191,6 +191,22 @@ dem_status dem_engine_destroy(dem_engine* eng);
 /* Status of one system after an engine step (DEM_OK or the failure code). */
 dem_status dem_sim_status(const dem_sim* sim);
 
+/* Launch-shape tuning of one system, set before dem_add_aggregates (the
+ * buffers are sized from it).  gravity_tile: spheres per gravity tile, one of
+ * the sizes dem_gravity_tiles lists for the system's precision (0: default);
+ * cell_scale >= 1 multiplies the contact cell side (at least the largest
+ * sphere diameter).  Results do not depend on cell_scale; gravity_tile changes
+ * the summation order of gravity (rounding only).  An engine may hold systems
+ * with different tunings. */
+typedef struct {
+    int32_t gravity_tile;
+    double cell_scale;
+} dem_tuning;
+dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
+/* Gravity tile sizes supported for a precision: writes up to n_max of them
+ * to tiles (default first) and returns how many there are. */
+int32_t dem_gravity_tiles(int32_t precision, int32_t* tiles, int32_t n_max);
+
 /* Per-kernel timing (measurement aid for benchmarks).  While enabled,
  * dem_step launches the step's kernels one by one (no graph) with a HIP event
  * before and after each, on the system's stream, and accumulates the elapsed

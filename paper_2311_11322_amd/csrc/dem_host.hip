@@ -67,7 +67,21 @@ int choose_bits(int64_t ns) {
   return std::min(10, std::max(2, b));
 }
 
-Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max) {
+int default_tile(int precision) {
+  int t[8];
+  gravity_tiles(precision, t);
+  return t[0];
+}
+
+bool tile_supported(int precision, int tile) {
+  int t[8];
+  const int n = gravity_tiles(precision, t);
+  for (int k = 0; k < n; ++k)
+    if (t[k] == tile) return true;
+  return false;
+}
+
+Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int tile) {
   Sizes z;
   z.na = na;
   z.ns = ns;
@@ -75,7 +89,7 @@ Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max) {
   z.cells = int64_t(1) << (3 * choose_bits(ns));
   z.grav = p.G != 0.0;
   z.precision = p.precision;
-  z.g_tile = gravity_tile(p.precision);
+  z.g_tile = tile > 0 ? tile : default_tile(p.precision);
   z.g_nt = (ns + z.g_tile - 1) / z.g_tile;
   z.n_rblk = (ns + kBlock - 1) / kBlock;
   return z;
@@ -171,8 +185,11 @@ struct Batch {
   int n_agg_blk = 0;
   WorkItem* wl_sph = nullptr;
   int n_sph_blk = 0;
-  GravItem* gl = nullptr;
-  int n_grav = 0;
+  // gravity tile pairs, grouped by tile size (one launch per group)
+  GravItem* gl[3] = {nullptr, nullptr, nullptr};
+  int n_grav[3] = {0, 0, 0};
+  int grav_tile[3] = {0, 0, 0};
+  int n_grav_groups = 0;
   bool any_grav = false;
   bool all_soft = true;
   ScanSeg* seg_cells = nullptr;
@@ -209,6 +226,7 @@ struct dem_sim {
   dem_engine* engine = nullptr;
   int engine_slot = -1;
   dem_status last_status = DEM_OK;
+  dem_tuning tune{0, 1.0};
   // per-kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -263,7 +281,9 @@ hipError_t upload(Batch& b, T** dst, const std::vector<T>& src, hipStream_t st) 
 dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
   std::vector<WorkItem> wa, wsph;
-  std::vector<GravItem> gl;
+  std::vector<GravItem> glg[3];
+  int tiles[3] = {0, 0, 0};
+  int n_groups = 0;
   std::vector<ScanSeg> sc, sp;
   std::vector<ScanItem> ic, ip;
   b.any_grav = false;
@@ -277,8 +297,11 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       b.any_grav = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
       // every tile pair (ti <= tj) of the pile: each unordered pair once
+      int g = 0;
+      while (g < n_groups && tiles[g] != h.g_tile) ++g;
+      if (g == n_groups) tiles[n_groups++] = h.g_tile;
       for (int ti = 0; ti < h.g_nt; ++ti)
-        for (int tj = ti; tj < h.g_nt; ++tj) gl.push_back({p, ti, tj, 0});
+        for (int tj = ti; tj < h.g_nt; ++tj) glg[g].push_back({p, ti, tj, 0});
     }
     // cell-count scan of this pile
     auto add_seg = [](std::vector<ScanSeg>& segs, std::vector<ScanItem>& items, const uint32_t* in,
@@ -301,7 +324,12 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   }
   HIPCHK(errsim, upload(b, &b.wl_agg, wa, st));
   HIPCHK(errsim, upload(b, &b.wl_sph, wsph, st));
-  HIPCHK(errsim, upload(b, &b.gl, gl, st));
+  for (int g = 0; g < 3; ++g) {
+    HIPCHK(errsim, upload(b, &b.gl[g], glg[g], st));
+    b.n_grav[g] = (int)glg[g].size();
+    b.grav_tile[g] = tiles[g];
+  }
+  b.n_grav_groups = n_groups;
   HIPCHK(errsim, upload(b, &b.seg_cells, sc, st));
   HIPCHK(errsim, upload(b, &b.item_cells, ic, st));
   HIPCHK(errsim, upload(b, &b.seg_pairs, sp, st));
@@ -311,7 +339,6 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   HIPCHK(errsim, upload(b, &b.sums_pairs, zp, st));
   b.n_agg_blk = (int)wa.size();
   b.n_sph_blk = (int)wsph.size();
-  b.n_grav = (int)gl.size();
   b.n_seg_cells = (int)sc.size();
   b.n_item_cells = (int)ic.size();
   b.n_seg_pairs = (int)sp.size();
@@ -356,8 +383,13 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(11);
   launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   mark(12);
-  if (b.any_grav)
-    launch_gravity(st, b.d_table, b.wl_sph, b.n_sph_blk, b.gl, b.n_grav, b.precision, b.all_soft);
+  if (b.any_grav) {
+    launch_gravity_records(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    for (int g = 0; g < b.n_grav_groups; ++g)
+      launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
+                           b.grav_tile[g]);
+    launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+  }
   mark(13);
   launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
   mark(14);
@@ -438,7 +470,7 @@ void release_pile(dem_sim* s) {
 
 dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   PileDev h{};
-  s->sz = pile_sizes(s->prm, na, ns, s->c_max);
+  s->sz = pile_sizes(s->prm, na, ns, s->c_max, s->tune.gravity_tile);
   BufList L;
   plan_pile(h, s->sz, L);
   for (auto& r : L.req) {
@@ -534,7 +566,7 @@ size_t dem_footprint_bytes(const dem_params* params, int64_t n_agg, int64_t n_sp
   int c = params->max_contacts_per_sphere > 0 ? params->max_contacts_per_sphere : kDefaultContacts;
   PileDev h{};
   BufList L;
-  plan_pile(h, pile_sizes(*params, n_agg, n_sph, c), L);
+  plan_pile(h, pile_sizes(*params, n_agg, n_sph, c, 0), L);
   return L.total();
 }
 
@@ -597,15 +629,16 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
     if (agg_spin && !std::isfinite(agg_spin[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite spin");
   }
   int nb_periodic = 0;
+  const double cell_min = s->tune.cell_scale * 2.0 * smax;
   if (s->prm.periodic) {
     // cells per axis: the largest power of two whose cell still spans the
-    // largest sphere diameter (one cell if the box is smaller than that)
-    const double ratio = s->prm.box[0] / (2.0 * smax);
+    // minimum cell side (one cell if the box is smaller than that)
+    const double ratio = s->prm.box[0] / cell_min;
     nb_periodic = ratio >= 1.0 ? (int)std::floor(std::log2(ratio)) : 0;
   }
   dem_status st = alloc_pile(s, n_agg, ns);
   if (st != DEM_OK) return st;
-  s->h.cell_min = 2.0 * smax;
+  s->h.cell_min = cell_min;
   // the Morton table must hold every periodic cell: larger cells if needed
   s->h.nb_periodic = std::min(nb_periodic, s->h.bits);
   hipStream_t str = s->stream;
@@ -947,6 +980,24 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   io.n_pairs = np;
   io.step = step;
   return dem_restore_state(s, &io);
+}
+
+dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
+  if (!s || !t) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  if (s->has_aggs) return fail(s, DEM_ERR_STATE, "tuning must be set before adding aggregates");
+  if (t->gravity_tile != 0 && !tile_supported(s->prm.precision, t->gravity_tile))
+    return fail(s, DEM_ERR_INVALID_ARG, "unsupported gravity tile size");
+  if (!(t->cell_scale >= 1.0) || !std::isfinite(t->cell_scale))
+    return fail(s, DEM_ERR_INVALID_ARG, "cell_scale must be finite and >= 1");
+  s->tune = *t;
+  return DEM_OK;
+}
+
+int32_t dem_gravity_tiles(int32_t precision, int32_t* tiles, int32_t n_max) {
+  int t[8];
+  const int n = gravity_tiles(precision == 1 ? 1 : 0, t);
+  for (int k = 0; k < n && k < n_max; ++k) tiles[k] = t[k];
+  return n;
 }
 
 dem_status dem_set_profiling(dem_sim* s, int32_t enabled) {

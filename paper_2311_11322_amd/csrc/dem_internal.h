@@ -165,9 +165,16 @@ void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
 void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                   ContactParams cp, int precision);
-void launch_gravity(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
-                    const GravItem* gl, int nitems, int precision, bool softened);
-int gravity_tile(int precision);
+// Gravity: records and the per-slot combine cover every pile; the tile-pair
+// kernel runs once per tile size present in the batch.
+void launch_gravity_records(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                            int precision);
+void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
+                          int precision, bool softened, int tile);
+void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                            int precision);
+// Supported tile sizes for a precision (default first); returns the count.
+int gravity_tiles(int precision, int* tiles);
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode);

@@ -27,9 +27,6 @@ namespace dem {
 
 namespace {
 
-constexpr int kIptF64 = 4;
-constexpr int kIptF32 = 8;
-
 struct alignas(64) Rec64 {
   double x, y, z, m, e, p0, p1, p2;
 };
@@ -286,29 +283,54 @@ __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restri
 
 }  // namespace
 
-int gravity_tile(int precision) { return 64 * (precision == 1 ? kIptF32 : kIptF64); }
-
-void launch_gravity(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
-                    const GravItem* gl, int nitems, int precision, bool softened) {
-  if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_grav_records, dim3(nblk), dim3(kBlock), 0, st, piles, wl, precision);
+int gravity_tiles(int precision, int* tiles) {
+  // default first: the fastest at 125k spheres on MI355X (measured)
   if (precision == 1) {
-    if (softened)
-      hipLaunchKernelGGL((k_grav_tiles<float, kIptF32, true>), dim3(nitems), dim3(64), 0, st,
-                         piles, gl);
-    else
-      hipLaunchKernelGGL((k_grav_tiles<float, kIptF32, false>), dim3(nitems), dim3(64), 0, st,
-                         piles, gl);
-    hipLaunchKernelGGL(k_grav_combine<float>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+    tiles[0] = 64 * 16;
+    tiles[1] = 64 * 8;
+    tiles[2] = 64 * 4;
   } else {
-    if (softened)
-      hipLaunchKernelGGL((k_grav_tiles<double, kIptF64, true>), dim3(nitems), dim3(64), 0, st,
-                         piles, gl);
-    else
-      hipLaunchKernelGGL((k_grav_tiles<double, kIptF64, false>), dim3(nitems), dim3(64), 0, st,
-                         piles, gl);
-    hipLaunchKernelGGL(k_grav_combine<double>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+    tiles[0] = 64 * 8;
+    tiles[1] = 64 * 4;
+    tiles[2] = 64 * 2;
   }
+  return 3;
+}
+
+void launch_gravity_records(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                            int precision) {
+  hipLaunchKernelGGL(k_grav_records, dim3(nblk), dim3(kBlock), 0, st, piles, wl, precision);
+}
+
+template <typename T, int IPT>
+static void tiles_launch(hipStream_t st, const PileDev* piles, const GravItem* gl, int n, bool soft) {
+  if (soft)
+    hipLaunchKernelGGL((k_grav_tiles<T, IPT, true>), dim3(n), dim3(64), 0, st, piles, gl);
+  else
+    hipLaunchKernelGGL((k_grav_tiles<T, IPT, false>), dim3(n), dim3(64), 0, st, piles, gl);
+}
+
+void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
+                          int precision, bool softened, int tile) {
+  if (nitems <= 0) return;
+  const int ipt = tile / 64;
+  if (precision == 1) {
+    if (ipt == 4) tiles_launch<float, 4>(st, piles, gl, nitems, softened);
+    else if (ipt == 16) tiles_launch<float, 16>(st, piles, gl, nitems, softened);
+    else tiles_launch<float, 8>(st, piles, gl, nitems, softened);
+  } else {
+    if (ipt == 2) tiles_launch<double, 2>(st, piles, gl, nitems, softened);
+    else if (ipt == 8) tiles_launch<double, 8>(st, piles, gl, nitems, softened);
+    else tiles_launch<double, 4>(st, piles, gl, nitems, softened);
+  }
+}
+
+void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                            int precision) {
+  if (precision == 1)
+    hipLaunchKernelGGL(k_grav_combine<float>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+  else
+    hipLaunchKernelGGL(k_grav_combine<double>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 
 }  // namespace dem

@@ -61,6 +61,10 @@ class dem_allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
 
 
+class dem_tuning(C.Structure):
+    _fields_ = [("gravity_tile", C.c_int32), ("cell_scale", C.c_double)]
+
+
 class dem_forcing(C.Structure):
     _fields_ = [("spin_dw", C.c_double)]
 
@@ -106,6 +110,9 @@ def lib():
         L.dem_engine_detach.argtypes = [vp, vp]
         L.dem_engine_destroy.argtypes = [vp]
         L.dem_sim_status.argtypes = [vp]
+        L.dem_set_tuning.argtypes = [vp, C.POINTER(dem_tuning)]
+        L.dem_gravity_tiles.argtypes = [C.c_int32, _PI32, C.c_int32]
+        L.dem_gravity_tiles.restype = C.c_int32
         L.dem_set_profiling.argtypes = [vp, C.c_int32]
         L.dem_get_profile.argtypes = [vp, _PD, C.c_int32, _PI64]
         L.dem_profile_names.restype = C.c_char_p
@@ -116,7 +123,7 @@ def lib():
                      "dem_reserve_contacts", "dem_find_contacts", "dem_destroy",
                      "dem_engine_create", "dem_engine_attach", "dem_engine_step",
                      "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
-                     "dem_set_profiling", "dem_get_profile"):
+                     "dem_set_profiling", "dem_get_profile", "dem_set_tuning"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -287,6 +294,10 @@ class Sim:
     def status(self) -> int:
         return int(lib().dem_sim_status(self.h))
 
+    def set_tuning(self, gravity_tile: int = 0, cell_scale: float = 1.0):
+        t = dem_tuning(int(gravity_tile), float(cell_scale))
+        _check(lib().dem_set_tuning(self.h, C.byref(t)), self.h)
+
     def set_profiling(self, on: bool):
         _check(lib().dem_set_profiling(self.h, int(bool(on))), self.h)
 
@@ -349,6 +360,13 @@ def find_contacts(pos, radius, agg, box=None) -> np.ndarray:
     _check(lib().dem_find_contacts(_p(pos), _p(radius), _p(agg, _PI32), n, _p(bx),
                                    _p(keys, _PU64), cap, C.byref(nout)))
     return keys[:nout.value].copy()
+
+
+def gravity_tiles(precision: int = PREC_FP64):
+    """Gravity tile sizes the library supports for a precision (default first)."""
+    buf = (C.c_int32 * 8)()
+    n = lib().dem_gravity_tiles(int(precision), buf, 8)
+    return [int(buf[k]) for k in range(n)]
 
 
 def footprint_bytes(params: Dict, n_agg: int, n_sph: int, precision: int = PREC_FP64,

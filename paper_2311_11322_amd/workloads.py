@@ -304,6 +304,131 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
     return pos, radius
 
 
+def _random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n uniformly random proper rotation matrices [n, 3, 3]."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ], 1)
+
+
+def _place_rounds(rng, counts, clusters, container, chunk=16384, max_rounds=2000,
+                  near_after=40):
+    """Random sequential addition in rounds (fast path for large systems).
+
+    Each round draws random centres and orientations for the pending
+    aggregates (largest first; several tries each when few are pending),
+    drops tries that come closer than MIN_GAP to a placed sphere, then accepts
+    tries in order unless their aggregate is already placed or they clash with
+    a try accepted earlier in the same round.  Centres are uniform in the
+    ball / periodic cube.  After ``near_after`` rounds (close to the jamming
+    limit) tries are drawn next to placed spheres at a small gap instead.
+    """
+    from scipy.spatial import cKDTree
+    kind, size = container
+    L = float(size) if kind == "box" else None
+    R = float(size) if kind == "ball" else None
+    rel = [c[0] - c[0].mean(axis=0) for c in clusters]
+    order = list(np.argsort(-counts, kind="stable"))
+    placed = [None] * len(counts)
+    P = np.zeros((0, 3))
+    Rr = np.zeros(0)
+    reach = 2.4 + MIN_GAP
+    for _round in range(max_rounds):
+        if not order:
+            break
+        batch = order[:chunk]
+        tries = max(1, min(4096, chunk // len(batch)))
+        agg_of = np.repeat(np.asarray(batch), tries)           # aggregate of each try
+        nt = agg_of.shape[0]
+        rots = _random_rotations(rng, nt)
+        sizes = counts[agg_of]
+        starts = np.concatenate([[0], np.cumsum(sizes)])
+        near = _round >= near_after and P.shape[0] > 0
+        if near:
+            # near jamming: put a random member of each try at a surface gap of
+            # U[1e-5, 1e-3] from a random placed sphere
+            t = rng.integers(P.shape[0], size=nt)
+            mem = (rng.uniform(size=nt) * sizes).astype(np.int64)
+            u = rng.normal(size=(nt, 3))
+            u /= np.linalg.norm(u, axis=1, keepdims=True)
+            gap0 = rng.uniform(1e-5, 1e-3, nt)
+            mrel = np.stack([rel[a][k] for a, k in zip(agg_of, mem)])
+            mrad = np.array([clusters[a][1][k] for a, k in zip(agg_of, mem)])
+            centres = (P[t] + (Rr[t] + mrad + gap0)[:, None] * u
+                       - np.einsum("kij,kj->ki", rots, mrel))
+        elif kind == "box":
+            centres = rng.uniform(0.0, L, (nt, 3))
+        else:
+            v = rng.normal(size=(nt, 3))
+            v /= np.linalg.norm(v, axis=1, keepdims=True)
+            centres = v * (R * rng.uniform(size=(nt, 1)) ** (1.0 / 3.0))
+        owner = np.repeat(np.arange(nt), sizes)                # try of each sphere
+        body = np.concatenate([rel[a] for a in agg_of])
+        crad = np.concatenate([clusters[a][1] for a in agg_of])
+        cpos = np.einsum("kij,kj->ki", rots[owner], body) + centres[owner]
+        qpos = np.mod(cpos, L) if kind == "box" else cpos
+        bad = np.zeros(nt, dtype=bool)
+        if kind == "ball":
+            bad |= np.linalg.norm(centres, axis=1) > R
+        if P.shape[0]:
+            tree = cKDTree(np.mod(P, L) if kind == "box" else P, boxsize=L)
+            dist, idx = tree.query(qpos, k=16, distance_upper_bound=reach)
+            hit = np.isfinite(dist)
+            lim = np.where(hit, crad[:, None] + Rr[np.minimum(idx, len(Rr) - 1)] + MIN_GAP, 0.0)
+            clash = (hit & (dist < lim)).any(axis=1)
+            bad[np.unique(owner[clash])] = True
+        good_sph = ~bad[owner]
+        conflicts = {}
+        if good_sph.any():
+            gidx = np.nonzero(good_sph)[0]
+            ctree = cKDTree(qpos[gidx], boxsize=L)
+            pairs = ctree.query_pairs(reach, output_type="ndarray")
+            if pairs.size:
+                a0, a1 = gidx[pairs[:, 0]], gidx[pairs[:, 1]]
+                oa, ob = owner[a0], owner[a1]
+                d = qpos[a1] - qpos[a0]
+                if kind == "box":
+                    d -= L * np.round(d / L)
+                gap = np.sqrt((d * d).sum(1)) - crad[a0] - crad[a1]
+                m = (oa != ob) & (gap < MIN_GAP)
+                for x, y in zip(oa[m].tolist(), ob[m].tolist()):
+                    conflicts.setdefault(x, []).append(y)
+                    conflicts.setdefault(y, []).append(x)
+        accepted = np.zeros(nt, dtype=bool)
+        done = set()
+        for k in np.nonzero(~bad)[0].tolist():
+            a = int(agg_of[k])
+            if a in done:
+                continue
+            if any(accepted[o] for o in conflicts.get(k, ())):
+                continue
+            accepted[k] = True
+            done.add(a)
+        new_p, new_r = [], []
+        for k in np.nonzero(accepted)[0].tolist():
+            a = int(agg_of[k])
+            pos = cpos[starts[k]:starts[k + 1]]
+            if kind == "box":
+                pos = pos - centres[k] + np.mod(centres[k], L)
+            placed[a] = pos
+            new_p.append(pos)
+            new_r.append(clusters[a][1])
+        if new_p:
+            P = np.concatenate([P] + new_p)
+            Rr = np.concatenate([Rr] + new_r)
+        order = [a for a in batch if a not in done] + order[chunk:]
+    if order:
+        raise RuntimeError("random sequential addition did not converge; lower the packing")
+    pos = np.concatenate([placed[a] for a in range(len(counts))])
+    radius = np.concatenate([clusters[a][1] for a in range(len(counts))])
+    return pos, radius
+
+
 # --------------------------------------------------------------------------
 # public workloads
 # --------------------------------------------------------------------------
@@ -355,7 +480,10 @@ def collapse_cloud(seed: int = 1, n_agg: int = 25000, cmin: int = 2, cmax: int =
     clusters = [random_cluster(rng, int(c)) for c in counts]
     vol = sum(float(sphere_mass(c[1]).sum()) for c in clusters)
     R = collapse_radius(vol, phi0)
-    pos, radius = _place(rng, counts, clusters, ("ball", R), contact_seeded)
+    if contact_seeded:
+        pos, radius = _place(rng, counts, clusters, ("ball", R), True)
+    else:
+        pos, radius = _place_rounds(rng, counts, clusters, ("ball", R))
     mass = sphere_mass(radius)
     agg_vel = rng.normal(0.0, vel_sigma, (n_agg, 3)) if vel_sigma > 0 else np.zeros((n_agg, 3))
     agg_spin = rng.normal(0.0, spin_sigma, (n_agg, 3)) if spin_sigma > 0 else np.zeros((n_agg, 3))
@@ -367,29 +495,39 @@ def collapse_cloud(seed: int = 1, n_agg: int = 25000, cmin: int = 2, cmax: int =
                     + (", contact-seeded" if contact_seeded else ""))
 
 
+def _one_pile(args):
+    k, prng_seed, n_agg, cmin, cmax, phi0, dt, n_steps, G, soft_frac, spin = args
+    w = collapse_cloud(seed=prng_seed, n_agg=n_agg, cmin=cmin, cmax=cmax, phi0=phi0, dt=dt,
+                       n_steps=n_steps, G=G, soft_frac=soft_frac)
+    w.name = f"pile{k}"
+    w.params["spin_dw"] = spin / dt      # spin increment per step, rad per time unit
+    return w
+
+
 def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 20000,
-               cmin: int = 1, cmax: int = 8, phi0: float = 0.2, dt: float = 5e-4,
+               cmin: int = 1, cmax: int = 8, phi0: float = 0.15, dt: float = 5e-4,
                n_steps: int = 800, spin_rate_per_step2: float = 1e-6,
-               G: float = 1.0, soft_frac: float = 0.5) -> List[Workload]:
+               G: float = 1.0, soft_frac: float = 0.5, workers: int = 0) -> List[Workload]:
     """Independent piles with log-uniform sphere counts in [nmin, nmax].
 
     Each pile is a cloud of aggregates packed at phi0 about the origin; the
     spin-up forcing (constant spin increment per step) is recorded in the
-    params of every pile.
+    params of every pile.  ``workers`` > 1 generates piles in parallel
+    processes (same result: every pile has its own seed).
     """
     rng = np.random.default_rng(seed)
     targets = np.floor(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_piles))).astype(int)
-    piles = []
+    jobs = []
     for k, nt in enumerate(targets):
         prng_seed = int(rng.integers(2 ** 31))
-        mean_c = 0.5 * (cmin + cmax)
-        n_agg = max(1, int(round(nt / mean_c)))
-        w = collapse_cloud(seed=prng_seed, n_agg=n_agg, cmin=cmin, cmax=cmax,
-                           phi0=phi0, dt=dt, n_steps=n_steps, G=G, soft_frac=soft_frac)
-        w.name = f"pile{k}"
-        w.params["spin_dw"] = spin_rate_per_step2 / dt   # rad per time unit, per step
-        piles.append(w)
-    return piles
+        n_agg = max(1, int(round(nt / (0.5 * (cmin + cmax)))))
+        jobs.append((k, prng_seed, n_agg, cmin, cmax, phi0, dt, n_steps, G, soft_frac,
+                     spin_rate_per_step2))
+    if workers and workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(_one_pile, jobs, chunksize=1))
+    return [_one_pile(j) for j in jobs]
 
 
 def subset(w: Workload, n_agg: int) -> Workload:

@@ -512,3 +512,45 @@ def test_subset_evaluation_matches_full_evaluation():
     F, T = o.eval_subset(idx)
     assert np.array_equal(F, s["F"][idx])
     assert np.array_equal(T, s["tau"][idx])
+
+
+# ---------------------------------------------------------------------------
+# spin-up forcing and the bulk radius diagnostic
+# ---------------------------------------------------------------------------
+
+def test_spin_up_forcing_adds_spin_and_angular_momentum():
+    """Each step adds dw about +z through the pile's centre of mass to every
+    body: space spins grow by n dw exactly, and L_z grows by
+    dw sum(M r_perp^2 + I_zz) per step (bodies barely move here)."""
+    dw = 1e-3
+    prm = dict(W.CONTACT_PARAMS, dt=1e-3, G=0.0, soft_frac=0.5, periodic=0, box=(0, 0, 0),
+               spin_dw=dw)
+    ang = np.linspace(0, 2 * np.pi, 9)[:-1]
+    pos = np.stack([5 * np.cos(ang), 5 * np.sin(ang), np.linspace(-1, 1, 8)], 1) + [1.0, 2.0, 0.0]
+    rad = np.full(8, 0.9)
+    m = W.sphere_mass(rad)
+    o = O.Oracle(prm).add([1] * 8, pos, rad, m)
+    L0 = o.diagnostics()["L"][2]
+    n = 20
+    o.step(n)
+    a = o.aggregates()
+    w_space = np.array([O.quat_matrix(q) @ wb for q, wb in zip(a["q"], a["wb"])])
+    assert np.allclose(w_space[:, 2], n * dw, rtol=1e-12)
+    assert np.abs(w_space[:, :2]).max() < 1e-15
+    com = (m[:, None] * pos).sum(0) / m.sum()
+    rp2 = ((pos - com)[:, :2] ** 2).sum(1)
+    expect = n * dw * (m * rp2 + 0.4 * m * rad ** 2).sum()
+    # the orbital part about the origin also picks up r_A x (dw z x (r_A - com))
+    assert o.diagnostics()["L"][2] - L0 == pytest.approx(
+        expect + n * dw * (m * ((pos[:, :2] - com[:2]) * com[:2]).sum(1)).sum(), rel=1e-4)
+
+
+def test_bulk_radius_of_uniform_ball():
+    """A uniform ball of radius R has sqrt(5/3 <r^2>) = R."""
+    g = np.arange(-20, 21) * 0.5
+    p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    p = p[np.linalg.norm(p, axis=1) <= 10.0]
+    rad = np.full(len(p), 0.01)
+    prm = dict(W.CONTACT_PARAMS, dt=1e-3, G=0.0, soft_frac=0.5, periodic=0, box=(0, 0, 0))
+    o = O.Oracle(prm).add([1] * len(p), p, rad, W.sphere_mass(rad))
+    assert o.diagnostics()["R_bulk"] == pytest.approx(10.0, rel=2e-2)
