@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline workload (skip FP32-force, batched and served)")
+    ap.add_argument("--piles", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -174,10 +178,99 @@ def main():
         "kernel_ms_per_step": per_kernel,
         "roofline": roofline,
     }
+    sim.close()
+    if not args.no_extra:
+        extra_runs(args, w, out, prec)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def timed_steps(sim, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def extra_runs(args, w, out, prec):
+    """The FP32-force form on the same collapse, the batched spin-up piles
+    (plain FP64 one pile at a time vs FP32-force batched in one engine) and
+    a served request stream."""
+    import numpy as np
+    import torch
+    from paper_2311_11322_amd import dem, serve
+    from paper_2311_11322_amd import workloads as W
+    workers = min(16, len(os.sched_getaffinity(0)))
+    # -- FP32-force form at 125k spheres
+    if prec == dem.PREC_FP64:
+        s32 = dem.Sim(w.params, precision=dem.PREC_FP32_FORCE)
+        s32.add_workload(w)
+        s32.step(2)
+        s32.set_profiling(True)
+        wall = timed_steps(s32, args.steps)
+        p32 = s32.profile()
+        s32.close()
+        g_ms = p32["gravity"] / p32["_steps"]
+        ach = GRAVITY_FLOP_PER_PAIR * w.n_sph * (w.n_sph - 1) / (g_ms * 1e-3) / 1e12
+        out["fp32_force"] = {"value": round(w.n_sph * args.steps / wall, 1),
+                             "ms_per_step": round(1e3 * wall / args.steps, 4),
+                             "gravity_ms": round(g_ms, 4),
+                             "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
+        log(f"fp32-force: {out['fp32_force']}")
+    # -- batched spin-up piles
+    t = time.time()
+    piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)
+    n_tot = sum(p.n_sph for p in piles)
+    log(f"{len(piles)} piles, {n_tot} spheres ({time.time() - t:.1f} s to place)")
+    tune = serve.autotune(piles, dem.PREC_FP32_FORCE, steps=3)
+    log(f"autotuned: tile {tune['gravity_tile']}, cell scale {tune['cell_scale']}")
+    bsteps = max(5, args.steps // 2)
+    batch = serve.run_batch(piles, bsteps, dem.PREC_FP32_FORCE,
+                            tuning=(tune["gravity_tile"], tune["cell_scale"]), warmup=2)
+    for s in batch["sims"]:
+        s.close()
+    # plain: the same piles, FP64, one at a time
+    plain_time = 0.0
+    for p in piles:
+        sp = dem.Sim(p.params)
+        sp.add_workload(p)
+        sp.set_forcing(p.params["spin_dw"])
+        sp.step(1)
+        plain_time += timed_steps(sp, bsteps)
+        sp.close()
+    plain_value = n_tot * bsteps / plain_time
+    out["batched"] = {
+        "workload": f"{len(piles)} independent spin-up piles, 500-20000 spheres each "
+                    f"(log-uniform), {n_tot} spheres, FP32-force, one engine",
+        "value": round(batch["sphere_steps_per_s"], 1), "unit": "sphere-steps/s",
+        "ms_per_step": round(batch["ms_per_step"], 4),
+        "gravity_pairs_per_step": batch["sum_n2"],
+        "tuning": {"gravity_tile": tune["gravity_tile"], "cell_scale": tune["cell_scale"]},
+        "plain_fp64_one_pile_at_a_time": round(plain_value, 1),
+        "speedup_vs_plain": round(batch["sphere_steps_per_s"] / plain_value, 2)}
+    log(f"batched: {out['batched']}")
+    # -- served stream
+    if args.requests > 0:
+        t = time.time()
+        reqs = serve.request_stream(seed=4, n_requests=args.requests, rate_per_s=20.0,
+                                    workers=workers)
+        log(f"{len(reqs)} requests generated ({time.time() - t:.1f} s)")
+        srv = serve.Server(64 << 30, precision=dem.PREC_FP32_FORCE, chunk_steps=50,
+                           tuning=(tune["gravity_tile"], tune["cell_scale"]))
+        st = srv.run(reqs)
+        out["served"] = {
+            "workload": f"{len(reqs)} requests, Poisson arrivals at 20/s, collapse or spin-up, "
+                        "1k-50k spheres, 100-5000 steps, FP32-force, 64 GiB admission budget",
+            "p50_latency_s": round(st["p50_latency_s"], 3),
+            "p99_latency_s": round(st["p99_latency_s"], 3),
+            "sphere_steps_per_s": round(st["sphere_steps_per_s"], 1),
+            "makespan_s": round(st["makespan_s"], 2), "completed": st["completed"],
+            "failed": st["failed"]}
+        log(f"served: {out['served']}")
 
 
 if __name__ == "__main__":

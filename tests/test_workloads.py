@@ -73,3 +73,15 @@ def test_shape_fixtures_touching(name):
         d = np.linalg.norm(p[:, None] - p[None], axis=2)
         np.fill_diagonal(d, np.inf)
         assert d.min() == pytest.approx(2.0, abs=1e-12)
+
+
+def test_request_stream_is_seeded():
+    from paper_2311_11322_amd import serve
+    a = serve.request_stream(seed=1, n_requests=5, rate_per_s=20.0, nmin=300, nmax=900,
+                             smin=10, smax=50)
+    b = serve.request_stream(seed=1, n_requests=5, rate_per_s=20.0, nmin=300, nmax=900,
+                             smin=10, smax=50)
+    assert [r.arrival for r in a] == [r.arrival for r in b]
+    assert all(np.array_equal(x.workload.pos, y.workload.pos) for x, y in zip(a, b))
+    assert a[0].arrival == 0.0 and all(x.arrival <= y.arrival for x, y in zip(a, a[1:]))
+    assert all(10 <= r.steps <= 50 for r in a)
