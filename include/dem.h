@@ -78,10 +78,17 @@ typedef struct {
     void* ctx;
 } dem_allocator;
 
-/* Optional forcing of one system (spin-up experiment of Sec. 4.1: a constant
- * spin increment per step about +z through the system's centre of mass). */
+/* Optional forcing of one system.  Spin-up (Sec. 4.1: a constant spin
+ * increment per step about +z through the system's centre of mass) and a
+ * tidal perturber (Sec. 4.2: a point mass passing the system), which is an
+ * unsoftened point mass integrated by the same leapfrog: every sphere feels
+ * G m_i M (r_p - r_i)/|r_p - r_i|^3 and the perturber the sum of the
+ * reactions.  Requires G > 0. */
 typedef struct {
     double spin_dw;            /* spin increment per step (rad per time unit); 0: off */
+    double pert_mass;          /* perturber mass; 0: no perturber */
+    double pert_pos[3];        /* perturber position */
+    double pert_vel[3];        /* perturber velocity */
 } dem_forcing;
 
 /* State read-out / restore.  Caller-owned host buffers sized by
@@ -145,12 +152,19 @@ dem_status dem_read_state(dem_sim* sim, dem_state* out);
 /* Counts: aggregates, spheres, contacts of the last evaluation. */
 dem_status dem_get_counts(const dem_sim* sim, int64_t* n_agg, int64_t* n_sph, int64_t* n_pairs);
 
+/* Set the forcing.  A perturber set before dem_add_aggregates gets its t0
+ * acceleration from the initial evaluation; set later, its acceleration
+ * starts at zero until the next evaluation. */
 dem_status dem_set_forcing(dem_sim* sim, const dem_forcing* forcing);
+/* Current forcing, with the perturber's position and velocity now. */
+dem_status dem_get_forcing(dem_sim* sim, dem_forcing* out);
 
 /* Restore aggregate state, contact list and spring history from a checkpoint
  * written by dem_read_state (fields agg_pos, agg_vel, agg_acc, agg_torque,
  * agg_quat, agg_spin_body, pair_keys, pair_hist, n_pairs, step).  Resuming
- * reproduces the uninterrupted run bit for bit. */
+ * reproduces the uninterrupted run bit for bit.  A perturber is not part of
+ * the checkpoint (dem_get_forcing / dem_set_forcing carry its position and
+ * velocity). */
 dem_status dem_restore_state(dem_sim* sim, const dem_state* in);
 
 /* Grow the contact capacity (per sphere, each side) after DEM_ERR_CAPACITY. */

@@ -58,6 +58,8 @@ def lib():
         L.ora_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64]
         L.ora_gravity.argtypes = [_PD, _PD, _PD, C.c_int64, C.c_double, C.c_double, _PI64,
                                   C.c_int64, _PD]
+        L.ora_set_perturber.argtypes = [C.c_void_p, C.c_double, _PD, _PD]
+        L.ora_get_perturber.argtypes = [C.c_void_p, _PD, _PD, _PD]
         L.ora_rotate.argtypes = [_PD, _PD, _PD, _PD, C.c_double, _PD]
         L.ora_setup_body.restype = C.c_int
         L.ora_setup_body.argtypes = [C.c_int64, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
@@ -120,6 +122,17 @@ class Oracle:
 
     def add_workload(self, w, evaluate=True):
         return self.add(w.counts, w.pos, w.radius, w.mass, w.agg_vel, w.agg_spin, evaluate)
+
+    def set_perturber(self, M, pos, vel):
+        pos = _f64(pos)
+        vel = _f64(vel)
+        lib().ora_set_perturber(self._h, float(M), _p(pos), _p(vel))
+        return self
+
+    def perturber(self):
+        r, v, a = np.zeros(3), np.zeros(3), np.zeros(3)
+        lib().ora_get_perturber(self._h, _p(r), _p(v), _p(a))
+        return r, v, a
 
     def step(self, n=1):
         if lib().ora_step(self._h, int(n)) != 0:

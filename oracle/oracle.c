@@ -54,6 +54,9 @@ struct ora_sim {
     double *hist;   /* 7 per pair */
     double *pforce; /* 9 per pair */
     double *pdiag;  /* 8 per pair */
+    /* point-mass perturber */
+    int pert_on;
+    double pert_M, pert_r[3], pert_v[3], pert_a[3];
 };
 
 /* ------------------------------------------------------------------ */
@@ -593,6 +596,36 @@ void ora_gravity(const double* pos, const double* mass, const double* radius, in
     }
 }
 
+/* Unsoftened pull of the perturber on sphere i (added to F). */
+static void perturber_pull(const ora_sim* s, int64_t i, double* F)
+{
+    double d[3] = {s->pert_r[0] - s->r[3 * i], s->pert_r[1] - s->r[3 * i + 1],
+                   s->pert_r[2] - s->r[3 * i + 2]};
+    double r2 = dot(d, d);
+    double f = s->p.G * s->m[i] * s->pert_M / (r2 * sqrt(r2));
+    F[0] += f * d[0];
+    F[1] += f * d[1];
+    F[2] += f * d[2];
+}
+
+void ora_set_perturber(ora_sim* s, double M, const double* pos, const double* vel)
+{
+    int c;
+    s->pert_on = M > 0.0;
+    s->pert_M = M;
+    for (c = 0; c < 3; c++) { s->pert_r[c] = pos[c]; s->pert_v[c] = vel[c]; s->pert_a[c] = 0.0; }
+}
+
+void ora_get_perturber(const ora_sim* s, double* pos, double* vel, double* acc)
+{
+    int c;
+    for (c = 0; c < 3; c++) {
+        if (pos) pos[c] = s->pert_r[c];
+        if (vel) vel[c] = s->pert_v[c];
+        if (acc) acc[c] = s->pert_a[c];
+    }
+}
+
 /* Binary search for (i, j) in the previous step's canonical pair list. */
 static int64_t find_old(const int64_t* opi, const int64_t* opj, int64_t onp, int64_t i, int64_t j)
 {
@@ -664,6 +697,16 @@ static void evaluate(ora_sim* s, int carry_history)
             }
             for (c = 0; c < 3; c++) s->F[3 * i + c] += acc[c];
         }
+    }
+    /* perturber: pull on every sphere (after self-gravity), reaction on it */
+    if (s->pert_on) {
+        double Fp[3] = {0.0, 0.0, 0.0};
+        for (i = 0; i < s->ns; i++) {
+            double f[3] = {0.0, 0.0, 0.0};
+            perturber_pull(s, i, f);
+            for (c = 0; c < 3; c++) { s->F[3 * i + c] += f[c]; Fp[c] -= f[c]; }
+        }
+        for (c = 0; c < 3; c++) s->pert_a[c] = Fp[c] / s->pert_M;
     }
     /* GetAccelAndTorque: a_A = (1/M) sum F_i  (Eqs. 5, 7);
      * N_A = sum [(r_i - r_A) x F_i + tau_i]  (Eqs. 6, 9: the contact part of
@@ -809,6 +852,12 @@ static void step_once(ora_sim* s)
             }
         }
     }
+    if (s->pert_on) {
+        for (c = 0; c < 3; c++) {
+            s->pert_v[c] += 0.5 * h * s->pert_a[c];
+            s->pert_r[c] += h * s->pert_v[c];
+        }
+    }
     /* orientation and spin: one RK5 step with the last torque */
     for (A = 0; A < s->na; A++)
         ora_rotate(&s->q[4 * A], &s->wb[3 * A], &s->I[3 * A], &s->NA[3 * A], h, NULL);
@@ -818,6 +867,8 @@ static void step_once(ora_sim* s)
     /* second half kick */
     for (A = 0; A < s->na; A++)
         for (c = 0; c < 3; c++) s->vA[3 * A + c] += 0.5 * h * s->aA[3 * A + c];
+    if (s->pert_on)
+        for (c = 0; c < 3; c++) s->pert_v[c] += 0.5 * h * s->pert_a[c];
     spin_up(s);
 }
 
@@ -953,6 +1004,7 @@ void ora_eval_subset(const ora_sim* s, const int64_t* idx, int64_t n_idx, double
             }
             for (c = 0; c < 3; c++) f[c] += acc[c];
         }
+        if (s->pert_on) perturber_pull(s, x, f);
         for (c = 0; c < 3; c++) { F[3 * k + c] = f[c]; tau[3 * k + c] = t[c]; }
     }
 }

@@ -60,6 +60,13 @@ void ora_get_spheres(const ora_sim* s, double* r, double* v, double* F, double* 
 void ora_get_pairs(const ora_sim* s, int64_t* pi, int64_t* pj, double* hist,
                    double* force, double* diag);
 
+/* Point-mass perturber (tidal flyby): unsoftened, mass M, integrated by the
+ * same leapfrog; every sphere feels G m_i M (r_p - r_i)/|r_p - r_i|^3 and the
+ * perturber the sum of the reactions.  Set before ora_add (its t0
+ * acceleration comes from the initial evaluation).  get returns pos, vel. */
+void ora_set_perturber(ora_sim* s, double M, const double* pos, const double* vel);
+void ora_get_perturber(const ora_sim* s, double* pos, double* vel, double* acc);
+
 /* Diagnostics of the current state: out[0..2] linear momentum, out[3..5]
  * angular momentum about the origin, out[6] translational KE, out[7]
  * rotational KE, out[8] normal spring energy, out[9] gravitational energy,

@@ -146,6 +146,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
     L.add(&h.gacc, 3 * ns);
   }
   L.add(&h.bpart, 10 * z.n_rblk);
+  L.add(&h.ppart, 3 * z.n_rblk);
   L.add(&h.grid, 1);
   L.add(&h.cell_cnt, z.cells);
   L.add(&h.cell_start, z.cells + 1);
@@ -220,7 +221,7 @@ struct dem_sim {
   int c_max = kDefaultContacts;
   bool has_aggs = false;
   bool stepped = false;
-  double spin_dw = 0.0;
+  dem_forcing forcing{};
   // where the authoritative copy of the table entry lives
   Batch own;                         // standalone batch of one
   dem_engine* engine = nullptr;
@@ -393,7 +394,7 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(13);
   launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
   mark(14);
-  launch_finish(st, b.d_table, np, mode);
+  launch_finish(st, b.d_table, np, mode, b.cp.dt);
   mark(15);
 }
 
@@ -494,7 +495,16 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.box = s->prm.box[0];
   h.G = s->prm.G;
   h.soft_frac = s->prm.softening_frac;
-  h.spin_dw = s->spin_dw;
+  h.spin_dw = s->forcing.spin_dw;
+  h.pert_on = s->forcing.pert_mass > 0.0 ? 1 : 0;
+  h.pert_M = s->forcing.pert_mass;
+  for (int k = 0; k < 3; ++k) {
+    for (int q = 0; q < 2; ++q) {
+      h.pert_r[q][k] = s->forcing.pert_pos[k];
+      h.pert_v[q][k] = s->forcing.pert_vel[k];
+      h.pert_a[q][k] = 0.0;
+    }
+  }
   h.parity = 0;
   h.status = 0;
   h.step = 0;
@@ -508,6 +518,22 @@ hipError_t put_entry(const dem_sim* s, PileDev* dst, hipStream_t st) {
   return hipMemcpyAsync(dst, &s->h, sizeof(PileDev), hipMemcpyHostToDevice, st);
 }
 
+// Fields of a table entry that the kernels update (everything else is set
+// by the host): bookkeeping and the perturber's state.
+void copy_device_fields(PileDev& dst, const PileDev& src) {
+  dst.parity = src.parity;
+  dst.status = src.status;
+  dst.step = src.step;
+  dst.fail_step = src.fail_step;
+  dst.n_pairs = src.n_pairs;
+  for (int q = 0; q < 2; ++q)
+    for (int k = 0; k < 3; ++k) {
+      dst.pert_r[q][k] = src.pert_r[q][k];
+      dst.pert_v[q][k] = src.pert_v[q][k];
+      dst.pert_a[q][k] = src.pert_a[q][k];
+    }
+}
+
 // Read back a table entry into the host mirror (after the stream is idle).
 hipError_t get_entry(dem_sim* s, const PileDev* src, hipStream_t st) {
   PileDev tmp;
@@ -515,11 +541,7 @@ hipError_t get_entry(dem_sim* s, const PileDev* src, hipStream_t st) {
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
-  s->h.parity = tmp.parity;
-  s->h.status = tmp.status;
-  s->h.step = tmp.step;
-  s->h.fail_step = tmp.fail_step;
-  s->h.n_pairs = tmp.n_pairs;
+  copy_device_fields(s->h, tmp);
   return hipSuccess;
 }
 
@@ -899,14 +921,43 @@ dem_status dem_restore_state(dem_sim* s, const dem_state* in) {
 
 dem_status dem_set_forcing(dem_sim* s, const dem_forcing* f) {
   if (!s || !f) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
-  if (!std::isfinite(f->spin_dw)) return fail(s, DEM_ERR_INVALID_ARG, "non-finite forcing");
-  s->spin_dw = f->spin_dw;
+  bool ok = std::isfinite(f->spin_dw) && std::isfinite(f->pert_mass) && f->pert_mass >= 0.0;
+  for (int k = 0; k < 3; ++k) ok = ok && std::isfinite(f->pert_pos[k]) && std::isfinite(f->pert_vel[k]);
+  if (!ok) return fail(s, DEM_ERR_INVALID_ARG, "non-finite or negative forcing");
+  if (f->pert_mass > 0.0 && !(s->prm.G > 0.0))
+    return fail(s, DEM_ERR_INVALID_ARG, "a perturber needs G > 0");
+  s->forcing = *f;
   if (!s->has_aggs) return DEM_OK;
   hipStream_t st = stream_of(s);
   HIPCHK(s, get_entry(s, entry_of(s), st));
-  s->h.spin_dw = f->spin_dw;
+  PileDev& h = s->h;
+  h.spin_dw = f->spin_dw;
+  h.pert_on = f->pert_mass > 0.0 ? 1 : 0;
+  h.pert_M = f->pert_mass;
+  for (int k = 0; k < 3; ++k) {
+    h.pert_r[h.parity][k] = f->pert_pos[k];
+    h.pert_v[h.parity][k] = f->pert_vel[k];
+    h.pert_a[h.parity][k] = 0.0;
+  }
   HIPCHK(s, put_entry(s, const_cast<PileDev*>(entry_of(s)), st));
   HIPCHK(s, hipStreamSynchronize(st));
+  return DEM_OK;
+}
+
+dem_status dem_get_forcing(dem_sim* s, dem_forcing* out) {
+  if (!s || !out) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
+  *out = s->forcing;
+  if (!s->has_aggs) return DEM_OK;
+  hipStream_t st = stream_of(s);
+  PileDev cur;
+  HIPCHK(s, hipMemcpyAsync(&cur, entry_of(s), sizeof(PileDev), hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  out->spin_dw = cur.spin_dw;
+  out->pert_mass = cur.pert_on ? cur.pert_M : 0.0;
+  for (int k = 0; k < 3; ++k) {
+    out->pert_pos[k] = cur.pert_r[cur.parity][k];
+    out->pert_vel[k] = cur.pert_v[cur.parity][k];
+  }
   return DEM_OK;
 }
 
@@ -961,6 +1012,11 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   h.cell_min = cell_min;
   h.nb_periodic = nbp;
   h.step = step;
+  for (int k = 0; k < 3; ++k) {   // the perturber continues where it was
+    h.pert_r[0][k] = old.pert_r[old.parity][k];
+    h.pert_v[0][k] = old.pert_v[old.parity][k];
+    h.pert_a[0][k] = old.pert_a[old.parity][k];
+  }
   HIPCHK(s, hipMemcpyAsync(h.first, first.data(), na * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(h.count, count.data(), na * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(h.agg, agg.data(), ns * 4, hipMemcpyHostToDevice, st));
@@ -1233,11 +1289,7 @@ dem_status dem_engine_step(dem_engine* e, int64_t n_steps) {
   dem_status first = DEM_OK;
   for (size_t k = 0; k < b.members.size(); ++k) {
     dem_sim* s = b.members[k];
-    s->h.parity = tab[k].parity;
-    s->h.status = tab[k].status;
-    s->h.step = tab[k].step;
-    s->h.fail_step = tab[k].fail_step;
-    s->h.n_pairs = tab[k].n_pairs;
+    copy_device_fields(s->h, tab[k]);
     s->stepped = true;
     const dem_status c = status_code(s->h.status);
     if (c != DEM_OK && first == DEM_OK) first = c;

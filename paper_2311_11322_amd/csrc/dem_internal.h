@@ -67,6 +67,13 @@ struct PileDev {
   uint32_t n_pairs;          // contacts of the last evaluation
   uint32_t pad0;
 
+  // point-mass perturber, ping-pong by parity (state lives in the table)
+  int32_t pert_on;
+  int32_t pad1;
+  double pert_M;
+  double pert_r[2][3], pert_v[2][3], pert_a[2][3];
+  double* ppart;             // [n_rblk][3] block sums of the perturber's pull
+
   // aggregate constants (written once by the set-up kernel)
   int32_t* first;            // [na] first member sphere
   int32_t* count;            // [na]
@@ -177,7 +184,7 @@ void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem
 int gravity_tiles(int precision, int* tiles);
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
-void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode);
+void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
                  int n_items, uint32_t* item_sums);

@@ -214,11 +214,11 @@ __device__ void rk5_rotate(double y[7], const double I[3], const double N[3], do
 // the next state, the space-frame spin w_A = R w_b and the predicted
 // centre-of-mass velocity v_A + h/2 a_A (first bracket of Eq. 3).  Init mode
 // copies the state unchanged (evaluation at t0).
-__global__ __launch_bounds__(kBlock) void k_integrate(const PileDev* __restrict__ piles,
+__global__ __launch_bounds__(kBlock) void k_integrate(PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl,
                                                       ContactParams cp, int mode) {
   const WorkItem w = wl[blockIdx.x];
-  const PileDev& P = piles[w.pile];
+  PileDev& P = piles[w.pile];
   const int A = w.base + threadIdx.x;
   if (A >= P.na || P.status != 0) return;
   const int na = P.na, cur = P.parity, nxt = cur ^ 1;
@@ -259,6 +259,18 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const PileDev* __restrict_
     P.wb[nxt][k * na + A] = y[4 + k];
   }
   for (int k = 0; k < 4; ++k) P.q[nxt][k * na + A] = y[k];
+  if (A == 0 && P.pert_on) {
+    // the perturber is one more body of the same leapfrog
+    for (int k = 0; k < 3; ++k) {
+      double pv = P.pert_v[cur][k], pr = P.pert_r[cur][k];
+      if (mode == kModeStep) {
+        pv += 0.5 * h * P.pert_a[cur][k];
+        pr += h * pv;
+      }
+      P.pert_v[nxt][k] = pv;
+      P.pert_r[nxt][k] = pr;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -477,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
 // One thread per pile: commit the step (flip the ping-pong halves) unless
 // the pile failed during it, in which case its state stays at the failing
 // step's start and the step index is recorded.
-__global__ void k_finish(PileDev* __restrict__ piles, int n_piles, int mode) {
+__global__ void k_finish(PileDev* __restrict__ piles, int n_piles, int mode, double dt) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_piles) return;
   PileDev& P = piles[p];
@@ -486,6 +498,18 @@ __global__ void k_finish(PileDev* __restrict__ piles, int n_piles, int mode) {
     return;
   }
   const int nxt = P.parity ^ 1;
+  if (P.pert_on) {
+    // reaction on the perturber: minus the pull on every sphere, summed over
+    // the per-block partials in block order; then its closing half kick
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < P.n_rblk; ++b)
+      for (int k = 0; k < 3; ++k) f[k] += P.ppart[b * 3 + k];
+    for (int k = 0; k < 3; ++k) {
+      const double a = -f[k] / P.pert_M;
+      P.pert_a[nxt][k] = a;
+      if (mode == kModeStep) P.pert_v[nxt][k] += 0.5 * dt * a;
+    }
+  }
   P.n_pairs = P.up_off[nxt][P.ns];
   P.parity = nxt;
   if (mode == kModeStep) P.step += 1;
@@ -505,7 +529,8 @@ void launch_setup(hipStream_t st, const PileDev* piles, const WorkItem* wl, int 
 
 void launch_integrate(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                       ContactParams cp, int mode) {
-  hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode);
+  hipLaunchKernelGGL(k_integrate, dim3(nblk), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), wl,
+                     cp, mode);
 }
 
 void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
@@ -521,8 +546,9 @@ void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
   hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode);
 }
 
-void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode) {
-  hipLaunchKernelGGL(k_finish, dim3((n_piles + 63) / 64), dim3(64), 0, st, piles, n_piles, mode);
+void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt) {
+  hipLaunchKernelGGL(k_finish, dim3((n_piles + 63) / 64), dim3(64), 0, st, piles, n_piles, mode,
+                     dt);
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n) {

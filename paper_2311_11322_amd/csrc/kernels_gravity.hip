@@ -263,22 +263,52 @@ __global__ __launch_bounds__(64) void k_grav_tiles(const PileDev* __restrict__ p
 }
 
 // One thread per sorted slot: add the per-tile partials in tile order (FP64)
-// and store the gravity force G m_i sum under the sphere's id.
+// and store the gravity force G m_i sum under the sphere's id.  With a
+// perturber, its unsoftened pull G m_i M d/|d|^3 is added (FP64) and each
+// block stores the sum of its spheres' pulls (the reaction, reduced in block
+// order at the end of the step).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restrict__ piles,
                                                          const WorkItem* __restrict__ wl) {
   const WorkItem w = wl[blockIdx.x];
   const PileDev& P = piles[w.pile];
+  if (P.status != 0 || P.G == 0.0) return;
   const int k = w.base + threadIdx.x;
-  if (k >= P.ns || P.status != 0 || P.G == 0.0) return;
   const int ns = P.ns, nt = P.g_nt;
-  const T* __restrict__ part = (const T*)P.gpart;
-  double g[3] = {0.0, 0.0, 0.0};
-  for (int t = 0; t < nt; ++t)
-    for (int c = 0; c < 3; ++c) g[c] += (double)part[((size_t)t * 3 + c) * ns + k];
-  const uint32_t i = P.sidx[k];
-  const double gm = P.G * P.m[i];
-  for (int c = 0; c < 3; ++c) P.gacc[c * ns + i] = gm * g[c];
+  double pull[3] = {0.0, 0.0, 0.0};
+  if (k < ns) {
+    const T* __restrict__ part = (const T*)P.gpart;
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < nt; ++t)
+      for (int c = 0; c < 3; ++c) g[c] += (double)part[((size_t)t * 3 + c) * ns + k];
+    const uint32_t i = P.sidx[k];
+    const double gm = P.G * P.m[i];
+    for (int c = 0; c < 3; ++c) g[c] *= gm;
+    if (P.pert_on) {
+      const int nxt = P.parity ^ 1;
+      const double d[3] = {P.pert_r[nxt][0] - P.xs[k], P.pert_r[nxt][1] - P.xs[ns + k],
+                           P.pert_r[nxt][2] - P.xs[2 * ns + k]};
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double f = gm * P.pert_M / (r2 * sqrt(r2));
+      for (int c = 0; c < 3; ++c) {
+        pull[c] = f * d[c];
+        g[c] += pull[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) P.gacc[c * ns + i] = g[c];
+  }
+  if (!P.pert_on) return;
+  // block sum of the pulls (fixed order: wave butterflies, then waves 0..3)
+  for (int off = 32; off > 0; off >>= 1)
+    for (int c = 0; c < 3; ++c) pull[c] += __shfl_xor(pull[c], off);
+  __shared__ double red[4][3];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 3; ++c) red[wave][c] = pull[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c)
+      P.ppart[(w.base / kBlock) * 3 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 }  // namespace

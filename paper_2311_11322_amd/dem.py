@@ -66,7 +66,8 @@ class dem_tuning(C.Structure):
 
 
 class dem_forcing(C.Structure):
-    _fields_ = [("spin_dw", C.c_double)]
+    _fields_ = [("spin_dw", C.c_double), ("pert_mass", C.c_double),
+                ("pert_pos", C.c_double * 3), ("pert_vel", C.c_double * 3)]
 
 
 class dem_state(C.Structure):
@@ -98,6 +99,7 @@ def lib():
         L.dem_read_state.argtypes = [vp, C.POINTER(dem_state)]
         L.dem_get_counts.argtypes = [vp, _PI64, _PI64, _PI64]
         L.dem_set_forcing.argtypes = [vp, C.POINTER(dem_forcing)]
+        L.dem_get_forcing.argtypes = [vp, C.POINTER(dem_forcing)]
         L.dem_restore_state.argtypes = [vp, C.POINTER(dem_state)]
         L.dem_reserve_contacts.argtypes = [vp, C.c_int32]
         L.dem_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64, _PI64]
@@ -123,7 +125,8 @@ def lib():
                      "dem_reserve_contacts", "dem_find_contacts", "dem_destroy",
                      "dem_engine_create", "dem_engine_attach", "dem_engine_step",
                      "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
-                     "dem_set_profiling", "dem_get_profile", "dem_set_tuning"):
+                     "dem_set_profiling", "dem_get_profile", "dem_set_tuning",
+                     "dem_get_forcing"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -284,9 +287,17 @@ class Sim:
         st.step = int(ck.get("step", 0))
         _check(lib().dem_restore_state(self.h, C.byref(st)), self.h)
 
-    def set_forcing(self, spin_dw: float):
-        f = dem_forcing(float(spin_dw))
+    def set_forcing(self, spin_dw: float = 0.0, pert_mass: float = 0.0, pert_pos=(0, 0, 0),
+                    pert_vel=(0, 0, 0)):
+        f = dem_forcing(float(spin_dw), float(pert_mass), (C.c_double * 3)(*map(float, pert_pos)),
+                        (C.c_double * 3)(*map(float, pert_vel)))
         _check(lib().dem_set_forcing(self.h, C.byref(f)), self.h)
+
+    def get_forcing(self) -> Dict:
+        f = dem_forcing()
+        _check(lib().dem_get_forcing(self.h, C.byref(f)), self.h)
+        return {"spin_dw": f.spin_dw, "pert_mass": f.pert_mass,
+                "pert_pos": np.array(f.pert_pos[:]), "pert_vel": np.array(f.pert_vel[:])}
 
     def reserve_contacts(self, per_sphere: int):
         _check(lib().dem_reserve_contacts(self.h, int(per_sphere)), self.h)

@@ -25,7 +25,7 @@ from . import dem
 @dataclasses.dataclass
 class Request:
     rid: int
-    kind: str                       # "collapse" or "spinup"
+    kind: str                       # "collapse", "spinup" or "flyby"
     workload: object                # workloads.Workload
     steps: int
     arrival: float                  # seconds after the stream starts
@@ -40,13 +40,35 @@ class Request:
 
 
 def make_sim(w, precision: int, tuning=None, allocator=None, stream=None) -> dem.Sim:
+    """A system for a workload: tuning, forcing (spin-up, perturber), then the
+    aggregates (so the perturber's t0 acceleration is evaluated)."""
     sim = dem.Sim(w.params, precision=precision, allocator=allocator, stream=stream)
     if tuning:
         sim.set_tuning(*tuning)
+    pert = w.params.get("perturber")
+    if w.params.get("spin_dw", 0.0) or pert:
+        if pert:
+            sim.set_forcing(w.params.get("spin_dw", 0.0), pert[0], pert[1], pert[2])
+        else:
+            sim.set_forcing(w.params["spin_dw"])
     sim.add_workload(w)
-    if w.params.get("spin_dw", 0.0):
-        sim.set_forcing(w.params["spin_dw"])
     return sim
+
+
+def add_flyby(w, mass_ratio: float = 1000.0, periapsis_radii: float = 3.0,
+              start_factor: float = 3.0, ecc: float = 2.0) -> None:
+    """Give a pile a tidal perturber: a point mass of ``mass_ratio`` pile
+    masses on an inbound hyperbola (eccentricity ``ecc``) with periapsis
+    ``periapsis_radii`` bulk radii from the pile's centre of mass, starting at
+    ``start_factor`` periapses."""
+    from . import workloads as W
+    M = float(w.mass.sum())
+    com = (w.mass[:, None] * w.pos).sum(0) / M
+    r2 = float((w.mass * ((w.pos - com) ** 2).sum(1)).sum() / M)
+    R = math.sqrt(5.0 / 3.0 * r2)
+    pos, vel = W.flyby_orbit(M, mass_ratio * M, periapsis_radii * R, ecc=ecc,
+                             start_factor=start_factor, G=w.params["G"])
+    w.params["perturber"] = (mass_ratio * M, pos + com, vel)
 
 
 def bulk_radius(sim: dem.Sim) -> float:
@@ -62,8 +84,8 @@ def bulk_radius(sim: dem.Sim) -> float:
 def run_batch(workloads: Sequence, steps: int, precision: int = dem.PREC_FP32_FORCE,
               tuning=None, budget_bytes: int = 1 << 40, warmup: int = 1,
               profile: bool = False) -> Dict:
-    """Step every workload ``steps`` times in one engine; returns timing."""
-    import torch
+    """Step every workload ``steps`` times in one engine; returns timing.
+    dem_engine_step returns after the device work is complete."""
     eng = dem.Engine(budget_bytes)
     sims = [make_sim(w, precision, tuning) for w in workloads]
     for s in sims:
@@ -72,10 +94,8 @@ def run_batch(workloads: Sequence, steps: int, precision: int = dem.PREC_FP32_FO
         code = eng.step(warmup)
         if code != dem.DEM_OK:
             raise dem.DemError(code, "warm-up step failed")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     code = eng.step(steps)
-    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_sph = sum(w.n_sph for w in workloads)
     out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "spheres": n_sph,
@@ -204,7 +224,7 @@ class Server:
 
 def request_stream(seed: int, n_requests: int, rate_per_s: float, nmin: int = 1000,
                    nmax: int = 50000, smin: int = 100, smax: int = 5000,
-                   kinds=("collapse", "spinup"), workers: int = 0) -> List[Request]:
+                   kinds=("collapse", "spinup", "flyby"), workers: int = 0) -> List[Request]:
     """Poisson arrivals at ``rate_per_s``; sphere counts and step counts
     log-uniform; kind uniform.  Inputs are generated up front."""
     from . import workloads as W
@@ -223,4 +243,7 @@ def request_stream(seed: int, n_requests: int, rate_per_s: float, nmin: int = 10
             wl = list(ex.map(W._one_pile, jobs, chunksize=1))
     else:
         wl = [W._one_pile(j) for j in jobs]
+    for k in range(n_requests):
+        if kind[k] == "flyby":
+            add_flyby(wl[k])
     return [Request(k, kind[k], wl[k], int(steps[k]), float(arrivals[k])) for k in range(n_requests)]

@@ -530,6 +530,27 @@ def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 2
     return [_one_pile(j) for j in jobs]
 
 
+def flyby_orbit(M_pile: float, M_pert: float, periapsis: float, ecc: float = 2.0,
+                start_factor: float = 10.0, G: float = 1.0, incline: float = 0.0):
+    """Initial position and velocity (relative to the pile's centre of mass)
+    of a perturber on an inbound hyperbolic orbit of eccentricity ``ecc`` and
+    the given periapsis, starting at ``start_factor`` x periapsis.  Two-body
+    relation for the relative orbit, G (M_pile + M_pert)."""
+    mu = G * (M_pile + M_pert)
+    a = periapsis / (ecc - 1.0)                 # |semi-major axis| of the hyperbola
+    p = a * (ecc * ecc - 1.0)                   # semi-latus rectum
+    r = start_factor * periapsis
+    nu = -math.acos((p / r - 1.0) / ecc)        # inbound branch
+    h = math.sqrt(mu * p)
+    pos = np.array([r * math.cos(nu), r * math.sin(nu), 0.0])
+    vel = (mu / h) * np.array([-math.sin(nu), ecc + math.cos(nu), 0.0])
+    if incline:
+        c, s_ = math.cos(incline), math.sin(incline)
+        rot = np.array([[1, 0, 0], [0, c, -s_], [0, s_, c]])
+        pos, vel = rot @ pos, rot @ vel
+    return pos, vel
+
+
 def subset(w: Workload, n_agg: int) -> Workload:
     """First ``n_agg`` aggregates of a workload (for reduced-size checks)."""
     off = w.offsets()

@@ -120,6 +120,27 @@ def test_fp32_force_form_parity(D):
     assert rel_err(g["agg_pos"], o.aggregates()["rA"]) <= 1e-12
 
 
+def test_flyby_perturber_parity(D):
+    """A point-mass perturber passing a contact-seeded cloud: state and the
+    perturber's own position and velocity agree with the oracle."""
+    say("flyby perturber n_agg=200")
+    from paper_2311_11322_amd import serve
+    w = W.collapse_cloud(47, n_agg=200, contact_seeded=True, spin_sigma=0.2, vel_sigma=0.05)
+    serve.add_flyby(w, start_factor=1.2)
+    Mp, rp, vp = w.params["perturber"]
+    sim = serve.make_sim(w, D.PREC_FP64)
+    o = O.Oracle(w.params).set_perturber(Mp, rp, vp).add_workload(w)
+    compare_states(sim, o)
+    for n in (1, 3):
+        sim.step(n)
+        o.step(n)
+        compare_states(sim, o, tol=1e-12 if n == 1 else 1e-10)
+        f = sim.get_forcing()
+        orp, ovp, _ = o.perturber()
+        assert rel_err(f["pert_pos"], orp) <= 1e-13
+        assert rel_err(f["pert_vel"], ovp) <= 1e-12
+
+
 def test_lone_spheres_and_large_aggregate(D):
     """Degenerate cases: 1-sphere aggregates (I = 2/5 m s^2) beside one
     155-sphere aggregate spanning several blocks."""

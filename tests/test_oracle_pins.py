@@ -554,3 +554,55 @@ def test_bulk_radius_of_uniform_ball():
     prm = dict(W.CONTACT_PARAMS, dt=1e-3, G=0.0, soft_frac=0.5, periodic=0, box=(0, 0, 0))
     o = O.Oracle(prm).add([1] * len(p), p, rad, W.sphere_mass(rad))
     assert o.diagnostics()["R_bulk"] == pytest.approx(10.0, rel=2e-2)
+
+
+# ---------------------------------------------------------------------------
+# point-mass perturber (tidal flyby)
+# ---------------------------------------------------------------------------
+
+def _kepler_pair(h_frac):
+    G, m, Mp, d = 1.0, 4.0, 12.0, 30.0
+    v = math.sqrt(G * (m + Mp) / d)
+    T = 2 * math.pi * math.sqrt(d ** 3 / (G * (m + Mp)))
+    h = T * h_frac
+    prm = dict(W.CONTACT_PARAMS, dt=h, G=G, soft_frac=0.5, periodic=0, box=(0, 0, 0))
+    o = O.Oracle(prm)
+    o.set_perturber(Mp, [d * m / (m + Mp), 0, 0], [0, v * m / (m + Mp), 0])
+    o.add([1], [[-d * Mp / (m + Mp), 0, 0]], [0.5], [m], [[0, -v * Mp / (m + Mp), 0]])
+    P0 = m * o.aggregates()["vA"][0] + Mp * o.perturber()[1]
+    o.step(int(round(1.0 / h_frac)))
+    rp, vp, _ = o.perturber()
+    P1 = m * o.aggregates()["vA"][0] + Mp * vp
+    return np.linalg.norm(rp - [d * m / (m + Mp), 0, 0]) / d, np.abs(P1 - P0).max()
+
+
+def test_perturber_two_body_orbit_and_momentum():
+    """A lone sphere and the perturber on a circular orbit about their common
+    centre of mass return after one period (second order); total momentum
+    (spheres + perturber) is conserved to rounding."""
+    e1, dp1 = _kepler_pair(1 / 400)
+    e2, dp2 = _kepler_pair(1 / 800)
+    assert e1 < 5e-3 and e1 / e2 > 3.0
+    assert dp1 < 1e-12 and dp2 < 1e-12
+
+
+def test_flyby_orbit_reaches_its_periapsis():
+    """The inbound hyperbolic initial condition (e = 2) passes a point-like
+    pile at the requested periapsis."""
+    G, m, Mp, q = 1.0, 1.0, 1000.0, 10.0
+    pos, vel = W.flyby_orbit(m, Mp, q, ecc=2.0, start_factor=10.0, G=G)
+    h = 2e-3
+    prm = dict(W.CONTACT_PARAMS, dt=h, G=G, soft_frac=0.5, periodic=0, box=(0, 0, 0))
+    # the pile is at rest at the origin, the perturber carries the relative
+    # velocity; move to the centre-of-mass frame so the relative orbit holds
+    vc = Mp * vel / (m + Mp)
+    rc = Mp * pos / (m + Mp)
+    o = O.Oracle(prm)
+    o.set_perturber(Mp, pos - rc, vel - vc)
+    o.add([1], [-rc], [0.5], [m], [-vc])
+    dmin = np.inf
+    for _ in range(600):
+        o.step(10)
+        rp = o.perturber()[0]
+        dmin = min(dmin, np.linalg.norm(rp - o.aggregates()["rA"][0]))
+    assert dmin == pytest.approx(q, rel=2e-3)
