@@ -221,6 +221,26 @@ def extra_runs(args, w, out, prec):
                              "gravity_ms": round(g_ms, 4),
                              "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
         log(f"fp32-force: {out['fp32_force']}")
+    # -- the paper's efficiency experiment: original (full-scan) vs improved
+    #    (contiguous) member search, on its collapse shape (2e4 spheres)
+    wa = W.collapse_cloud(seed=5, n_agg=4444, cmin=1, cmax=8)
+    abl = {}
+    for scan in (0, 1):
+        sa = dem.Sim(wa.params)
+        sa.set_tuning(0, 1.0, scan)
+        sa.add_workload(wa)
+        sa.step(2)
+        sa.set_profiling(True)
+        wall = timed_steps(sa, 10)
+        pa = sa.profile()
+        sa.close()
+        abl[scan] = (1e3 * wall / 10, pa["reduce"] / pa["_steps"])
+    out["member_search_ablation"] = {
+        "workload": f"collapse, {wa.n_agg} aggregates of 1-8 spheres ({wa.n_sph} spheres), FP64",
+        "improved_ms_per_step": round(abl[0][0], 4), "original_ms_per_step": round(abl[1][0], 4),
+        "improved_reduce_ms": round(abl[0][1], 4), "original_reduce_ms": round(abl[1][1], 4),
+        "speedup": round(abl[1][0] / abl[0][0], 3)}
+    log(f"member search ablation: {out['member_search_ablation']}")
     # -- batched spin-up piles
     t = time.time()
     piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)

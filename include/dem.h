@@ -215,6 +215,10 @@ dem_status dem_sim_status(const dem_sim* sim);
 typedef struct {
     int32_t gravity_tile;
     double cell_scale;
+    int32_t member_scan;       /* 1: GetAccelAndTorque finds each aggregate's members by a
+                                  full scan of the sphere list, as the paper's original
+                                  routines did (Sec. 3.1); 0: contiguous member segments
+                                  (the paper's improvement).  Same results, different cost. */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them

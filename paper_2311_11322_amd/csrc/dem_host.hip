@@ -227,7 +227,7 @@ struct dem_sim {
   dem_engine* engine = nullptr;
   int engine_slot = -1;
   dem_status last_status = DEM_OK;
-  dem_tuning tune{0, 1.0};
+  dem_tuning tune{0, 1.0, 0};
   // per-kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -489,6 +489,7 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.cap_pairs = (int32_t)s->sz.cap;
   h.bits = choose_bits(ns);
   h.periodic = s->prm.periodic ? 1 : 0;
+  h.member_scan = s->tune.member_scan;
   h.g_tile = (int32_t)s->sz.g_tile;
   h.g_nt = (int32_t)s->sz.g_nt;
   h.n_rblk = (int32_t)s->sz.n_rblk;
@@ -1045,6 +1046,8 @@ dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
     return fail(s, DEM_ERR_INVALID_ARG, "unsupported gravity tile size");
   if (!(t->cell_scale >= 1.0) || !std::isfinite(t->cell_scale))
     return fail(s, DEM_ERR_INVALID_ARG, "cell_scale must be finite and >= 1");
+  if (t->member_scan != 0 && t->member_scan != 1)
+    return fail(s, DEM_ERR_INVALID_ARG, "member_scan must be 0 or 1");
   s->tune = *t;
   return DEM_OK;
 }

@@ -55,6 +55,8 @@ struct PileDev {
   int32_t g_nt;              // gravity tiles
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
   int32_t nb_periodic;       // cells per axis = 1 << nb_periodic for a periodic pile
+  int32_t member_scan;       // 1: reduction finds members by scanning all spheres
+  int32_t pad2;
   double box;                // periodic cube side
   double G, soft_frac, spin_dw;
   double cell_min;           // largest sphere diameter of the pile

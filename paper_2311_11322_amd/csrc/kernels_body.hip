@@ -429,9 +429,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
   for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
   quat_rot(q, R);
   double FA[3] = {0.0, 0.0, 0.0}, NA[3] = {0.0, 0.0, 0.0};
-  const int i0 = P.first[A], n = P.count[A];
   const bool grav = P.G != 0.0;
-  for (int i = i0; i < i0 + n; ++i) {
+  // members: the contiguous segment, or (ablation of the paper's original
+  // routines) every sphere of the pile tested for membership in order
+  const bool scan = P.member_scan != 0;
+  const int i_lo = scan ? 0 : P.first[A];
+  const int i_hi = scan ? ns : P.first[A] + P.count[A];
+  for (int i = i_lo; i < i_hi; ++i) {
+    if (scan && P.agg[i] != A) continue;
     double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
     for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
       const uint32_t p = P.lo_pair[e];

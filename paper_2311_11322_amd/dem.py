@@ -62,7 +62,8 @@ class dem_allocator(C.Structure):
 
 
 class dem_tuning(C.Structure):
-    _fields_ = [("gravity_tile", C.c_int32), ("cell_scale", C.c_double)]
+    _fields_ = [("gravity_tile", C.c_int32), ("cell_scale", C.c_double),
+                ("member_scan", C.c_int32)]
 
 
 class dem_forcing(C.Structure):
@@ -305,8 +306,8 @@ class Sim:
     def status(self) -> int:
         return int(lib().dem_sim_status(self.h))
 
-    def set_tuning(self, gravity_tile: int = 0, cell_scale: float = 1.0):
-        t = dem_tuning(int(gravity_tile), float(cell_scale))
+    def set_tuning(self, gravity_tile: int = 0, cell_scale: float = 1.0, member_scan: int = 0):
+        t = dem_tuning(int(gravity_tile), float(cell_scale), int(member_scan))
         _check(lib().dem_set_tuning(self.h, C.byref(t)), self.h)
 
     def set_profiling(self, on: bool):

@@ -330,3 +330,20 @@ def test_engine_alone_vs_mix_bit_identical(D):
         got = s.read_state(pairs=True)
         for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "pair_hist", "sph_force"):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
+
+
+def test_member_scan_ablation_gives_identical_results(D):
+    """The paper's original member search (full scan per aggregate) and its
+    improvement (contiguous segments) give bit-identical states."""
+    say("member scan ablation")
+    w = W.collapse_cloud(61, n_agg=400, contact_seeded=True, spin_sigma=0.2)
+    out = []
+    for scan in (0, 1):
+        sim = D.Sim(w.params)
+        sim.set_tuning(0, 1.0, scan)
+        sim.add_workload(w)
+        sim.step(3)
+        out.append(sim.read_state(pairs=True))
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
