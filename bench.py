@@ -29,6 +29,12 @@ sys.path.insert(0, ROOT)
 METRIC = "sphere-steps/sec at 125k spheres (plain vs FP32-force batched); p50/p99 run latency"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}     # MI355X vector peaks
 GRAVITY_FLOP_PER_PAIR = 20                      # 3 sub, 3 fma, rsqrt, 2 mul, 1 mul, 3 fma
+PEAK_HBM_GBS = 8000.0                           # MI355X HBM3E
+# algorithmic bytes of the contact path per sphere-step: about 390 B for the
+# aggregate update, reconstruction, binning, search and force-side reads, plus
+# 64 B per contact of the sphere (keys and FP64 spring history, read and written)
+CONTACT_BYTES_FIXED = 390
+CONTACT_BYTES_PER_CONTACT = 64
 
 
 # HBM traffic of the gravity stage per launch (bytes), from rocprofv3 --pmc
@@ -221,6 +227,32 @@ def extra_runs(args, w, out, prec):
                              "gravity_ms": round(g_ms, 4),
                              "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
         log(f"fp32-force: {out['fp32_force']}")
+    # -- contact path on a contact-dense workload (HBM-bound kernels)
+    wl = W.dense_lattice(n_side=50)
+    sl = dem.Sim(wl.params)
+    sl.add_workload(wl)
+    sl.step(2)
+    sl.set_profiling(True)
+    wall = timed_steps(sl, args.steps)
+    pl = sl.profile()
+    n_pairs = sl.counts()[2]
+    sl.close()
+    contact_ms = sum(v for k, v in pl.items() if not k.startswith("_") and k != "gravity") / pl["_steps"]
+    zbar = 2.0 * n_pairs / wl.n_sph
+    bytes_per_sphere = CONTACT_BYTES_FIXED + CONTACT_BYTES_PER_CONTACT * zbar
+    gbs = bytes_per_sphere * wl.n_sph / (contact_ms * 1e-3) / 1e9
+    out["contact_path"] = {
+        "workload": f"periodic lattice of {wl.n_sph} unit spheres (dumbbells + lone), "
+                    f"{n_pairs} contacts (z = {zbar:.2f}), FP64, no gravity",
+        "value": round(wl.n_sph * args.steps / wall, 1), "unit": "sphere-steps/s",
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "kernel_ms_per_step": {k: round(v / pl["_steps"], 4) for k, v in pl.items()
+                               if not k.startswith("_") and k != "gravity"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "algorithmic": f"{CONTACT_BYTES_FIXED} B + {CONTACT_BYTES_PER_CONTACT} B x "
+                                    f"z per sphere-step over all contact-path kernels"}}
+    log(f"contact path: {out['contact_path']}")
     # -- the paper's efficiency experiment: original (full-scan) vs improved
     #    (contiguous) member search, on its collapse shape (2e4 spheres)
     wa = W.collapse_cloud(seed=5, n_agg=4444, cmin=1, cmax=8)

@@ -551,6 +551,41 @@ def flyby_orbit(M_pile: float, M_pert: float, periapsis: float, ecc: float = 2.0
     return pos, vel
 
 
+def dense_lattice(seed: int = 6, n_side: int = 50, spacing: float = 1.999,
+                  jitter: float = 2e-4, dt: float = 1e-4, vel_sigma: float = 0.01,
+                  n_steps: int = 100) -> Workload:
+    """Contact-dense periodic workload: unit spheres on a jittered cubic
+    lattice whose spacing is slightly below a diameter, so every sphere
+    overlaps its six neighbours; lattice neighbours along x are bonded in
+    pairs (dumbbells), the rest are lone spheres.  Used to measure the
+    contact path, where memory traffic rather than arithmetic dominates."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n_side) * spacing
+    p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    p = p + rng.uniform(-jitter, jitter, p.shape) + 0.5 * spacing
+    ix = np.arange(n_side)
+    # pair (x even, x odd) into dumbbells when n_side is even; lone otherwise
+    counts, order = [], []
+    idx = np.arange(p.shape[0]).reshape(n_side, n_side, n_side)
+    for a in range(0, n_side - 1, 2):
+        pairs = np.stack([idx[a].ravel(), idx[a + 1].ravel()], 1)
+        order.append(pairs.ravel())
+        counts += [2] * pairs.shape[0]
+    if n_side % 2:
+        order.append(idx[n_side - 1].ravel())
+        counts += [1] * (n_side * n_side)
+    order = np.concatenate(order)
+    pos = p[order]
+    radius = np.ones(pos.shape[0])
+    n_agg = len(counts)
+    L = n_side * spacing
+    params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=1, box=(L, L, L))
+    return Workload("dense_lattice", np.asarray(counts, dtype=np.int32), pos, radius,
+                    sphere_mass(radius), rng.normal(0.0, vel_sigma, (n_agg, 3)),
+                    np.zeros((n_agg, 3)), params, n_steps,
+                    notes=f"periodic lattice {n_side}^3 spacing {spacing}, seed {seed}")
+
+
 def subset(w: Workload, n_agg: int) -> Workload:
     """First ``n_agg`` aggregates of a workload (for reduced-size checks)."""
     off = w.offsets()

@@ -347,3 +347,20 @@ def test_member_scan_ablation_gives_identical_results(D):
         sim.close()
     for k in out[0]:
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_dense_lattice_parity(D):
+    """Contact-dense periodic lattice (five contacts per sphere): one and
+    three steps against the oracle."""
+    say("dense lattice 10^3")
+    w = W.dense_lattice(n_side=10)
+    L = w.params["box"][0]
+    sim, o = _pair(D, w)
+    compare_states(sim, o, box=L)
+    assert sim.counts()[2] == 2500
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o, box=L)
+    sim.step(2)
+    o.step(2)
+    compare_states(sim, o, box=L, tol=1e-10)
