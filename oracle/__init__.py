@@ -30,6 +30,9 @@ class Params(C.Structure):
         ("k_r", C.c_double), ("k_q", C.c_double),
         ("periodic", C.c_int32), ("box", C.c_double * 3),
         ("spin_dw", C.c_double), ("torque_at_centre", C.c_int32),
+        ("g", C.c_double * 3), ("n_walls", C.c_int32), ("wall", (C.c_double * 4) * 6),
+        ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
+        ("shake_phase", C.c_double),
     ]
 
 
@@ -89,6 +92,19 @@ def make_params(d: Dict) -> Params:
         p.box[c] = float(box[c])
     p.spin_dw = float(d.get("spin_dw", 0.0))
     p.torque_at_centre = int(d.get("torque_at_centre", 0))
+    g = d.get("g", (0.0, 0.0, 0.0))
+    for c in range(3):
+        p.g[c] = float(g[c])
+    walls = d.get("walls", ())
+    p.n_walls = len(walls)
+    amp = d.get("shake_amp", ())
+    for w, wl in enumerate(walls):
+        for c in range(4):
+            p.wall[w][c] = float(wl[c])
+        for c in range(3):
+            p.shake_amp[w][c] = float(amp[w][c]) if len(amp) else 0.0
+    p.shake_omega = float(d.get("shake_omega", 0.0))
+    p.shake_phase = float(d.get("shake_phase", 0.0))
     return p
 
 
@@ -171,8 +187,8 @@ class Oracle:
         o = np.zeros(16)
         lib().ora_diagnostics(self._h, _p(o))
         return dict(P=o[0:3].copy(), L=o[3:6].copy(), Kt=o[6], Kr=o[7], Es=o[8], Ug=o[9],
-                    max_overlap=o[10], R_bulk=o[11], com=o[12:15].copy(),
-                    E=o[6] + o[7] + o[8] + o[9])
+                    max_overlap=o[10], R_bulk=o[11], com=o[12:15].copy(), Uu=o[15],
+                    E=o[6] + o[7] + o[8] + o[9] + o[15])
 
     def eval_subset(self, idx):
         idx = np.ascontiguousarray(idx, dtype=np.int64)

@@ -54,6 +54,9 @@ struct ora_sim {
     double *hist;   /* 7 per pair */
     double *pforce; /* 9 per pair */
     double *pdiag;  /* 8 per pair */
+    /* time of the current evaluation (walls move with it) */
+    double t_eval;
+    int64_t steps;
     /* point-mass perturber */
     int pert_on;
     double pert_M, pert_r[3], pert_v[3], pert_a[3];
@@ -412,11 +415,30 @@ static void push_pair(ora_sim* s, int64_t i, int64_t j)
     s->np++;
 }
 
+/* Wall w at time t: signed distance of point x from the plane n.x = d
+ * displaced by A sin(omega t + phase), summed as ((n0 x0 + n1 x1) + n2 x2)
+ * - (d + n.A sin(.)); and the wall's velocity. */
+static double wall_distance(const ora_params* p, int w, double t, const double* x, double* vel)
+{
+    const double* n = p->wall[w];
+    const double* A = p->shake_amp[w];
+    double ph = p->shake_omega * t + p->shake_phase;
+    double sn = sin(ph), cs = cos(ph);
+    double shift = (n[0] * A[0] + n[1] * A[1]) + n[2] * A[2];
+    int c;
+    if (vel)
+        for (c = 0; c < 3; c++) vel[c] = A[c] * p->shake_omega * cs;
+    return ((n[0] * x[0] + n[1] * x[1]) + n[2] * x[2]) - (n[3] + shift * sn);
+}
+
 /* Brute-force search over all i<j (lexicographic order); spheres of the
- * same aggregate never form a contact. */
+ * same aggregate never form a contact.  Walls follow the spheres as
+ * partners n_sph + w: sphere i touches wall w iff its centre is closer to the
+ * plane than its radius (strict). */
 static void find_pairs(ora_sim* s)
 {
     int64_t i, j;
+    int w;
     s->np = 0;
     for (i = 0; i < s->ns; i++) {
         for (j = i + 1; j < s->ns; j++) {
@@ -424,6 +446,10 @@ static void find_pairs(ora_sim* s)
             if (s->agg[i] == s->agg[j]) continue;
             separation(&s->p, &s->r[3 * i], &s->r[3 * j], d);
             if (in_contact(d, s->s[i], s->s[j])) push_pair(s, i, j);
+        }
+        for (w = 0; w < s->p.n_walls; w++) {
+            if (wall_distance(&s->p, w, s->t_eval, &s->r[3 * i], NULL) < s->s[i])
+                push_pair(s, i, s->ns + w);
         }
     }
 }
@@ -461,31 +487,54 @@ static void pair_force(const ora_sim* s, int64_t i, int64_t j, const double* h_o
 {
     const ora_params* p = &s->p;
     const double h = p->dt;
+    const int wall = j >= s->ns;
     int c;
-    double d[3], n[3];
-    separation(p, &s->r[3 * i], &s->r[3 * j], d);
-    double dist = sqrt(dot(d, d));
-    for (c = 0; c < 3; c++) n[c] = d[c] / dist;
-    double si = s->s[i], sj = s->s[j];
-    double delta = (si + sj) - dist;
-    double li = (si * si - sj * sj + dist * dist) / (2.0 * dist);
-    double lj = dist - li;
-
-    int64_t Ai = s->agg[i], Aj = s->agg[j];
+    double d[3], n[3], dist, delta, li, lj, si = s->s[i], sj, Rij, mu;
+    double vj[3], wj_zero[3] = {0.0, 0.0, 0.0};
+    const double* wj;
+    int64_t Ai = s->agg[i];
     const double* wi = &s->wA[3 * Ai];
-    const double* wj = &s->wA[3 * Aj];
+    if (wall) {
+        /* sphere against a plane: the partner is the wall (infinite mass, no
+         * spin); the contact point is the foot of the perpendicular, so the
+         * lever arm is the centre's distance from the plane, and the normal
+         * points from the sphere into the wall */
+        int w = (int)(j - s->ns);
+        dist = wall_distance(p, w, s->t_eval, &s->r[3 * i], vj);
+        for (c = 0; c < 3; c++) n[c] = -p->wall[w][c];
+        delta = si - dist;
+        li = dist;
+        lj = 0.0;
+        sj = 0.0;
+        wj = wj_zero;
+        mu = s->M[Ai];
+        Rij = si;
+    } else {
+        separation(p, &s->r[3 * i], &s->r[3 * j], d);
+        dist = sqrt(dot(d, d));
+        for (c = 0; c < 3; c++) n[c] = d[c] / dist;
+        sj = s->s[j];
+        delta = (si + sj) - dist;
+        li = (si * si - sj * sj + dist * dist) / (2.0 * dist);
+        lj = dist - li;
+        int64_t Aj = s->agg[j];
+        wj = &s->wA[3 * Aj];
+        for (c = 0; c < 3; c++) vj[c] = s->v[3 * j + c];
+        double MA = s->M[Ai], MB = s->M[Aj];
+        mu = MA * MB / (MA + MB);
+        Rij = si * sj / (si + sj);
+    }
+
     double arm_i[3], arm_j[3], t1[3], t2[3], u[3];
     for (c = 0; c < 3; c++) { arm_i[c] = li * n[c]; arm_j[c] = -lj * n[c]; }
     cross(wi, arm_i, t1);
     cross(wj, arm_j, t2);
     for (c = 0; c < 3; c++)
-        u[c] = (s->v[3 * j + c] + t2[c]) - (s->v[3 * i + c] + t1[c]);
+        u[c] = (vj[c] + t2[c]) - (s->v[3 * i + c] + t1[c]);
     double un = dot(u, n);
     double ut[3];
     for (c = 0; c < 3; c++) ut[c] = u[c] - un * n[c];
 
-    double MA = s->M[Ai], MB = s->M[Aj];
-    double mu = MA * MB / (MA + MB);
     double Cn = dashpot(p->k_n, mu, p->eps_n);
     double Ct = dashpot(p->k_t, mu, p->eps_t);
 
@@ -509,8 +558,7 @@ static void pair_force(const ora_sim* s, int64_t i, int64_t j, const double* h_o
         for (c = 0; c < 3; c++) FT[c] = p->k_t * xt[c] + Ct * ut[c];
     }
 
-    /* rolling */
-    double Rij = si * sj / (si + sj);
+    /* rolling (lever R_ij = s_i s_j/(s_i+s_j); s_i against a wall) */
     double dw[3], dwxn[3], xr[3];
     for (c = 0; c < 3; c++) dw[c] = wj[c] - wi[c];
     cross(dw, n, dwxn);
@@ -680,8 +728,10 @@ static void evaluate(ora_sim* s, int carry_history)
         for (c = 0; c < 3; c++) {
             s->F[3 * ii + c] += f[c];
             s->tau[3 * ii + c] += f[3 + c];
-            s->F[3 * jj + c] -= f[c];
-            s->tau[3 * jj + c] += f[6 + c];
+            if (jj < s->ns) {             /* a wall takes the reaction */
+                s->F[3 * jj + c] -= f[c];
+                s->tau[3 * jj + c] += f[6 + c];
+            }
         }
     }
     /* self-gravity, Eq. 4, every j != i including members of the same
@@ -724,8 +774,9 @@ static void evaluate(ora_sim* s, int carry_history)
                 NA[c] += dxF[c] + s->tau[3 * i + c];
             }
         }
+        /* a uniform field adds g to every body and no torque */
         for (c = 0; c < 3; c++) {
-            s->aA[3 * A + c] = FA[c] / s->M[A];
+            s->aA[3 * A + c] = FA[c] / s->M[A] + s->p.g[c];
             s->NA[3 * A + c] = NA[c];
         }
     }
@@ -863,7 +914,9 @@ static void step_once(ora_sim* s)
         ora_rotate(&s->q[4 * A], &s->wb[3 * A], &s->I[3 * A], &s->NA[3 * A], h, NULL);
     /* member positions and predicted velocities (Eq. 3) */
     reconstruct(s, 0.5 * h);
+    s->t_eval = (double)(s->steps + 1) * h;
     evaluate(s, 1);
+    s->steps++;
     /* second half kick */
     for (A = 0; A < s->na; A++)
         for (c = 0; c < 3; c++) s->vA[3 * A + c] += 0.5 * h * s->aA[3 * A + c];
@@ -970,9 +1023,13 @@ void ora_diagnostics(ora_sim* s, double* out)
         r2 += s->m[i] * dot(d, d);
     }
     r2 /= Mt;
+    /* potential of the uniform field: -sum_A M_A g . r_A */
+    double Uu = 0.0;
+    for (A = 0; A < s->na; A++) Uu -= s->M[A] * dot(s->p.g, &s->rA[3 * A]);
     for (c = 0; c < 3; c++) { out[c] = P[c]; out[3 + c] = L[c]; out[12 + c] = com[c]; }
     out[6] = Kt; out[7] = Kr; out[8] = Es; out[9] = Ug; out[10] = maxov;
     out[11] = sqrt(5.0 / 3.0 * r2);
+    out[15] = Uu;
 }
 
 void ora_eval_subset(const ora_sim* s, const int64_t* idx, int64_t n_idx, double* F, double* tau)
@@ -1003,6 +1060,15 @@ void ora_eval_subset(const ora_sim* s, const int64_t* idx, int64_t n_idx, double
                              s->s[x], s->s[j], acc);
             }
             for (c = 0; c < 3; c++) f[c] += acc[c];
+        }
+        {
+            int w;
+            for (w = 0; w < s->p.n_walls; w++) {
+                double hz[7] = {0, 0, 0, 0, 0, 0, 0}, hn[7], o9[9];
+                if (!(wall_distance(&s->p, w, s->t_eval, &s->r[3 * x], NULL) < s->s[x])) continue;
+                pair_force(s, x, s->ns + w, hz, hn, o9, NULL);
+                for (c = 0; c < 3; c++) { f[c] += o9[c]; t[c] += o9[3 + c]; }
+            }
         }
         if (s->pert_on) perturber_pull(s, x, f);
         for (c = 0; c < 3; c++) { F[3 * k + c] = f[c]; tau[3 * k + c] = t[c]; }

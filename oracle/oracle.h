@@ -31,6 +31,14 @@ typedef struct {
     double spin_dw;     /* spin-up forcing: spin increment per step about +z      */
     int32_t torque_at_centre; /* negative control only: apply contact forces at
                                  sphere centres instead of the contact point       */
+    /* box-filling and shaking workloads: uniform acceleration on every body,
+     * and up to 6 planar walls n.x = d (unit n pointing into the domain),
+     * displaced rigidly by A_w sin(omega t + phase) */
+    double g[3];
+    int32_t n_walls;
+    double wall[6][4];
+    double shake_amp[6][3];
+    double shake_omega, shake_phase;
 } ora_params;
 
 typedef struct ora_sim ora_sim;
@@ -54,7 +62,8 @@ void ora_get_aggregates(const ora_sim* s, double* M, double* rA, double* vA, dou
                         double* NA, double* q, double* wb, double* wA, double* I);
 void ora_get_spheres(const ora_sim* s, double* r, double* v, double* F, double* tau,
                      double* body);
-/* Per-pair output of the last evaluation, canonical (i<j, lexicographic).
+/* Per-pair output of the last evaluation, canonical (i<j, lexicographic);
+ * a contact of sphere i with wall w has j = n_sph + w.
  * hist: 7 per pair (xi_t[3], xi_r[3], xi_q).  force: F on i[3], tau_i[3],
  * tau_j[3].  diag: f_N, |F_T|, |F_r|, |F_q|, delta, l_i, l_j, sliding flag. */
 void ora_get_pairs(const ora_sim* s, int64_t* pi, int64_t* pj, double* hist,
@@ -70,7 +79,8 @@ void ora_get_perturber(const ora_sim* s, double* pos, double* vel, double* acc);
 /* Diagnostics of the current state: out[0..2] linear momentum, out[3..5]
  * angular momentum about the origin, out[6] translational KE, out[7]
  * rotational KE, out[8] normal spring energy, out[9] gravitational energy,
- * out[10] max overlap, out[11] bulk radius, out[12..14] centre of mass. */
+ * out[10] max overlap, out[11] bulk radius, out[12..14] centre of mass,
+ * out[15] potential of the uniform field. */
 void ora_diagnostics(ora_sim* s, double* out);
 
 /* Forces and torques on a subset of spheres at the current state, evaluated
