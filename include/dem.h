@@ -70,6 +70,20 @@ typedef struct {
                                         contacts per sphere on average; <= 0: 8 */
     double max_overlap_frac;   /* > 0: overlap above this fraction of the smaller radius is
                                   an instability (DEM_ERR_UNSTABLE); <= 0: no check */
+    /* Container and uniform field of the box-filling and shaking workloads
+     * (Sec. 3.2 profiling runs, Sec. 4.3 Brazil-nut runs).  g is added to the
+     * acceleration of every body.  Wall w is the plane n.x = d with
+     * walls[w] = {n_x, n_y, n_z, d}, n a unit normal pointing into the domain,
+     * displaced rigidly by shake_amp[w] * sin(shake_omega * t + shake_phase)
+     * at time t = step * dt.  A wall is a contact partner of infinite mass
+     * and no spin under the same contact model as a sphere pair; the contact
+     * of sphere i with wall w has the key i * 2^32 + (n_sph + w).  Walls need
+     * an open system (periodic == 0). */
+    double g[3];
+    int32_t n_walls;           /* 0 .. 6 */
+    double walls[6][4];
+    double shake_amp[6][3];
+    double shake_omega, shake_phase;
 } dem_params;
 
 typedef struct {

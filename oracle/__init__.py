@@ -134,6 +134,7 @@ class Oracle:
                            _p(mass), _p(v), _p(w), int(bool(evaluate)))
         if rc != 0:
             raise ValueError("ora_add rejected the input")
+        self.agg_counts = counts.copy()
         return self
 
     def add_workload(self, w, evaluate=True):

@@ -364,7 +364,7 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(1);
   launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(2);
-  launch_grid(st, b.d_table, np);
+  launch_grid(st, b.d_table, np, mode, b.cp.dt);
   mark(3);
   launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(4);
@@ -444,6 +444,22 @@ dem_status valid_params(const dem_params* p, std::string* why) {
   }
   if (p->precision != DEM_PREC_FP64 && p->precision != DEM_PREC_FP32_FORCE)
     return bad("unknown precision");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(p->g[k])) return bad("non-finite uniform field");
+  if (p->n_walls < 0 || p->n_walls > 6) return bad("n_walls must be in 0..6");
+  if (p->n_walls > 0 && p->periodic) return bad("walls need an open (non-periodic) system");
+  if (!std::isfinite(p->shake_omega) || !std::isfinite(p->shake_phase))
+    return bad("non-finite shaking frequency or phase");
+  for (int w = 0; w < p->n_walls; ++w) {
+    double nn = 0.0;
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(p->walls[w][k])) return bad("non-finite wall");
+    for (int k = 0; k < 3; ++k) {
+      if (!std::isfinite(p->shake_amp[w][k])) return bad("non-finite shaking amplitude");
+      nn += p->walls[w][k] * p->walls[w][k];
+    }
+    if (!(std::fabs(std::sqrt(nn) - 1.0) <= 1e-12)) return bad("wall normal must be a unit vector");
+  }
   return DEM_OK;
 }
 
@@ -497,6 +513,14 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.G = s->prm.G;
   h.soft_frac = s->prm.softening_frac;
   h.spin_dw = s->forcing.spin_dw;
+  h.n_walls = s->prm.n_walls;
+  for (int k = 0; k < 3; ++k) h.gfield[k] = s->prm.g[k];
+  for (int w = 0; w < 6; ++w) {
+    for (int k = 0; k < 4; ++k) h.wall[w][k] = w < h.n_walls ? s->prm.walls[w][k] : 0.0;
+    for (int k = 0; k < 3; ++k) h.wall_amp[w][k] = w < h.n_walls ? s->prm.shake_amp[w][k] : 0.0;
+  }
+  h.wall_omega = s->prm.shake_omega;
+  h.wall_phase = s->prm.shake_phase;
   h.pert_on = s->forcing.pert_mass > 0.0 ? 1 : 0;
   h.pert_M = s->forcing.pert_mass;
   for (int k = 0; k < 3; ++k) {
@@ -1145,7 +1169,7 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
   if (r != DEM_OK) return fail(nullptr, r, s->err);
   Batch& b = s->own;
   launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  launch_grid(st, b.d_table, 1);
+  launch_grid(st, b.d_table, 1, kModeInit, 1.0);
   launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells);
   launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);

@@ -43,6 +43,9 @@ struct Grid {
   double com[3];             // centre of mass of the pile (spin-up forcing)
   int32_t nb;                // cells per axis = 1 << nb
   int32_t pad;
+  double t;                  // time of this evaluation
+  double wall_d[6];          // plane offset of each wall at time t
+  double wall_v[6][3];       // velocity of each wall at time t
 };
 
 struct PileDev {
@@ -60,6 +63,13 @@ struct PileDev {
   double box;                // periodic cube side
   double G, soft_frac, spin_dw;
   double cell_min;           // largest sphere diameter of the pile
+  // uniform field and container walls (host-set)
+  int32_t n_walls;
+  int32_t pad3;
+  double gfield[3];
+  double wall[6][4];         // unit normal (into the domain), offset
+  double wall_amp[6][3];     // rigid sinusoidal displacement amplitude
+  double wall_omega, wall_phase;
 
   // device-updated bookkeeping
   int32_t parity;            // which half of each ping-pong pair is current
@@ -166,7 +176,7 @@ void launch_setup(hipStream_t st, const PileDev* piles, const WorkItem* wl, int 
 void launch_integrate(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                       ContactParams cp, int mode);
 void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
-void launch_grid(hipStream_t st, const PileDev* piles, int n_piles);
+void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, double dt);
 void launch_bin(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_scatter(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
@@ -262,6 +272,16 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, 
   c = c < 0 ? 0 : c;
   c = c > n - 1 ? n - 1 : c;
   return c;
+}
+
+// Signed distance of a point from wall w at the grid's evaluation time,
+// rounded step by step (no fused multiply-add) so that the contact decision
+// is reproducible: ((n_x x + n_y y) + n_z z) - d(t).
+__device__ __forceinline__ double wall_gap(const PileDev& P, const Grid& g, int w, double x,
+                                           double y, double z) {
+  const double* n = P.wall[w];
+  const double s = __dadd_rn(__dadd_rn(__dmul_rn(n[0], x), __dmul_rn(n[1], y)), __dmul_rn(n[2], z));
+  return __dadd_rn(s, -g.wall_d[w]);
 }
 
 }  // namespace dem

@@ -348,7 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
 // One block per pile: combine the block partials into the cell grid and the
 // pile's centre of mass.  Cells are at least one largest-sphere diameter;
 // an open pile's grid spans its bounding box with (1 << bits) cells per axis.
-__global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles) {
+__global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, int mode,
+                                                 double dt) {
   PileDev& P = piles[blockIdx.x];
   if (P.status != 0) return;
   double vals[10] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
@@ -402,6 +403,27 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles) {
   g.inv_cell = 1.0 / g.cell;
   for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
   g.pad = 0;
+  // time of this evaluation: the end of the step being taken, or the
+  // current time for an evaluation in place; walls displaced rigidly by
+  // A sin(omega t + phase), moving at A omega cos(omega t + phase)
+  g.t = (double)(P.step + (mode == kModeStep ? 1 : 0)) * dt;
+  for (int w = 0; w < 6; ++w) {
+    g.wall_d[w] = 0.0;
+    for (int k = 0; k < 3; ++k) g.wall_v[w][k] = 0.0;
+  }
+  if (P.n_walls > 0) {
+    const double ph = __dadd_rn(__dmul_rn(P.wall_omega, g.t), P.wall_phase);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    for (int w = 0; w < P.n_walls; ++w) {
+      const double* n = P.wall[w];
+      const double* A = P.wall_amp[w];
+      const double shift =
+          __dadd_rn(__dadd_rn(__dmul_rn(n[0], A[0]), __dmul_rn(n[1], A[1])), __dmul_rn(n[2], A[2]));
+      g.wall_d[w] = __dadd_rn(n[3], __dmul_rn(shift, sn));
+      for (int k = 0; k < 3; ++k) g.wall_v[w][k] = __dmul_rn(__dmul_rn(A[k], P.wall_omega), cs);
+    }
+  }
   *P.grid = g;
 }
 
@@ -412,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles) {
 // One thread per aggregate.  For each member sphere (in order): its contact
 // force and torque gathered in canonical contact order -- contacts (j, i)
 // with j < i by increasing j, then (i, j) by increasing j -- plus its
-// gravity force.  Then F_A = sum F_i, a_A = F_A / M,
+// gravity force.  Then F_A = sum F_i, a_A = F_A / M + g,
 // N_A = sum [ (R b_i) x F_i + tau_i ], and in step mode v_A += h/2 a_A
 // followed by the spin-up increment about +z through the pile's centre.
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
@@ -467,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
   const double M = P.M[A];
   double a[3];
   for (int k = 0; k < 3; ++k) {
-    a[k] = FA[k] / M;
+    a[k] = FA[k] / M + P.gfield[k];      // a uniform field adds no torque
     P.aA[nxt][k * na + A] = a[k];
     P.NA[nxt][k * na + A] = NA[k];
   }
@@ -542,8 +564,9 @@ void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl
   hipLaunchKernelGGL(k_reconstruct, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 
-void launch_grid(hipStream_t st, const PileDev* piles, int n_piles) {
-  hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles));
+void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, double dt) {
+  hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), mode,
+                     dt);
 }
 
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,

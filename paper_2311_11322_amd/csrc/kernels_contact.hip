@@ -127,7 +127,7 @@ __device__ __forceinline__ void sort_run(uint32_t* __restrict__ a, uint32_t n) {
 }
 
 // One thread per sorted slot.  Scans the 27 neighbouring cells and finds
-// every j != i of another aggregate in contact.  Count mode stores the number
+// every j != i of another aggregate in contact, then the walls it touches.  Count mode stores the number
 // of contacts with j > i (upper) and j < i (lower) under sphere id i; write
 // mode stores the ids at the scanned offsets and sorts each run, after
 // checking the pile's contact capacity.
@@ -196,6 +196,12 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
         }
       }
     }
+  }
+  // walls are partners ns + w, after every sphere partner
+  for (int wl_ = 0; wl_ < P.n_walls; ++wl_) {
+    if (!(wall_gap(P, g, wl_, x, y, z) < si)) continue;
+    if (write) up_out[nup] = (uint32_t)(ns + wl_);
+    ++nup;
   }
   if (write) {
     sort_run(up_out, nup);

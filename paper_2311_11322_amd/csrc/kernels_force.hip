@@ -8,7 +8,8 @@
 // j > i, sorted by j).  The previous step's upper list of i is sorted too, so
 // the history lookup is a merge walk.  The thread then maps its lower list
 // (contacts (j, i), j < i) to indices in j's upper list, which the per-sphere
-// gather uses.  Geometry (separation, distance, overlap) is always FP64; the
+// gather uses.  A wall is partner ns + w: infinite mass, no spin, moving
+// rigidly; its reaction goes nowhere.  Geometry (separation, distance, overlap) is always FP64; the
 // force arithmetic runs in T (double, or float for the FP32-force form).
 #include "dem_internal.h"
 
@@ -94,26 +95,53 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
   bool bad = false;
   for (uint32_t p = new_off[i], p1 = new_off[i + 1]; p < p1; ++p) {
     const uint32_t j = new_j[p];
-    // geometry in FP64
-    double dx = P.r[j] - rix, dy = P.r[ns + j] - riy, dz = P.r[2 * ns + j] - riz;
-    if (periodic) {
-      const double hL = 0.5 * L;
-      if (dx > hL) dx -= L;
-      else if (dx < -hL) dx += L;
-      if (dy > hL) dy -= L;
-      else if (dy < -hL) dy += L;
-      if (dz > hL) dz -= L;
-      else if (dz < -hL) dz += L;
+    // geometry in FP64; partner velocity, spin and the reduced mass
+    double delta_d, li_d, lj_d, mu, Rij_d, s_min;
+    V3<T> n, vj, wj;
+    if (j >= (uint32_t)ns) {
+      // a wall: infinite mass, no spin; the contact point is the foot of
+      // the perpendicular and the normal points from the sphere into the wall
+      const int wi_ = (int)(j - (uint32_t)ns);
+      const Grid& g = *P.grid;
+      const double gap = wall_gap(P, g, wi_, rix, riy, riz);
+      n = mk<T>((T)-P.wall[wi_][0], (T)-P.wall[wi_][1], (T)-P.wall[wi_][2]);
+      delta_d = si - gap;
+      li_d = gap;
+      lj_d = 0.0;
+      mu = Mi;
+      Rij_d = si;
+      s_min = si;
+      vj = mk<T>((T)g.wall_v[wi_][0], (T)g.wall_v[wi_][1], (T)g.wall_v[wi_][2]);
+      wj = mk<T>((T)0, (T)0, (T)0);
+    } else {
+      double dx = P.r[j] - rix, dy = P.r[ns + j] - riy, dz = P.r[2 * ns + j] - riz;
+      if (periodic) {
+        const double hL = 0.5 * L;
+        if (dx > hL) dx -= L;
+        else if (dx < -hL) dx += L;
+        if (dy > hL) dy -= L;
+        else if (dy < -hL) dy += L;
+        if (dz > hL) dz -= L;
+        else if (dz < -hL) dz += L;
+      }
+      const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+      const double sj = P.s[j];
+      delta_d = (si + sj) - dist;
+      li_d = (si * si - sj * sj + dist * dist) / (2.0 * dist);
+      lj_d = dist - li_d;
+      const double inv_d = 1.0 / dist;
+      n = mk<T>(dx * inv_d, dy * inv_d, dz * inv_d);
+      const int Aj = P.agg[j];
+      vj = mk<T>(P.v[j], P.v[ns + j], P.v[2 * ns + j]);
+      wj = mk<T>(P.wA[Aj], P.wA[na + Aj], P.wA[2 * na + Aj]);
+      const double Mj = P.M[Aj];
+      mu = Mi * Mj / (Mi + Mj);
+      Rij_d = si * sj / (si + sj);
+      s_min = fmin(si, sj);
     }
-    const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-    const double sj = P.s[j];
-    const double delta_d = (si + sj) - dist;
-    const double li_d = (si * si - sj * sj + dist * dist) / (2.0 * dist);
-    const double inv_d = 1.0 / dist;
-    const V3<T> n = mk<T>(dx * inv_d, dy * inv_d, dz * inv_d);
     const T delta = (T)delta_d;
     const T li = (T)li_d;
-    const T lj = (T)(dist - li_d);
+    const T lj = (T)lj_d;
 
     // history of this contact from the previous step, if it existed
     while (o < o1 && old_j[o] < j) ++o;
@@ -124,10 +152,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
       for (int c = 0; c < kHist; ++c) hs[c] = (T)0;
     }
 
-    const int Aj = P.agg[j];
-    const V3<T> vj = mk<T>(P.v[j], P.v[ns + j], P.v[2 * ns + j]);
-    const V3<T> wj = mk<T>(P.wA[Aj], P.wA[na + Aj], P.wA[2 * na + Aj]);
-    const double Mj = P.M[Aj];
     // velocity of each body's material point at the contact point
     const V3<T> arm_i = li * n;
     const V3<T> arm_j = ((T)-1) * (lj * n);
@@ -135,7 +159,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
     const T un = dotv(u, n);
     const V3<T> ut = u - un * n;
     // dashpots from the restitution coefficients, aggregate reduced mass
-    const double mu = Mi * Mj / (Mi + Mj);
     const T Cn = (T)(cp.damp_n * sqrt(cp.k_n * mu));
     const T Ct = (T)(cp.damp_t * sqrt(cp.k_t * mu));
     const T fn = -kn * delta + Cn * un;              // along n, on i
@@ -151,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
     const V3<T> FT = slid ? kt * xt : kt * xt + Ct * ut;
 
     // rolling and twisting: springs on the relative spin of the two bodies
-    const T Rij = (T)(si * sj / (si + sj));
+    const T Rij = (T)Rij_d;
     const V3<T> dw = wj - wi;
     V3<T> xr = mk(hs[3], hs[4], hs[5]);
     xr = (xr - dotv(xr, n) * n) + (h * Rij) * crossv(dw, n);
@@ -180,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
     for (int c = 0; c < kHist; ++c) new_h[(size_t)c * cap + p] = (double)hn[c];
 
     if (!isfinite((double)F.x) || !isfinite((double)F.y) || !isfinite((double)F.z)) bad = true;
-    if (cp.max_overlap_frac > 0.0 && delta_d > cp.max_overlap_frac * fmin(si, sj)) bad = true;
+    if (cp.max_overlap_frac > 0.0 && delta_d > cp.max_overlap_frac * s_min) bad = true;
   }
   if (bad) atomicOr(&P.status, kStUnstable);
 

@@ -50,6 +50,9 @@ class dem_params(C.Structure):
         ("periodic", C.c_int32), ("box", C.c_double * 3),
         ("precision", C.c_int32), ("max_contacts_per_sphere", C.c_int32),
         ("max_overlap_frac", C.c_double),
+        ("g", C.c_double * 3), ("n_walls", C.c_int32), ("walls", (C.c_double * 4) * 6),
+        ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
+        ("shake_phase", C.c_double),
     ]
 
 
@@ -160,6 +163,21 @@ def make_params(d: Dict, precision: int = PREC_FP64, max_contacts: int = 0,
     p.precision = int(d.get("precision", precision))
     p.max_contacts_per_sphere = int(d.get("max_contacts_per_sphere", max_contacts))
     p.max_overlap_frac = float(d.get("max_overlap_frac", max_overlap_frac))
+    g = d.get("g", (0.0, 0.0, 0.0))
+    for c in range(3):
+        p.g[c] = float(g[c])
+    walls = d.get("walls", ())
+    if len(walls) > 6:
+        raise ValueError("at most 6 walls")
+    p.n_walls = len(walls)
+    amp = d.get("shake_amp", ())
+    for w, wl in enumerate(walls):
+        for c in range(4):
+            p.walls[w][c] = float(wl[c])
+        for c in range(3):
+            p.shake_amp[w][c] = float(amp[w][c]) if len(amp) else 0.0
+    p.shake_omega = float(d.get("shake_omega", 0.0))
+    p.shake_phase = float(d.get("shake_phase", 0.0))
     return p
 
 

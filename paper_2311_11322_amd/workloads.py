@@ -229,7 +229,12 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
     """Random sequential addition of whole aggregates (largest first).
 
     container: ("ball", R): aggregate centres uniform in the ball; or
-    ("box", L): centres uniform in the periodic cube.  If ``contact_seeded`` every
+    ("box", L): centres uniform in the periodic cube; or ("cuboid", (Lx, Ly,
+    Lz, z_lo, z_hi, p_floor)): inside the walled box [0, Lx] x [0, Ly] x
+    [0, Lz], every sphere at least MIN_GAP clear of the walls, centres drawn
+    with z in [z_lo, z_hi], and with probability p_floor an aggregate lowered
+    onto the floor so that its lowest sphere overlaps it by U[1e-5, 1e-3].
+    If ``contact_seeded`` every
     aggregate after the first is put in contact, with overlap drawn from
     U[1e-5, 1e-3], with a sphere of an already-placed aggregate.  Otherwise,
     once ``near_after`` uniform draws for one aggregate have failed (close to
@@ -242,6 +247,10 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
     if kind == "box":
         L = float(size)
         grid = _Grid(np.zeros(3), None, 2.4, periodic=True, box=np.full(3, L))
+    elif kind == "cuboid":
+        Lx, Ly, Lz, z_lo, z_hi, p_floor = (float(v) for v in size)
+        grid = _Grid(np.full(3, -3.0), np.array([Lx, Ly, Lz]) + 3.0,
+                     max(2.4, 2.0 * float(max(c[1].max() for c in clusters)) + 0.1))
     else:
         R = float(size)
         grid = _Grid(np.full(3, -R - 3.0), np.full(3, R + 3.0), 2.4)
@@ -253,8 +262,9 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
         for tries in range(max_tries):
             rot = _random_rotation(rng)
             body = rel @ rot.T
-            seeded = contact_seeded and n_done > 0
-            near = (not seeded) and n_done > 0 and tries >= near_after
+            floor_pick = kind == "cuboid" and p_floor > 0 and rng.uniform() < p_floor
+            seeded = contact_seeded and n_done > 0 and not floor_pick
+            near = (not seeded) and (not floor_pick) and n_done > 0 and tries >= near_after
             if seeded or near:
                 # put member m against placed sphere t: overlapping it by
                 # U[1e-5, 1e-3] (contact-seeded) or, when plain random draws
@@ -272,12 +282,27 @@ def _place(rng, counts, clusters, container, contact_seeded, max_tries=20000,
                 t = -1
                 if kind == "box":
                     centre = rng.uniform(0.0, L, 3)
+                elif kind == "cuboid":
+                    centre = np.array([rng.uniform(0.0, Lx), rng.uniform(0.0, Ly),
+                                       rng.uniform(z_lo, z_hi)])
+                    if floor_pick:
+                        centre[2] -= (body[:, 2] - rad + centre[2]).min() + rng.uniform(1e-5, 1e-3)
                 else:
                     v = _unit_vectors(rng, 1)[0]
                     centre = v * R * rng.uniform() ** (1.0 / 3.0)
             if kind == "box":
                 # keep the aggregate whole; only its centre is wrapped
                 centre = np.mod(centre, L)
+            elif kind == "cuboid":
+                p = centre + body
+                lo = p - rad[:, None]
+                hi = p + rad[:, None]
+                if ((lo[:, :2] < MIN_GAP).any() or (hi[:, 0] > Lx - MIN_GAP).any()
+                        or (hi[:, 1] > Ly - MIN_GAP).any() or (hi[:, 2] > Lz).any()):
+                    continue
+                lz = lo[:, 2]
+                if ((lz >= -MIN_GAP) & (lz < MIN_GAP)).any() or (lz < -1.001e-3).any():
+                    continue    # floor contacts are seeded overlaps, never near misses
             elif np.linalg.norm(centre) > R:
                 continue        # centres of mass uniform in the ball
             p = centre + body
@@ -645,3 +670,156 @@ def fixture_system(shapes, centres, s=1.0, vel=None, spin=None, rot=None,
         prm.update(params)
     return Workload("fixture", np.asarray(counts, dtype=np.int32), pos, radius, mass,
                     vel, spin, prm, n_steps)
+
+
+# --------------------------------------------------------------------------
+# walled workloads: box filling (Sec. 3.2) and the Brazil-nut effect (Sec. 4.3)
+# --------------------------------------------------------------------------
+
+MIXED_SHAPES = ("dumbbell", "diamond", "tetrahedron", "rod", "cube")
+
+
+def open_box_walls(Lx: float, Ly: float):
+    """Floor z = 0 and four side walls of the box [0, Lx] x [0, Ly]; open top.
+    Each wall is (n_x, n_y, n_z, d) with the unit normal pointing inward."""
+    return [(0.0, 0.0, 1.0, 0.0), (1.0, 0.0, 0.0, 0.0), (-1.0, 0.0, 0.0, -float(Lx)),
+            (0.0, 1.0, 0.0, 0.0), (0.0, -1.0, 0.0, -float(Ly))]
+
+
+def _shape_mix(rng, n_sph: int, shape: str):
+    """Shape names whose member counts add up to n_sph: one shape, or a
+    uniform mix of the symmetric shapes of 2-8 spheres (no free spheres)."""
+    if shape != "mixed":
+        k = shape_fixture(shape).shape[0]
+        if n_sph % k:
+            raise ValueError(f"{n_sph} spheres do not divide into {shape}s")
+        return [shape] * (n_sph // k)
+    sizes = {s: shape_fixture(s).shape[0] for s in MIXED_SHAPES}
+    if n_sph % 2:
+        raise ValueError("a mix of even-sized shapes needs an even sphere count")
+    out, left = [], n_sph
+    while left > 0:
+        fit = [s for s in MIXED_SHAPES if sizes[s] <= left]
+        s = fit[int(rng.integers(len(fit)))]
+        out.append(s)
+        left -= sizes[s]
+    return out
+
+
+def box_fill(seed: int = 8, n_sph: int = 6400, shape: str = "mixed", base: float = 40.0,
+             height: float = 240.0, g: float = 2.0, dt: float = 5e-4, z_range=None,
+             floor_seeded: float = 0.0, contact_seeded: bool = False,
+             n_steps: int = 10000) -> Workload:
+    """Box filling under a uniform field (the uniform-gravity profiling runs).
+
+    Equal spheres of radius 1 (0.25 cm in the paper) bound into the paper's
+    symmetric shapes -- one shape, or "mixed": shapes of 2-8 members and no
+    free spheres -- with ``n_sph`` member spheres in all, placed at rest at
+    random positions and orientations in the open-topped box of base
+    ``base`` x ``base`` and height ``height`` radii (10 x 10 x 60 cm), under
+    a field of magnitude g along -z.  Length unit: the sphere radius; time
+    unit: the one that makes lunar gravity equal ``g`` (0.056 s for g = 2).
+    ``z_range`` limits the centres' heights (a partly filled box);
+    ``floor_seeded`` is the fraction of aggregates set down on the floor with
+    an overlap (for single-step checks of wall contacts).
+    """
+    rng = np.random.default_rng(seed)
+    names = _shape_mix(rng, n_sph, shape)
+    clusters = []
+    for nm in names:
+        rel = shape_fixture(nm)
+        clusters.append((rel, np.ones(rel.shape[0])))
+    counts = np.array([c[0].shape[0] for c in clusters], dtype=np.int32)
+    z_lo, z_hi = z_range if z_range is not None else (0.0, height)
+    pos, radius = _place(rng, counts, clusters,
+                         ("cuboid", (base, base, height, z_lo, z_hi, floor_seeded)),
+                         contact_seeded)
+    mass = sphere_mass(radius)
+    n_agg = counts.shape[0]
+    params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=0,
+                  box=(0.0, 0.0, 0.0), g=(0.0, 0.0, -float(g)),
+                  walls=open_box_walls(base, base))
+    return Workload("box_fill", counts, pos, radius, mass, np.zeros((n_agg, 3)),
+                    np.zeros((n_agg, 3)), params, n_steps,
+                    notes=f"{shape} shapes, {n_sph} spheres, box {base}x{base}x{height}, "
+                    f"g={g}, seed={seed}")
+
+
+def brazil_nut(seed: int = 9, n_sph: int = 4000, shape: str = "mixed",
+               intruder_radius: float = 6.0, base: float = 40.0, fill_height: float = 60.0,
+               g: float = 2.0, amplitude: float = 4.0, froude: float = 3.0,
+               dt: float = 5e-4, floor_seeded: float = 0.0, n_steps: int = 1000) -> Workload:
+    """Brazil-nut set-up: a large spherical intruder resting on the floor of
+    a box of base ``base`` x ``base`` (10 x 10 cm at 0.25 cm grains), grains
+    of radius 1 bound into the symmetric shapes placed at rest around and
+    above it up to ``fill_height``, under a field g along -z.  Every wall
+    oscillates vertically with amplitude A = ``amplitude`` (1 cm) and omega
+    from the Froude number A omega^2 / g (3 in the paper, 54.2 rad/s at Earth
+    gravity), starting from rest at the lowest point: displacement
+    A (1 + sin(omega t - pi/2)), so the floor starts at z = 0.  The intruder
+    is aggregate 0.  ``floor_seeded`` is the fraction of grains set down on
+    the floor with an overlap of U[1e-5, 1e-3] (for short checks).
+    """
+    rng = np.random.default_rng(seed)
+    names = _shape_mix(rng, n_sph, shape)
+    clusters = [(shape_fixture(nm), np.ones(shape_fixture(nm).shape[0])) for nm in names]
+    counts = np.array([c[0].shape[0] for c in clusters], dtype=np.int32)
+    R = float(intruder_radius)
+    x0 = np.array([0.5 * base, 0.5 * base, R + 1e-3])
+    # grains by RSA in the fill region, clear of the intruder
+    pos, radius = _place_around(rng, counts, clusters, base, fill_height, x0, R, floor_seeded)
+    pos = np.concatenate([x0[None, :], pos])
+    radius = np.concatenate([[R], radius])
+    counts = np.concatenate([[1], counts]).astype(np.int32)
+    mass = sphere_mass(radius)
+    omega = math.sqrt(froude * g / amplitude)
+    walls = open_box_walls(base, base)
+    walls[0] = (0.0, 0.0, 1.0, float(amplitude))      # floor at z = 0 at t = 0
+    params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=0,
+                  box=(0.0, 0.0, 0.0), g=(0.0, 0.0, -float(g)), walls=walls,
+                  shake_amp=[(0.0, 0.0, float(amplitude))] * len(walls),
+                  shake_omega=omega, shake_phase=-0.5 * math.pi)
+    n_agg = counts.shape[0]
+    return Workload("brazil_nut", counts, pos, radius, mass, np.zeros((n_agg, 3)),
+                    np.zeros((n_agg, 3)), params, n_steps,
+                    notes=f"{shape} grains, {n_sph} spheres, intruder R={R}, "
+                    f"omega={omega:.4f}, seed={seed}")
+
+
+def _place_around(rng, counts, clusters, base, height, x0, R, p_floor=0.0, max_tries=20000):
+    """RSA of aggregates in [0, base]^2 x [0, height], every sphere at least
+    MIN_GAP clear of the walls and of a fixed sphere (x0, R); with
+    probability p_floor an aggregate is lowered onto the floor so that its
+    lowest sphere overlaps it by U[1e-5, 1e-3]."""
+    order = np.argsort(-counts, kind="stable")
+    grid = _Grid(np.full(3, -3.0), np.array([base, base, height]) + 3.0, 2.4)
+    placed = [None] * len(counts)
+    for a in order:
+        rel, rad = clusters[a]
+        rel = rel - rel.mean(axis=0)
+        for _ in range(max_tries):
+            body = rel @ _random_rotation(rng).T
+            c = np.array([rng.uniform(0, base), rng.uniform(0, base), rng.uniform(0, height)])
+            if p_floor > 0 and rng.uniform() < p_floor:
+                c[2] -= (body[:, 2] - rad + c[2]).min() + rng.uniform(1e-5, 1e-3)
+            p = c + body
+            lo = p - rad[:, None]
+            hi = p + rad[:, None]
+            lz = lo[:, 2]
+            if ((lo[:, :2] < MIN_GAP).any() or (hi[:, :2] > base - MIN_GAP).any()
+                    or (hi[:, 2] > height).any() or ((lz >= -MIN_GAP) & (lz < MIN_GAP)).any()
+                    or (lz < -1.001e-3).any()):
+                continue
+            if (np.linalg.norm(p - x0, axis=1) - (R + rad) < MIN_GAP).any():
+                continue
+            gap, _ = grid.gaps(p, rad)
+            if gap.size and (gap < MIN_GAP).any():
+                continue
+            grid.insert(p, rad)
+            placed[a] = p
+            break
+        else:
+            raise RuntimeError("placement failed; raise fill_height")
+    pos = np.concatenate([placed[a] for a in range(len(counts))])
+    radius = np.concatenate([clusters[a][1] for a in range(len(counts))])
+    return pos, radius

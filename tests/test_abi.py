@@ -43,11 +43,19 @@ def test_parameter_validation_on_host():
     from paper_2311_11322_amd import workloads as W
     good = dict(W.CONTACT_PARAMS, dt=1e-4, G=0.0, soft_frac=0.5, periodic=0, box=(0, 0, 0))
     for bad in (dict(dt=0.0), dict(eps_n=0.0), dict(eps_t=1.5), dict(k_n=-1.0), dict(mu_s=-0.1),
-                dict(periodic=1, box=(10.0, 10.0, 9.0)), dict(dt=float("nan"))):
+                dict(periodic=1, box=(10.0, 10.0, 9.0)), dict(dt=float("nan")),
+                dict(walls=[(0.0, 0.0, 2.0, 0.0)]),                        # not a unit normal
+                dict(walls=[(0.0, 0.0, 1.0, 0.0)], periodic=1, box=(9.0, 9.0, 9.0)),
+                dict(walls=[(0.0, 0.0, 1.0, float("inf"))]),
+                dict(walls=[(0.0, 0.0, 1.0, 0.0)], shake_amp=[(0.0, 0.0, float("nan"))]),
+                dict(g=(0.0, 0.0, float("nan")))):
         p = dict(good, **bad)
         with pytest.raises(dem.DemError) as ei:
             dem.Sim(p)
         assert ei.value.code == dem.DEM_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        dem.Sim(dict(good, walls=[(0.0, 0.0, 1.0, 0.0)] * 7))
+    dem.Sim(dict(good, walls=W.open_box_walls(10, 10), g=(0, 0, -1))).close()
     # footprint is pure host arithmetic and grows with size
     f1 = dem.footprint_bytes(good, 1000, 4500)
     f2 = dem.footprint_bytes(good, 2000, 9000)

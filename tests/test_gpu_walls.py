@@ -1,0 +1,141 @@
+"""Parity of the walled workloads with the FP64 oracle (needs an MI355X).
+
+Box filling under a uniform field (open-topped box, wall contacts seeded on
+the floor) and the Brazil-nut set-up (a large intruder among aggregates, all
+walls shaken sinusoidally).  Each test prints its case before the GPU runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_11322_amd import workloads as W
+from tests.gpu_util import compare_states, oracle_keys, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_2311_11322_amd import dem
+    dem.lib()
+    return dem
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(D, w, precision=0):
+    sim = D.Sim(w.params, precision=precision)
+    sim.add_workload(w)
+    o = O.Oracle(w.params).add_workload(w)
+    return sim, o
+
+
+def _small_box(seed=2, shape="mixed"):
+    """A partly filled box with floor and aggregate contacts seeded, and
+    random velocities and spins so that every friction term is active."""
+    w = W.box_fill(seed=seed, n_sph=240, shape=shape, base=14, height=40, z_range=(0, 30),
+                   floor_seeded=0.3, contact_seeded=True)
+    rng = np.random.default_rng(seed + 100)
+    w.agg_vel[:] = rng.normal(0.0, 0.1, w.agg_vel.shape)
+    w.agg_spin[:] = rng.normal(0.0, 0.3, w.agg_spin.shape)
+    return w
+
+
+@pytest.mark.parametrize("shape", ["mixed", "sphere", "cube"])
+def test_box_fill_parity(D, shape):
+    """t0, one step and then 40 more: contacts with the floor and side walls
+    in the contact list, forces and the uniform field in the state."""
+    say("box fill", shape)
+    w = _small_box(shape=shape)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    keys = oracle_keys(o)
+    assert (keys & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)).any()     # wall contacts
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o)
+    for _ in range(4):
+        sim.step(10)
+        o.step(10)
+        compare_states(sim, o, tol=1e-10)
+
+
+def test_box_fill_wall_contacts_form_and_break(D):
+    """Aggregates dropped from just above the floor hit it and bounce: the
+    wall contacts of the last step agree with the oracle throughout."""
+    say("box fill drop")
+    w = W.box_fill(seed=4, n_sph=200, base=24, height=40, z_range=(0.0, 2.5))
+    w.agg_vel[:, 2] = -5.0
+    sim, o = _pair(D, w)
+    n_wall = []
+    for _ in range(8):
+        sim.step(50)
+        o.step(50)
+        compare_states(sim, o, tol=1e-9)
+        n_wall.append(int((oracle_keys(o) & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)).sum()))
+    print("wall contacts", n_wall)
+    assert max(n_wall) > 10 and min(n_wall) < max(n_wall)
+
+
+def test_brazil_nut_shaken_walls_parity(D):
+    """Large intruder among aggregates, every wall oscillating: the floor
+    comes up into the bed in the first steps."""
+    say("brazil nut small")
+    w = W.brazil_nut(seed=3, n_sph=300, intruder_radius=4.0, base=16, fill_height=30.0,
+                     floor_seeded=0.5)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    for n in (1, 9, 40, 150):
+        sim.step(n)
+        o.step(n)
+        compare_states(sim, o, tol=1e-9)
+    walls = oracle_keys(o) & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)
+    assert walls.sum() >= 5
+
+
+def test_box_fill_fp32_force_form(D):
+    """FP32 pair forces: sphere forces within 1e-5 of the oracle (max norm),
+    contact list exact."""
+    say("box fill fp32-force")
+    w = _small_box(seed=5)
+    sim, o = _pair(D, w, precision=D.PREC_FP32_FORCE)
+    sim.step(1)
+    o.step(1)
+    g = sim.read_state(["sph_force", "agg_pos"], pairs=True)
+    assert np.array_equal(g["pair_keys"], oracle_keys(o))
+    assert rel_err(g["sph_force"], o.spheres()["F"]) <= 1e-5
+
+
+def test_walled_piles_in_engine_match_alone(D):
+    """A box fill, a Brazil-nut set-up and a self-gravitating pile stepped
+    together in one engine give the states each gives alone, bit for bit."""
+    say("engine walls + pile")
+    ws = [_small_box(seed=6), W.brazil_nut(seed=7, n_sph=200, intruder_radius=3.0, base=14,
+                                            fill_height=24.0),
+          W.collapse_cloud(8, n_agg=60, contact_seeded=True)]
+    alone = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        s.step(7)
+        alone.append(s.read_state(pairs=True))
+        s.close()
+    eng = D.Engine(1 << 33)
+    sims = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        eng.attach(s)
+        sims.append(s)
+    assert eng.step(7) == D.DEM_OK
+    for s in list(eng.sims):
+        eng.detach(s)
+    for k, s in enumerate(sims):
+        got = s.read_state(pairs=True)
+        for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "pair_hist", "sph_force"):
+            assert np.array_equal(got[f], alone[k][f]), (k, f)
