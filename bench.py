@@ -98,6 +98,11 @@ def main():
                     help="only the headline workload (skip FP32-force, batched and served)")
     ap.add_argument("--piles", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--fill-steps", type=int, default=10000,
+                    help="steps of the box-filling runs (the paper profiles 10^4)")
+    ap.add_argument("--box-batch", type=int, default=64, help="box fills batched in one engine")
+    ap.add_argument("--only", choices=["contact_path", "walled"], default=None,
+                    help="run only this section and print its result (for profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -120,6 +125,15 @@ def main():
         return
     from paper_2311_11322_amd import dem
     from paper_2311_11322_amd import workloads as W
+    if args.only:
+        dem.lib()
+        part = {}
+        if args.only == "contact_path":
+            contact_path_run(args, part)
+        else:
+            walled_runs(args, part, min(16, len(os.sched_getaffinity(0))))
+        print(json.dumps(part), flush=True)
+        return
 
     t = time.time()
     w = W.collapse_cloud(1, n_agg=args.n_agg)
@@ -202,32 +216,17 @@ def timed_steps(sim, steps):
     return time.perf_counter() - t0
 
 
-def extra_runs(args, w, out, prec):
-    """The FP32-force form on the same collapse, the batched spin-up piles
-    (plain FP64 one pile at a time vs FP32-force batched in one engine) and
-    a served request stream."""
-    import numpy as np
-    import torch
-    from paper_2311_11322_amd import dem, serve
+def _box(seed_shape):
     from paper_2311_11322_amd import workloads as W
-    workers = min(16, len(os.sched_getaffinity(0)))
-    # -- FP32-force form at 125k spheres
-    if prec == dem.PREC_FP64:
-        s32 = dem.Sim(w.params, precision=dem.PREC_FP32_FORCE)
-        s32.add_workload(w)
-        s32.step(2)
-        s32.set_profiling(True)
-        wall = timed_steps(s32, args.steps)
-        p32 = s32.profile()
-        s32.close()
-        g_ms = p32["gravity"] / p32["_steps"]
-        ach = GRAVITY_FLOP_PER_PAIR * w.n_sph * (w.n_sph - 1) / (g_ms * 1e-3) / 1e12
-        out["fp32_force"] = {"value": round(w.n_sph * args.steps / wall, 1),
-                             "ms_per_step": round(1e3 * wall / args.steps, 4),
-                             "gravity_ms": round(g_ms, 4),
-                             "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
-        log(f"fp32-force: {out['fp32_force']}")
-    # -- contact path on a contact-dense workload (HBM-bound kernels)
+    seed, shape = seed_shape
+    return W.box_fill(seed=seed, shape=shape)
+
+
+def contact_path_run(args, out):
+    """The contact path alone on a contact-dense periodic lattice (no
+    gravity): every non-gravity kernel of the step, against the HBM roofline."""
+    from paper_2311_11322_amd import dem
+    from paper_2311_11322_amd import workloads as W
     wl = W.dense_lattice(n_side=50)
     sl = dem.Sim(wl.params)
     sl.add_workload(wl)
@@ -253,6 +252,114 @@ def extra_runs(args, w, out, prec):
                      "algorithmic": f"{CONTACT_BYTES_FIXED} B + {CONTACT_BYTES_PER_CONTACT} B x "
                                     f"z per sphere-step over all contact-path kernels"}}
     log(f"contact path: {out['contact_path']}")
+
+
+def walled_runs(args, out, workers):
+    """The box-filling profiling workload (6,400 unit spheres in a 40 x 40 x
+    240 open-topped box under a uniform field; the first 10^4 steps of the
+    fill, as profiled in the paper) for each aggregate shape, the member
+    search ablation on it, many box fills batched in one engine, and the
+    Brazil-nut set-up with shaken walls."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2311_11322_amd import dem, serve
+    from paper_2311_11322_amd import workloads as W
+    n_fill = args.fill_steps
+    shapes = ("sphere", "dumbbell", "cube", "mixed")
+    with ProcessPoolExecutor(max_workers=max(1, min(workers, 8))) as ex:
+        fills = dict(zip(shapes, ex.map(_box, [(8, s) for s in shapes])))
+    per_shape = {}
+    prof = None
+    for shape in shapes:
+        wb = fills[shape]
+        sb = dem.Sim(wb.params)
+        sb.add_workload(wb)
+        if shape == "mixed":
+            sb.set_profiling(True)
+        wall = timed_steps(sb, n_fill)
+        if shape == "mixed":
+            prof = sb.profile()
+        per_shape[shape] = {"aggregates": wb.n_agg, "ms_per_step": round(1e3 * wall / n_fill, 4),
+                            "contacts_at_end": sb.counts()[2]}
+        sb.close()
+    wm = fills["mixed"]
+    abl = {}
+    for scan in (0, 1):
+        sa = dem.Sim(wm.params)
+        sa.set_tuning(0, 1.0, scan)
+        sa.add_workload(wm)
+        abl[scan] = 1e3 * timed_steps(sa, n_fill // 5) / (n_fill // 5)
+        sa.close()
+    out["box_fill"] = {
+        "workload": f"box filling, {wm.n_sph} unit spheres, 40x40x240 open box, g = 2 along -z, "
+                    f"first {n_fill} steps from rest, FP64",
+        "value": round(wm.n_sph * n_fill / (per_shape["mixed"]["ms_per_step"] * 1e-3 * n_fill), 1),
+        "unit": "sphere-steps/s", "per_shape": per_shape,
+        "kernel_ms_per_step_mixed": {k: round(v / prof["_steps"], 5) for k, v in prof.items()
+                                     if not k.startswith("_")},
+        "member_search_ablation": {"improved_ms_per_step": round(abl[0], 4),
+                                   "original_ms_per_step": round(abl[1], 4),
+                                   "speedup": round(abl[1] / abl[0], 3)}}
+    log(f"box fill: {out['box_fill']}")
+    # many box fills in one engine (seeds differ, mixed shapes)
+    nb = args.box_batch
+    if nb > 0:
+        with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
+            boxes = list(ex.map(_box, [(100 + k, "mixed") for k in range(nb)]))
+        steps_b = max(50, n_fill // 20)
+        rb = serve.run_batch(boxes, steps_b, dem.PREC_FP64, warmup=2)
+        for s in rb["sims"]:
+            s.close()
+        out["box_fill"]["batched"] = {
+            "boxes": nb, "spheres": rb["spheres"], "steps": steps_b,
+            "value": round(rb["sphere_steps_per_s"], 1), "unit": "sphere-steps/s",
+            "ms_per_step": round(rb["ms_per_step"], 4)}
+        log(f"box fill batched: {out['box_fill']['batched']}")
+    # Brazil-nut set-up, walls shaken at Froude number 3
+    wn = W.brazil_nut()
+    sn = dem.Sim(wn.params)
+    sn.add_workload(wn)
+    sn.step(2)
+    sn.set_profiling(True)
+    n_bne = max(200, n_fill // 10)
+    wall = timed_steps(sn, n_bne)
+    pn = sn.profile()
+    out["brazil_nut"] = {
+        "workload": f"intruder R=6 among {wn.n_sph - 1} grain spheres ({wn.n_agg - 1} aggregates), "
+                    "40x40 box, all walls shaken, Froude 3, FP64",
+        "value": round(wn.n_sph * n_bne / wall, 1), "unit": "sphere-steps/s",
+        "ms_per_step": round(1e3 * wall / n_bne, 4),
+        "kernel_ms_per_step": {k: round(v / pn["_steps"], 5) for k, v in pn.items()
+                               if not k.startswith("_")}}
+    sn.close()
+    log(f"brazil nut: {out['brazil_nut']}")
+
+
+def extra_runs(args, w, out, prec):
+    """The FP32-force form on the same collapse, the batched spin-up piles
+    (plain FP64 one pile at a time vs FP32-force batched in one engine) and
+    a served request stream."""
+    import numpy as np
+    import torch
+    from paper_2311_11322_amd import dem, serve
+    from paper_2311_11322_amd import workloads as W
+    workers = min(16, len(os.sched_getaffinity(0)))
+    # -- FP32-force form at 125k spheres
+    if prec == dem.PREC_FP64:
+        s32 = dem.Sim(w.params, precision=dem.PREC_FP32_FORCE)
+        s32.add_workload(w)
+        s32.step(2)
+        s32.set_profiling(True)
+        wall = timed_steps(s32, args.steps)
+        p32 = s32.profile()
+        s32.close()
+        g_ms = p32["gravity"] / p32["_steps"]
+        ach = GRAVITY_FLOP_PER_PAIR * w.n_sph * (w.n_sph - 1) / (g_ms * 1e-3) / 1e12
+        out["fp32_force"] = {"value": round(w.n_sph * args.steps / wall, 1),
+                             "ms_per_step": round(1e3 * wall / args.steps, 4),
+                             "gravity_ms": round(g_ms, 4),
+                             "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
+        log(f"fp32-force: {out['fp32_force']}")
+    contact_path_run(args, out)
     # -- the paper's efficiency experiment: original (full-scan) vs improved
     #    (contiguous) member search, on its collapse shape (2e4 spheres)
     wa = W.collapse_cloud(seed=5, n_agg=4444, cmin=1, cmax=8)
@@ -273,6 +380,7 @@ def extra_runs(args, w, out, prec):
         "improved_reduce_ms": round(abl[0][1], 4), "original_reduce_ms": round(abl[1][1], 4),
         "speedup": round(abl[1][0] / abl[0][0], 3)}
     log(f"member search ablation: {out['member_search_ablation']}")
+    walled_runs(args, out, workers)
     # -- batched spin-up piles
     t = time.time()
     piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)

@@ -61,6 +61,15 @@ struct Sizes {
   int precision;
 };
 
+// Cells per axis of a periodic cube of side L: as many as fit with a side of
+// at least cell_min (with a relative margin against rounding), at least one,
+// and no more than the Morton table holds.
+int periodic_cells(double L, double cell_min, int bits) {
+  const double ratio = L / (cell_min * (1.0 + 1e-12));
+  int n = ratio >= 1.0 ? (int)std::min(std::floor(ratio), 1e9) : 1;
+  return std::max(1, std::min(n, 1 << bits));
+}
+
 int choose_bits(int64_t ns) {
   // at least two cells per sphere, 2..10 bits per axis
   int b = (ceil_log2(uint64_t(2 * ns)) + 2) / 3;
@@ -134,9 +143,11 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.tau, 3 * ns);
   L.add(&h.key, ns);
   L.add(&h.sidx, ns);
+  L.add(&h.sidx_raw, ns);
   L.add(&h.slot, ns);
   L.add(&h.xs, 4 * ns);
-  L.add(&h.sagg, ns);
+  L.add(&h.xg, ns);
+  L.add(&h.sid, ns);
   if (z.grav) {
     // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
     const int64_t part_vals = z.g_nt * 3 * ns;
@@ -675,19 +686,11 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
     if (agg_vel && !std::isfinite(agg_vel[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite velocity");
     if (agg_spin && !std::isfinite(agg_spin[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite spin");
   }
-  int nb_periodic = 0;
   const double cell_min = s->tune.cell_scale * 2.0 * smax;
-  if (s->prm.periodic) {
-    // cells per axis: the largest power of two whose cell still spans the
-    // minimum cell side (one cell if the box is smaller than that)
-    const double ratio = s->prm.box[0] / cell_min;
-    nb_periodic = ratio >= 1.0 ? (int)std::floor(std::log2(ratio)) : 0;
-  }
   dem_status st = alloc_pile(s, n_agg, ns);
   if (st != DEM_OK) return st;
   s->h.cell_min = cell_min;
-  // the Morton table must hold every periodic cell: larger cells if needed
-  s->h.nb_periodic = std::min(nb_periodic, s->h.bits);
+  if (s->prm.periodic) s->h.n_periodic = periodic_cells(s->prm.box[0], cell_min, s->h.bits);
   hipStream_t str = s->stream;
   // constants: membership, radius, mass
   std::vector<int32_t> first(n_agg), agg(ns);
@@ -1026,7 +1029,7 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   HIPCHK(s, hipMemcpyAsync(mass.data(), old.m, ns * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipStreamSynchronize(st));
   const double cell_min = old.cell_min;
-  const int nbp = old.nb_periodic;
+  const int nbp = old.n_periodic;
   const int64_t step = old.step;
   free_meta(s->own);
   release_pile(s);
@@ -1035,7 +1038,7 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   if (r != DEM_OK) return r;
   PileDev& h = s->h;
   h.cell_min = cell_min;
-  h.nb_periodic = nbp;
+  h.n_periodic = nbp;
   h.step = step;
   for (int k = 0; k < 3; ++k) {   // the perturber continues where it was
     h.pert_r[0][k] = old.pert_r[old.parity][k];
@@ -1140,18 +1143,13 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
     dem_sim* s;
     ~Guard() { dem_destroy(s); }
   } guard{s};
-  int nbp = 0;
-  if (box) {
-    const double ratio = box[0] / (2.0 * smax);
-    nbp = ratio >= 1.0 ? (int)std::floor(std::log2(ratio)) : 0;
-  }
   // one sphere per pseudo-aggregate; the given ids decide which pairs count
   r = alloc_pile(s, n, n);
   if (r != DEM_OK) return fail(nullptr, r, s->err);
   PileDev& h = s->h;
   h.na = 0;   // positions are given: reconstruction only measures the bbox
   h.cell_min = 2.0 * smax;
-  h.nb_periodic = std::min(nbp, h.bits);
+  if (box) h.n_periodic = periodic_cells(box[0], h.cell_min, h.bits);
   hipStream_t st = nullptr;
   std::vector<double> col(3 * n);
   for (int64_t i = 0; i < n; ++i)

@@ -41,11 +41,21 @@ struct Grid {
   double cell;               // cell side (>= largest sphere diameter)
   double inv_cell;
   double com[3];             // centre of mass of the pile (spin-up forcing)
-  int32_t nb;                // cells per axis = 1 << nb
+  int32_t n;                 // cells per axis
   int32_t pad;
   double t;                  // time of this evaluation
   double wall_d[6];          // plane offset of each wall at time t
   double wall_v[6][3];       // velocity of each wall at time t
+};
+
+// Sorted-slot records read by the contact search: one 32 B load for the
+// geometry and one 8 B load for the identity of each candidate.
+struct alignas(32) SortedGeom {
+  double x, y, z, s;
+};
+struct alignas(8) SortedId {
+  int32_t agg;
+  uint32_t id;
 };
 
 struct PileDev {
@@ -57,7 +67,7 @@ struct PileDev {
   int32_t g_tile;            // gravity tile (slots per tile)
   int32_t g_nt;              // gravity tiles
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
-  int32_t nb_periodic;       // cells per axis = 1 << nb_periodic for a periodic pile
+  int32_t n_periodic;        // cells per axis of a periodic pile
   int32_t member_scan;       // 1: reduction finds members by scanning all spheres
   int32_t pad2;
   double box;                // periodic cube side
@@ -113,9 +123,11 @@ struct PileDev {
   double* tau;               // [3][ns]
   uint32_t* key;             // [ns] Morton cell code
   uint32_t* sidx;            // [ns] sphere at sorted slot
+  uint32_t* sidx_raw;        // [ns] sphere at slot, in atomic arrival order
   uint32_t* slot;            // [ns] sorted slot of sphere
-  double* xs;                // [4][ns] sorted x, y, z, radius
-  int32_t* sagg;             // [ns] sorted aggregate id
+  double* xs;                // [4][ns] sorted x, y, z, radius (gravity)
+  SortedGeom* xg;            // [ns] sorted x, y, z, radius (search)
+  SortedId* sid;             // [ns] sorted aggregate id and sphere id
   void* jrec;                // gravity records in sorted order (64 B FP64 / 32 B FP32)
   double* ganchor;           // [g_nt][4] FP64 anchor of each tile (relative coordinates)
   void* gpart;               // [g_nt][3][ns] per-tile partial sums (sorted slots)
@@ -274,14 +286,25 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, 
   return c;
 }
 
-// Signed distance of a point from wall w at the grid's evaluation time,
-// rounded step by step (no fused multiply-add) so that the contact decision
-// is reproducible: ((n_x x + n_y y) + n_z z) - d(t).
-__device__ __forceinline__ double wall_gap(const PileDev& P, const Grid& g, int w, double x,
-                                           double y, double z) {
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  This bijection of [0, n) gives XCD x (blocks b with b % 8 == x) one
+// contiguous range of logical blocks, so spatially adjacent work shares an
+// L2 instead of being fetched by every XCD.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int x = b % kXcds, r = b / kXcds, q = n / kXcds, rem = n % kXcds;
+  return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+}
+
+// Signed distance of a point from wall w at the evaluation time (plane
+// offset d_t = Grid::wall_d[w]), rounded step by step (no fused
+// multiply-add) so that the contact decision is reproducible:
+// ((n_x x + n_y y) + n_z z) - d_t.
+__device__ __forceinline__ double wall_gap(const PileDev& P, int w, double d_t, double x, double y,
+                                           double z) {
   const double* n = P.wall[w];
   const double s = __dadd_rn(__dadd_rn(__dmul_rn(n[0], x), __dmul_rn(n[1], y)), __dmul_rn(n[2], z));
-  return __dadd_rn(s, -g.wall_d[w]);
+  return __dadd_rn(s, -d_t);
 }
 
 }  // namespace dem

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const PileDev* __restrict__ pi
                                                   const double* __restrict__ pos_in,
                                                   const double* __restrict__ vel_in,
                                                   const double* __restrict__ spin_in) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int A = w.base + threadIdx.x;
   if (A >= P.na) return;
@@ -217,7 +217,7 @@ __device__ void rk5_rotate(double y[7], const double I[3], const double N[3], do
 __global__ __launch_bounds__(kBlock) void k_integrate(PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl,
                                                       ContactParams cp, int mode) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   PileDev& P = piles[w.pile];
   const int A = w.base + threadIdx.x;
   if (A >= P.na || P.status != 0) return;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(PileDev* __restrict__ pile
 // for the per-pile cell grid.
 __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restrict__ piles,
                                                         const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   if (P.status != 0) return;
   const int i = w.base + threadIdx.x;
@@ -387,17 +387,17 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
     return;
   }
   if (P.periodic) {
-    g.nb = P.nb_periodic;
+    g.n = P.n_periodic;
     g.lo[0] = g.lo[1] = g.lo[2] = 0.0;
-    g.cell = P.box / (double)(1 << g.nb);
+    g.cell = P.box / (double)g.n;
   } else {
-    g.nb = P.bits;
+    g.n = 1 << P.bits;
     double ext = 0.0;
     for (int k = 0; k < 3; ++k) {
       g.lo[k] = vals[k];
       ext = fmax(ext, vals[3 + k] - vals[k]);
     }
-    const double fit = ext * (1.0 + 1e-12) / (double)(1 << g.nb) + 1e-300;
+    const double fit = ext * (1.0 + 1e-12) / (double)g.n + 1e-300;
     g.cell = fmax(P.cell_min, fit);
   }
   g.inv_cell = 1.0 / g.cell;
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl,
                                                    ContactParams cp, int mode) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int A = w.base + threadIdx.x;
   if (A >= P.na || P.status != 0) return;

@@ -5,8 +5,9 @@
 //
 // Binning is a counting sort on Morton cell codes: integer atomics build the
 // per-cell counts, a batched exclusive scan turns them into cell ranges, and
-// a per-cell insertion sort by sphere id makes the order deterministic.  The
-// search scans the 27 neighbouring cells of every sphere; each sphere lists
+// ranking each sphere by id within its cell makes the order deterministic.
+// The search scans the 27 neighbouring cells of every sphere (a group of
+// lanes per sphere, blocks mapped to XCDs by region); each sphere lists
 // its contacts with higher ids (the canonical upper list) and with lower ids
 // (the lower list) as count -> scan -> write, so the contact list comes out
 // in canonical (i, j) order without a global sort and without float atomics.
@@ -19,7 +20,7 @@ namespace {
 // Morton code of a sphere's cell on the pile's current grid.
 __device__ __forceinline__ void sphere_cell(const PileDev& P, const Grid& g, double x, double y,
                                             double z, int c[3]) {
-  const int n = 1 << g.nb;
+  const int n = g.n;
   c[0] = cell_coord(x, g.lo[0], g.inv_cell, n, P.periodic, P.box);
   c[1] = cell_coord(y, g.lo[1], g.inv_cell, n, P.periodic, P.box);
   c[2] = cell_coord(z, g.lo[2], g.inv_cell, n, P.periodic, P.box);
@@ -27,7 +28,7 @@ __device__ __forceinline__ void sphere_cell(const PileDev& P, const Grid& g, dou
 
 __global__ __launch_bounds__(kBlock) void k_bin(const PileDev* __restrict__ piles,
                                                 const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int i = w.base + threadIdx.x;
   if (i >= P.ns || P.status != 0) return;
@@ -40,47 +41,42 @@ __global__ __launch_bounds__(kBlock) void k_bin(const PileDev* __restrict__ pile
   atomicAdd(&P.cell_cnt[key], 1u);
 }
 
-// Place each sphere into its cell's range; the counts return to zero, ready
-// for the next step.
+// Place each sphere into its cell's range (in atomic arrival order); the
+// counts return to zero, ready for the next step.
 __global__ __launch_bounds__(kBlock) void k_scatter(const PileDev* __restrict__ piles,
                                                     const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int i = w.base + threadIdx.x;
   if (i >= P.ns || P.status != 0) return;
   const uint32_t key = P.key[i];
   const uint32_t k = atomicSub(&P.cell_cnt[key], 1u) - 1u;
-  P.sidx[P.cell_start[key] + k] = (uint32_t)i;
+  P.sidx_raw[P.cell_start[key] + k] = (uint32_t)i;
 }
 
-// The first slot of each cell sorts the cell's sphere ids (cells hold a few
-// spheres), making the binned order independent of atomic arrival order.
+// Order each cell's spheres by id, independent of atomic arrival order: the
+// sphere at raw slot k goes to its cell's start plus its rank (the number of
+// smaller ids in the cell).
 __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int k = w.base + threadIdx.x;
   if (k >= P.ns || P.status != 0) return;
-  uint32_t* __restrict__ sidx = P.sidx;
-  const uint32_t key = P.key[sidx[k]];
-  if (k > 0 && P.key[sidx[k - 1]] == key) return;
-  const uint32_t e = P.cell_start[key + 1];
-  for (uint32_t a = (uint32_t)k + 1; a < e; ++a) {
-    const uint32_t v = sidx[a];
-    uint32_t b = a;
-    while (b > (uint32_t)k && sidx[b - 1] > v) {
-      sidx[b] = sidx[b - 1];
-      --b;
-    }
-    sidx[b] = v;
-  }
+  const uint32_t* __restrict__ raw = P.sidx_raw;
+  const uint32_t i = raw[k];
+  const uint32_t key = P.key[i];
+  const uint32_t s0 = P.cell_start[key], s1 = P.cell_start[key + 1];
+  uint32_t r = 0;
+  for (uint32_t t = s0; t < s1; ++t) r += raw[t] < i;
+  P.sidx[s0 + r] = i;
 }
 
 // Sorted copies of positions, radii and aggregate ids (spatially coherent
 // reads in the search and in gravity) and the inverse permutation.
 __global__ __launch_bounds__(kBlock) void k_sorted_copy(const PileDev* __restrict__ piles,
                                                         const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int k = w.base + threadIdx.x;
   if (k >= P.ns || P.status != 0) return;
@@ -92,7 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_sorted_copy(const PileDev* __restric
   P.xs[ns + k] = y;
   P.xs[2 * ns + k] = z;
   P.xs[3 * ns + k] = s;
-  P.sagg[k] = P.agg[i];
+  P.xg[k] = SortedGeom{x, y, z, s};
+  P.sid[k] = SortedId{P.agg[i], i};
 }
 
 // Contact test exactly as written d^2 = (dx*dx + dy*dy) + dz*dz < S*S, each
@@ -126,89 +123,169 @@ __device__ __forceinline__ void sort_run(uint32_t* __restrict__ a, uint32_t n) {
   }
 }
 
-// One thread per sorted slot.  Scans the 27 neighbouring cells and finds
-// every j != i of another aggregate in contact, then the walls it touches.  Count mode stores the number
-// of contacts with j > i (upper) and j < i (lower) under sphere id i; write
-// mode stores the ids at the scanned offsets and sorts each run, after
-// checking the pile's contact capacity.
+// The search gives each sphere a group of kLanes lanes of one wave; the
+// lanes split the 27 neighbouring cells (and the walls) between them, so a
+// sphere's dependent cell-range and candidate loads run kLanes-wide.
+constexpr int kLanes = 8;
+constexpr int kGroups = kBlock / kLanes;   // spheres per block
+// Runs of up to this many contacts per sphere are gathered in LDS and
+// rank-sorted before they are written; longer runs are written in arrival
+// order and sorted in place by the group's first lane.
+constexpr int kRunLds = 16;
+
+__device__ __forceinline__ uint32_t group_sum(uint32_t v) {
+  v += __shfl_xor(v, 1, kLanes);
+  v += __shfl_xor(v, 2, kLanes);
+  v += __shfl_xor(v, 4, kLanes);
+  return v;
+}
+
+// kLanes lanes per sorted slot.  Every lane tests the spheres of its share of
+// the 27 neighbouring cells that belong to another aggregate, and its share
+// of the walls.  Count mode stores the number of contacts with j > i (upper)
+// and j < i (lower) under sphere id i; write mode collects the ids, sorts
+// each run and stores it at the scanned offsets, after checking the pile's
+// contact capacity.  Launched with kLanes blocks per work item.
 __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl, int write) {
-  const WorkItem w = wl[blockIdx.x];
+  __shared__ uint32_t buf_up[kGroups][kRunLds];
+  __shared__ uint32_t buf_lo[kGroups][kRunLds];
+  __shared__ uint32_t fill[kGroups][2];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const WorkItem w = wl[blk / kLanes];
   PileDev& P = piles[w.pile];
-  const int k = w.base + threadIdx.x;
-  if (k >= P.ns || P.status != 0) return;
+  const int grp = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
+  const int k = w.base + (blk % kLanes) * kGroups + grp;
+  if (k >= P.ns || P.status != 0) return;      // uniform over the lane group
   const int ns = P.ns, nxt = P.parity ^ 1;
   const Grid g = *P.grid;
-  const uint32_t* __restrict__ sidx = P.sidx;
-  const double* __restrict__ xs = P.xs;
-  const int32_t* __restrict__ sagg = P.sagg;
+  const SortedGeom* __restrict__ xg = P.xg;
+  const SortedId* __restrict__ sid = P.sid;
   const uint32_t* __restrict__ cstart = P.cell_start;
-  const uint32_t i = sidx[k];
-  const double x = xs[k], y = xs[ns + k], z = xs[2 * ns + k], si = xs[3 * ns + k];
-  const int ai = sagg[k];
+  const SortedId me = sid[k];
+  const SortedGeom mg = xg[k];
+  const uint32_t i = me.id;
+  const double x = mg.x, y = mg.y, z = mg.z, si = mg.s;
+  const int ai = me.agg;
   const int periodic = P.periodic;
   const double L = P.box;
   int c[3];
   sphere_cell(P, g, x, y, z, c);
-  const int n = 1 << g.nb;
+  const int n = g.n;
+  // neighbouring cells along an axis: c-1..c+1, or every cell when a
+  // periodic axis has fewer than three (so no cell is visited twice)
+  const bool all = periodic && n < 3;
+
   uint32_t* up_out = nullptr;
   uint32_t* lo_out = nullptr;
+  uint32_t run_up = 0, run_lo = 0;
+  bool in_lds = false;
   if (write) {
     const uint32_t tot_up = P.up_off[nxt][ns], tot_lo = P.lo_off[ns];
     if (tot_up > (uint32_t)P.cap_pairs || tot_lo > (uint32_t)P.cap_pairs) {
-      atomicOr(&P.status, kStCapacity);
+      if (lane == 0) atomicOr(&P.status, kStCapacity);
       return;
     }
-    up_out = P.pair_j[nxt] + P.up_off[nxt][i];
-    lo_out = P.lo_nbr + P.lo_off[i];
+    const uint32_t u0 = P.up_off[nxt][i], l0 = P.lo_off[i];
+    up_out = P.pair_j[nxt] + u0;
+    lo_out = P.lo_nbr + l0;
+    run_up = P.up_off[nxt][i + 1] - u0;
+    run_lo = P.lo_off[i + 1] - l0;
+    in_lds = run_up <= (uint32_t)kRunLds && run_lo <= (uint32_t)kRunLds;
+    if (lane == 0) {
+      fill[grp][0] = 0u;
+      fill[grp][1] = 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  // this lane's cells: d = lane, lane + kLanes, ... (d < 27)
+  uint32_t rs[4], re[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int d = lane + q * kLanes;
+    const int ox = d % 3, oy = (d / 3) % 3, oz = d / 9;
+    int cx, cy, cz;
+    bool ok;
+    if (all) {
+      cx = ox;
+      cy = oy;
+      cz = oz;
+      ok = cx < n && cy < n && cz < n;
+    } else {
+      cx = c[0] + ox - 1;
+      cy = c[1] + oy - 1;
+      cz = c[2] + oz - 1;
+      if (periodic) {
+        cx += cx < 0 ? n : (cx >= n ? -n : 0);
+        cy += cy < 0 ? n : (cy >= n ? -n : 0);
+        cz += cz < 0 ? n : (cz >= n ? -n : 0);
+        ok = true;
+      } else {
+        ok = cx >= 0 && cx < n && cy >= 0 && cy < n && cz >= 0 && cz < n;
+      }
+    }
+    ok = ok && d < 27;
+    const uint32_t key = ok ? morton3(cx, cy, cz) : 0u;
+    rs[q] = ok ? cstart[key] : 0u;
+    re[q] = ok ? cstart[key + 1] : 0u;
   }
   uint32_t nup = 0, nlo = 0;
-  // neighbouring cells along an axis: c-1..c+1, or every cell when a
-  // periodic axis has fewer than three (so no cell is visited twice)
-  const int lo_d = (periodic && n < 3) ? 0 : -1;
-  const int hi_d = (periodic && n < 3) ? n - 1 : 1;
-  for (int dz = lo_d; dz <= hi_d; ++dz) {
-    int cz = (periodic && n < 3) ? dz : c[2] + dz;
-    if (periodic) cz &= n - 1;
-    else if (cz < 0 || cz >= n) continue;
-    for (int dy = lo_d; dy <= hi_d; ++dy) {
-      int cy = (periodic && n < 3) ? dy : c[1] + dy;
-      if (periodic) cy &= n - 1;
-      else if (cy < 0 || cy >= n) continue;
-      for (int dx = lo_d; dx <= hi_d; ++dx) {
-        int cx = (periodic && n < 3) ? dx : c[0] + dx;
-        if (periodic) cx &= n - 1;
-        else if (cx < 0 || cx >= n) continue;
-        const uint32_t key = morton3(cx, cy, cz);
-        const uint32_t t1 = cstart[key + 1];
-        for (uint32_t t = cstart[key]; t < t1; ++t) {
-          if (sagg[t] == ai) continue;        // same aggregate (includes t == k)
-          const double S = si + xs[3 * ns + t];
-          if (!touching(xs[t] - x, xs[ns + t] - y, xs[2 * ns + t] - z, S, periodic, L)) continue;
-          const uint32_t j = sidx[t];
-          if (j > i) {
-            if (write) up_out[nup] = j;
-            ++nup;
-          } else {
-            if (write) lo_out[nlo] = j;
-            ++nlo;
-          }
-        }
-      }
+  auto emit = [&](uint32_t j) {
+    const bool up = j > i;
+    if (up) ++nup;
+    else ++nlo;
+    if (!write) return;
+    const uint32_t pos = atomicAdd(&fill[grp][up ? 0 : 1], 1u);
+    if (in_lds) (up ? buf_up[grp] : buf_lo[grp])[pos] = j;
+    else (up ? up_out : lo_out)[pos] = j;
+  };
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (uint32_t t = rs[q]; t < re[q]; ++t) {
+      const SortedId o = sid[t];
+      if (o.agg == ai) continue;          // same aggregate (includes t == k)
+      const SortedGeom q = xg[t];
+      if (!touching(q.x - x, q.y - y, q.z - z, si + q.s, periodic, L)) continue;
+      emit(o.id);
     }
   }
   // walls are partners ns + w, after every sphere partner
-  for (int wl_ = 0; wl_ < P.n_walls; ++wl_) {
-    if (!(wall_gap(P, g, wl_, x, y, z) < si)) continue;
-    if (write) up_out[nup] = (uint32_t)(ns + wl_);
-    ++nup;
+  for (int wi_ = lane; wi_ < P.n_walls; wi_ += kLanes)
+    if (wall_gap(P, wi_, P.grid->wall_d[wi_], x, y, z) < si) emit((uint32_t)(ns + wi_));
+
+  if (!write) {
+    nup = group_sum(nup);
+    nlo = group_sum(nlo);
+    if (lane == 0) {
+      P.cnt_up[i] = nup;
+      P.cnt_lo[i] = nlo;
+    }
+    return;
   }
-  if (write) {
-    sort_run(up_out, nup);
-    sort_run(lo_out, nlo);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (in_lds) {
+    // rank sort: ids in a run are distinct, so each entry's rank is the
+    // number of smaller entries
+    for (uint32_t e = lane; e < run_up; e += kLanes) {
+      const uint32_t v = buf_up[grp][e];
+      uint32_t r = 0;
+      for (uint32_t f = 0; f < run_up; ++f) r += buf_up[grp][f] < v;
+      up_out[r] = v;
+    }
+    for (uint32_t e = lane; e < run_lo; e += kLanes) {
+      const uint32_t v = buf_lo[grp][e];
+      uint32_t r = 0;
+      for (uint32_t f = 0; f < run_lo; ++f) r += buf_lo[grp][f] < v;
+      lo_out[r] = v;
+    }
   } else {
-    P.cnt_up[i] = nup;
-    P.cnt_lo[i] = nlo;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    if (lane == 0) {
+      sort_run(up_out, run_up);
+      sort_run(lo_out, run_lo);
+    }
   }
 }
 
@@ -227,8 +304,8 @@ void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl
   hipLaunchKernelGGL(k_sorted_copy, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write) {
-  hipLaunchKernelGGL(k_search, dim3(nblk), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), wl,
-                     write);
+  hipLaunchKernelGGL(k_search, dim3(nblk * kLanes), dim3(kBlock), 0, st, const_cast<PileDev*>(piles),
+                     wl, write);
 }
 
 }  // namespace dem

@@ -67,7 +67,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
                                                   const WorkItem* __restrict__ wl,
                                                   ContactParams cp) {
-  const WorkItem w = wl[blockIdx.x];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   PileDev& P = piles[w.pile];
   const int i = w.base + threadIdx.x;
   if (i >= P.ns || P.status != 0) return;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
       // the perpendicular and the normal points from the sphere into the wall
       const int wi_ = (int)(j - (uint32_t)ns);
       const Grid& g = *P.grid;
-      const double gap = wall_gap(P, g, wi_, rix, riy, riz);
+      const double gap = wall_gap(P, wi_, g.wall_d[wi_], rix, riy, riz);
       n = mk<T>((T)-P.wall[wi_][0], (T)-P.wall[wi_][1], (T)-P.wall[wi_][2]);
       delta_d = si - gap;
       li_d = gap;
