@@ -161,6 +161,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.grid, 1);
   L.add(&h.cell_cnt, z.cells);
   L.add(&h.cell_start, z.cells + 1);
+  L.add(&h.run_cache, 2 * kRunCache * ns);
   L.add(&h.cnt_up, ns);
   L.add(&h.cnt_lo, ns);
   L.add(&h.up_off[0], ns + 1);
@@ -168,6 +169,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.lo_off, ns + 1);
   L.add(&h.pair_j[0], cap);
   L.add(&h.pair_j[1], cap);
+  L.add(&h.pair_i, cap);
   L.add(&h.hist[0], kHist * cap);
   L.add(&h.hist[1], kHist * cap);
   L.add(&h.lo_nbr, cap);

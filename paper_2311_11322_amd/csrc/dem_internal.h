@@ -17,6 +17,7 @@ constexpr int kBlock = 256;        // threads per block (4 wave64)
 constexpr int kHist = 7;           // spring history per contact: xi_t[3], xi_r[3], xi_q
 constexpr int kScanItems = 8;      // elements per thread in the batched scan
 constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kRunCache = 16;      // contact ids per run kept by the search's find pass
 
 // status bits of a pile (device-written)
 constexpr int kStCapacity = 1;
@@ -136,11 +137,13 @@ struct PileDev {
   Grid* grid;
   uint32_t* cell_cnt;        // [cells]
   uint32_t* cell_start;      // [cells + 1]
+  uint32_t* run_cache;       // [2][ns][kRunCache] sorted upper / lower runs by slot
   uint32_t* cnt_up;          // [ns]
   uint32_t* cnt_lo;          // [ns]
   uint32_t* up_off[2];       // [ns + 1] CSR of contacts (i, j>i) by i
   uint32_t* lo_off;          // [ns + 1] CSR of contacts (j<i, i) by i
   uint32_t* pair_j[2];       // [cap]
+  uint32_t* pair_i;          // [cap] owner i of each contact of the current upper list
   double* hist[2];           // [kHist][cap]
   uint32_t* lo_nbr;          // [cap] lower neighbour ids
   uint32_t* lo_pair;         // [cap] index of (j, i) in the upper list

@@ -129,9 +129,10 @@ __device__ __forceinline__ void sort_run(uint32_t* __restrict__ a, uint32_t n) {
 constexpr int kLanes = 8;
 constexpr int kGroups = kBlock / kLanes;   // spheres per block
 // Runs of up to this many contacts per sphere are gathered in LDS and
-// rank-sorted before they are written; longer runs are written in arrival
-// order and sorted in place by the group's first lane.
-constexpr int kRunLds = 16;
+// rank-sorted into a per-slot cache by the find pass; longer runs are found
+// again by the write pass, written in arrival order and sorted in place by
+// the group's first lane.
+constexpr int kRunLds = kRunCache;
 
 __device__ __forceinline__ uint32_t group_sum(uint32_t v) {
   v += __shfl_xor(v, 1, kLanes);
@@ -142,10 +143,15 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v) {
 
 // kLanes lanes per sorted slot.  Every lane tests the spheres of its share of
 // the 27 neighbouring cells that belong to another aggregate, and its share
-// of the walls.  Count mode stores the number of contacts with j > i (upper)
-// and j < i (lower) under sphere id i; write mode collects the ids, sorts
-// each run and stores it at the scanned offsets, after checking the pile's
-// contact capacity.  Launched with kLanes blocks per work item.
+// of the walls.
+//
+// Find mode stores the number of contacts with j > i (upper) and j < i
+// (lower) under sphere id i and, when both runs fit kRunLds entries, the
+// runs themselves sorted by id in the slot's cache.  Write mode (after the
+// scan) checks the pile's contact capacity and copies each cached run to its
+// offsets; a sphere whose runs did not fit is searched again and its runs
+// written in arrival order, then sorted in place.  Launched with kLanes
+// blocks per work item.
 __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl, int write) {
   __shared__ uint32_t buf_up[kGroups][kRunLds];
@@ -158,13 +164,49 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   const int k = w.base + (blk % kLanes) * kGroups + grp;
   if (k >= P.ns || P.status != 0) return;      // uniform over the lane group
   const int ns = P.ns, nxt = P.parity ^ 1;
-  const Grid g = *P.grid;
   const SortedGeom* __restrict__ xg = P.xg;
   const SortedId* __restrict__ sid = P.sid;
-  const uint32_t* __restrict__ cstart = P.cell_start;
   const SortedId me = sid[k];
-  const SortedGeom mg = xg[k];
   const uint32_t i = me.id;
+  uint32_t* cache_up = P.run_cache + (size_t)k * kRunLds;
+  uint32_t* cache_lo = P.run_cache + ((size_t)ns + k) * kRunLds;
+
+  uint32_t* up_out = nullptr;
+  uint32_t* lo_out = nullptr;
+  uint32_t* own_out = nullptr;
+  uint32_t run_up = 0, run_lo = 0;
+  if (write) {
+    const uint32_t tot_up = P.up_off[nxt][ns], tot_lo = P.lo_off[ns];
+    if (tot_up > (uint32_t)P.cap_pairs || tot_lo > (uint32_t)P.cap_pairs) {
+      if (lane == 0) atomicOr(&P.status, kStCapacity);
+      return;
+    }
+    const uint32_t u0 = P.up_off[nxt][i], l0 = P.lo_off[i];
+    up_out = P.pair_j[nxt] + u0;
+    own_out = P.pair_i + u0;
+    lo_out = P.lo_nbr + l0;
+    run_up = P.up_off[nxt][i + 1] - u0;
+    run_lo = P.lo_off[i + 1] - l0;
+    if (run_up <= (uint32_t)kRunLds && run_lo <= (uint32_t)kRunLds) {
+      // the find pass kept both runs, sorted
+      for (uint32_t e = lane; e < run_up; e += kLanes) {
+        up_out[e] = cache_up[e];
+        own_out[e] = i;
+      }
+      for (uint32_t e = lane; e < run_lo; e += kLanes) lo_out[e] = cache_lo[e];
+      return;
+    }
+  }
+  if (lane == 0) {
+    fill[grp][0] = 0u;
+    fill[grp][1] = 0u;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+
+  const Grid g = *P.grid;
+  const uint32_t* __restrict__ cstart = P.cell_start;
+  const SortedGeom mg = xg[k];
   const double x = mg.x, y = mg.y, z = mg.z, si = mg.s;
   const int ai = me.agg;
   const int periodic = P.periodic;
@@ -175,30 +217,6 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   // neighbouring cells along an axis: c-1..c+1, or every cell when a
   // periodic axis has fewer than three (so no cell is visited twice)
   const bool all = periodic && n < 3;
-
-  uint32_t* up_out = nullptr;
-  uint32_t* lo_out = nullptr;
-  uint32_t run_up = 0, run_lo = 0;
-  bool in_lds = false;
-  if (write) {
-    const uint32_t tot_up = P.up_off[nxt][ns], tot_lo = P.lo_off[ns];
-    if (tot_up > (uint32_t)P.cap_pairs || tot_lo > (uint32_t)P.cap_pairs) {
-      if (lane == 0) atomicOr(&P.status, kStCapacity);
-      return;
-    }
-    const uint32_t u0 = P.up_off[nxt][i], l0 = P.lo_off[i];
-    up_out = P.pair_j[nxt] + u0;
-    lo_out = P.lo_nbr + l0;
-    run_up = P.up_off[nxt][i + 1] - u0;
-    run_lo = P.lo_off[i + 1] - l0;
-    in_lds = run_up <= (uint32_t)kRunLds && run_lo <= (uint32_t)kRunLds;
-    if (lane == 0) {
-      fill[grp][0] = 0u;
-      fill[grp][1] = 0u;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
   // this lane's cells: d = lane, lane + kLanes, ... (d < 27)
   uint32_t rs[4], re[4];
 #pragma unroll
@@ -230,23 +248,21 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
     rs[q] = ok ? cstart[key] : 0u;
     re[q] = ok ? cstart[key + 1] : 0u;
   }
-  uint32_t nup = 0, nlo = 0;
+  // find mode keeps the first kRunLds ids of each run in LDS; write mode
+  // (runs too long for the cache) writes them straight to the runs
   auto emit = [&](uint32_t j) {
     const bool up = j > i;
-    if (up) ++nup;
-    else ++nlo;
-    if (!write) return;
     const uint32_t pos = atomicAdd(&fill[grp][up ? 0 : 1], 1u);
-    if (in_lds) (up ? buf_up[grp] : buf_lo[grp])[pos] = j;
-    else (up ? up_out : lo_out)[pos] = j;
+    if (write) (up ? up_out : lo_out)[pos] = j;
+    else if (pos < (uint32_t)kRunLds) (up ? buf_up[grp] : buf_lo[grp])[pos] = j;
   };
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     for (uint32_t t = rs[q]; t < re[q]; ++t) {
       const SortedId o = sid[t];
       if (o.agg == ai) continue;          // same aggregate (includes t == k)
-      const SortedGeom q = xg[t];
-      if (!touching(q.x - x, q.y - y, q.z - z, si + q.s, periodic, L)) continue;
+      const SortedGeom cg = xg[t];
+      if (!touching(cg.x - x, cg.y - y, cg.z - z, si + cg.s, periodic, L)) continue;
       emit(o.id);
     }
   }
@@ -254,38 +270,36 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   for (int wi_ = lane; wi_ < P.n_walls; wi_ += kLanes)
     if (wall_gap(P, wi_, P.grid->wall_d[wi_], x, y, z) < si) emit((uint32_t)(ns + wi_));
 
-  if (!write) {
-    nup = group_sum(nup);
-    nlo = group_sum(nlo);
-    if (lane == 0) {
-      P.cnt_up[i] = nup;
-      P.cnt_lo[i] = nlo;
-    }
-    return;
-  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  if (in_lds) {
-    // rank sort: ids in a run are distinct, so each entry's rank is the
-    // number of smaller entries
-    for (uint32_t e = lane; e < run_up; e += kLanes) {
-      const uint32_t v = buf_up[grp][e];
-      uint32_t r = 0;
-      for (uint32_t f = 0; f < run_up; ++f) r += buf_up[grp][f] < v;
-      up_out[r] = v;
-    }
-    for (uint32_t e = lane; e < run_lo; e += kLanes) {
-      const uint32_t v = buf_lo[grp][e];
-      uint32_t r = 0;
-      for (uint32_t f = 0; f < run_lo; ++f) r += buf_lo[grp][f] < v;
-      lo_out[r] = v;
-    }
-  } else {
+  if (write) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    for (uint32_t e = lane; e < run_up; e += kLanes) own_out[e] = i;
     if (lane == 0) {
       sort_run(up_out, run_up);
       sort_run(lo_out, run_lo);
     }
+    return;
+  }
+  const uint32_t nup = fill[grp][0], nlo = fill[grp][1];
+  if (lane == 0) {
+    P.cnt_up[i] = nup;
+    P.cnt_lo[i] = nlo;
+  }
+  if (nup > (uint32_t)kRunLds || nlo > (uint32_t)kRunLds) return;
+  // rank sort into the cache: ids in a run are distinct, so each entry's
+  // rank is the number of smaller entries
+  for (uint32_t e = lane; e < nup; e += kLanes) {
+    const uint32_t v = buf_up[grp][e];
+    uint32_t r = 0;
+    for (uint32_t f = 0; f < nup; ++f) r += buf_up[grp][f] < v;
+    cache_up[r] = v;
+  }
+  for (uint32_t e = lane; e < nlo; e += kLanes) {
+    const uint32_t v = buf_lo[grp][e];
+    uint32_t r = 0;
+    for (uint32_t f = 0; f < nlo; ++f) r += buf_lo[grp][f] < v;
+    cache_lo[r] = v;
   }
 }
 

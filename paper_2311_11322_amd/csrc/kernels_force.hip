@@ -4,13 +4,14 @@
 // friction, history kept while the contact lasts; Sec. 2.2.5: forces act at
 // the contact point, lever arm of Eq. 8, torque of Eq. 9).
 //
-// One thread per sphere i walks its canonical upper list (contacts (i, j),
-// j > i, sorted by j).  The previous step's upper list of i is sorted too, so
-// the history lookup is a merge walk.  The thread then maps its lower list
-// (contacts (j, i), j < i) to indices in j's upper list, which the per-sphere
-// gather uses.  A wall is partner ns + w: infinite mass, no spin, moving
-// rigidly; its reaction goes nowhere.  Geometry (separation, distance, overlap) is always FP64; the
-// force arithmetic runs in T (double, or float for the FP32-force form).
+// One thread per contact (i, j) of the canonical upper list (j > i, runs
+// sorted by j).  The previous step's upper run of i is sorted too, so the
+// history lookup is a short search.  The thread also maps j's lower-list
+// entry for i to the contact's index, which the per-sphere gather uses.  A
+// wall is partner ns + w: infinite mass, no spin, moving rigidly; its
+// reaction goes nowhere.  Geometry (separation, distance, overlap) is always
+// FP64; the force arithmetic runs in T (double, or float for the FP32-force
+// form).
 #include "dem_internal.h"
 
 namespace dem {
@@ -63,38 +64,47 @@ __device__ __forceinline__ V3<T> cap_spring(V3<T> xi, T k, T limit, bool* capped
   return xi;
 }
 
+// Blocks of the force kernel per work item (a work item covers 256 spheres,
+// and a pile has about three upper-list contacts per sphere).
+constexpr int kPairSplit = 4;
+
+// One thread per contact (i, j) of the new upper list, grid-stride over the
+// pile's contacts.  The history lookup searches i's previous (sorted) upper
+// run; the thread also records where (i, j) sits for j's lower list.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
                                                   const WorkItem* __restrict__ wl,
                                                   ContactParams cp) {
-  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const WorkItem w = wl[blk / kPairSplit];
   PileDev& P = piles[w.pile];
-  const int i = w.base + threadIdx.x;
-  if (i >= P.ns || P.status != 0) return;
+  if (P.status != 0) return;
   const int ns = P.ns, na = P.na, cap = P.cap_pairs;
   const int cur = P.parity, nxt = cur ^ 1;
   const uint32_t* __restrict__ new_j = P.pair_j[nxt];
-  const uint32_t* __restrict__ new_off = P.up_off[nxt];
+  const uint32_t* __restrict__ own = P.pair_i;
+  const uint32_t* __restrict__ old_off = P.up_off[cur];
   const uint32_t* __restrict__ old_j = P.pair_j[cur];
   const double* __restrict__ old_h = P.hist[cur];
   double* __restrict__ new_h = P.hist[nxt];
+  const uint32_t n_pairs = P.up_off[nxt][ns];
+  if (n_pairs > (uint32_t)cap) return;
   const int periodic = P.periodic;
   const double L = P.box;
-
-  const double rix = P.r[i], riy = P.r[ns + i], riz = P.r[2 * ns + i];
-  const double si = P.s[i];
-  const int Ai = P.agg[i];
-  const V3<T> vi = mk<T>(P.v[i], P.v[ns + i], P.v[2 * ns + i]);
-  const V3<T> wi = mk<T>(P.wA[Ai], P.wA[na + Ai], P.wA[2 * na + Ai]);
-  const double Mi = P.M[Ai];
   const T h = (T)cp.dt;
   const T kn = (T)cp.k_n, kt = (T)cp.k_t, kr = (T)cp.k_r, kq = (T)cp.k_q;
-
-  uint32_t o = P.up_off[cur][i];
-  const uint32_t o1 = P.up_off[cur][i + 1];
+  const uint32_t nbp = (uint32_t)((ns + kBlock - 1) / kBlock) * kPairSplit;
+  const uint32_t first = ((uint32_t)(w.base / kBlock) * kPairSplit + blk % kPairSplit) * kBlock;
   bool bad = false;
-  for (uint32_t p = new_off[i], p1 = new_off[i + 1]; p < p1; ++p) {
+  for (uint32_t p = first + threadIdx.x; p < n_pairs; p += nbp * kBlock) {
+    const uint32_t i = own[p];
     const uint32_t j = new_j[p];
+    const double rix = P.r[i], riy = P.r[ns + i], riz = P.r[2 * ns + i];
+    const double si = P.s[i];
+    const int Ai = P.agg[i];
+    const V3<T> vi = mk<T>(P.v[i], P.v[ns + i], P.v[2 * ns + i]);
+    const V3<T> wi = mk<T>(P.wA[Ai], P.wA[na + Ai], P.wA[2 * na + Ai]);
+    const double Mi = P.M[Ai];
     // geometry in FP64; partner velocity, spin and the reduced mass
     double delta_d, li_d, lj_d, mu, Rij_d, s_min;
     V3<T> n, vj, wj;
@@ -144,6 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
     const T lj = (T)lj_d;
 
     // history of this contact from the previous step, if it existed
+    uint32_t o = old_off[i];
+    const uint32_t o1 = old_off[i + 1];
     while (o < o1 && old_j[o] < j) ++o;
     T hs[kHist];
     if (o < o1 && old_j[o] == j) {
@@ -204,20 +216,18 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
 
     if (!isfinite((double)F.x) || !isfinite((double)F.y) || !isfinite((double)F.z)) bad = true;
     if (cp.max_overlap_frac > 0.0 && delta_d > cp.max_overlap_frac * s_min) bad = true;
+
+    // j's lower list holds i: point that entry at this contact
+    if (j < (uint32_t)ns) {
+      for (uint32_t e = P.lo_off[j], e1 = P.lo_off[j + 1]; e < e1; ++e) {
+        if (P.lo_nbr[e] == i) {
+          P.lo_pair[e] = p;
+          break;
+        }
+      }
+    }
   }
   if (bad) atomicOr(&P.status, kStUnstable);
-
-  // lower list: position of (j, i) inside j's upper list
-  for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
-    const uint32_t j = P.lo_nbr[e];
-    uint32_t lo = new_off[j], hi = new_off[j + 1];
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (new_j[mid] < (uint32_t)i) lo = mid + 1;
-      else hi = mid;
-    }
-    P.lo_pair[e] = lo;
-  }
 }
 
 }  // namespace
@@ -226,9 +236,9 @@ void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int 
                   ContactParams cp, int precision) {
   PileDev* p = const_cast<PileDev*>(piles);
   if (precision == 1)
-    hipLaunchKernelGGL(k_pairs<float>, dim3(nblk), dim3(kBlock), 0, st, p, wl, cp);
+    hipLaunchKernelGGL(k_pairs<float>, dim3(nblk * kPairSplit), dim3(kBlock), 0, st, p, wl, cp);
   else
-    hipLaunchKernelGGL(k_pairs<double>, dim3(nblk), dim3(kBlock), 0, st, p, wl, cp);
+    hipLaunchKernelGGL(k_pairs<double>, dim3(nblk * kPairSplit), dim3(kBlock), 0, st, p, wl, cp);
 }
 
 }  // namespace dem
