@@ -231,8 +231,9 @@ def contact_path_run(args, out):
     sl = dem.Sim(wl.params)
     sl.add_workload(wl)
     sl.step(2)
+    wall = timed_steps(sl, args.steps)          # graph replay, no per-kernel events
     sl.set_profiling(True)
-    wall = timed_steps(sl, args.steps)
+    timed_steps(sl, args.steps)
     pl = sl.profile()
     n_pairs = sl.counts()[2]
     sl.close()
@@ -273,13 +274,14 @@ def walled_runs(args, out, workers):
         wb = fills[shape]
         sb = dem.Sim(wb.params)
         sb.add_workload(wb)
-        if shape == "mixed":
-            sb.set_profiling(True)
         wall = timed_steps(sb, n_fill)
-        if shape == "mixed":
-            prof = sb.profile()
         per_shape[shape] = {"aggregates": wb.n_agg, "ms_per_step": round(1e3 * wall / n_fill, 4),
                             "contacts_at_end": sb.counts()[2]}
+        if shape == "mixed":
+            # per-kernel times over further steps, with an event around each kernel
+            sb.set_profiling(True)
+            timed_steps(sb, max(100, n_fill // 20))
+            prof = sb.profile()
         sb.close()
     wm = fills["mixed"]
     abl = {}
@@ -319,9 +321,10 @@ def walled_runs(args, out, workers):
     sn = dem.Sim(wn.params)
     sn.add_workload(wn)
     sn.step(2)
-    sn.set_profiling(True)
     n_bne = max(200, n_fill // 10)
     wall = timed_steps(sn, n_bne)
+    sn.set_profiling(True)
+    timed_steps(sn, max(100, n_bne // 4))
     pn = sn.profile()
     out["brazil_nut"] = {
         "workload": f"intruder R=6 among {wn.n_sph - 1} grain spheres ({wn.n_agg - 1} aggregates), "

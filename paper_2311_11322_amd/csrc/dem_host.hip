@@ -209,11 +209,11 @@ struct Batch {
   ScanSeg* seg_cells = nullptr;
   ScanItem* item_cells = nullptr;
   uint32_t* sums_cells = nullptr;
-  int n_seg_cells = 0, n_item_cells = 0;
+  int n_seg_cells = 0, n_item_cells = 0, max_items_cells = 0;
   ScanSeg* seg_pairs = nullptr;
   ScanItem* item_pairs = nullptr;
   uint32_t* sums_pairs = nullptr;
-  int n_seg_pairs = 0, n_item_pairs = 0;
+  int n_seg_pairs = 0, n_item_pairs = 0, max_items_pairs = 0;
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   bool dirty = true;
@@ -353,6 +353,9 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   HIPCHK(errsim, upload(b, &b.sums_pairs, zp, st));
   b.n_agg_blk = (int)wa.size();
   b.n_sph_blk = (int)wsph.size();
+  b.max_items_cells = b.max_items_pairs = 0;
+  for (const ScanSeg& g : sc) b.max_items_cells = std::max(b.max_items_cells, (int)g.n_items);
+  for (const ScanSeg& g : sp) b.max_items_pairs = std::max(b.max_items_pairs, (int)g.n_items);
   b.n_seg_cells = (int)sc.size();
   b.n_item_cells = (int)ic.size();
   b.n_seg_pairs = (int)sp.size();
@@ -381,7 +384,8 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(3);
   launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(4);
-  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells);
+  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
+              b.max_items_cells);
   mark(5);
   launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(6);
@@ -391,7 +395,8 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(8);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
   mark(9);
-  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs);
+  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
+              b.max_items_pairs);
   mark(10);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
   mark(11);
@@ -1171,12 +1176,14 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
   launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_grid(st, b.d_table, 1, kModeInit, 1.0);
   launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells);
+  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
+              b.max_items_cells);
   launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
-  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs);
+  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
+              b.max_items_pairs);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
   HIPCHK(s, hipGetLastError());
   PileDev tmp;

@@ -17,6 +17,7 @@ constexpr int kBlock = 256;        // threads per block (4 wave64)
 constexpr int kHist = 7;           // spring history per contact: xi_t[3], xi_r[3], xi_q
 constexpr int kScanItems = 8;      // elements per thread in the batched scan
 constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kScanSingleItems = 4;   // segments of at most this many chunks: one-launch scan
 constexpr int kRunCache = 16;      // contact ids per run kept by the search's find pass
 
 // status bits of a pile (device-written)
@@ -214,7 +215,7 @@ void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
-                 int n_items, uint32_t* item_sums);
+                 int n_items, uint32_t* item_sums, int max_seg_items);
 
 // ---------------------------------------------------------------------------
 // small device helpers

@@ -3,7 +3,8 @@
 // Many independent segments (the cell counts and contact counts of every
 // pile) are scanned by the same three launches: per-chunk totals, a scan of
 // each segment's chunk totals (one block per segment), and the chunk-local
-// scans with their offsets.  out[n] of each segment receives its total.
+// scans with their offsets; or, when every segment is short, by one launch
+// with a block per segment.  out[n] of each segment receives its total.
 // Integer arithmetic, so the result does not depend on the order of work.
 #include "dem_internal.h"
 
@@ -96,11 +97,44 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict_
   }
 }
 
+// One block per segment scans the whole segment chunk by chunk, carrying the
+// running total (one launch; for batches whose segments are all short).
+__global__ __launch_bounds__(kBlock) void k_scan_single(const ScanSeg* __restrict__ segs) {
+  const ScanSeg sg = segs[blockIdx.x];
+  uint32_t* __restrict__ out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
+  uint32_t carry = 0;
+  for (int c = 0; c < sg.n_items; ++c) {
+    const int64_t base = (int64_t)c * kScanChunk + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t e = base + k;
+      v[k] = e < sg.n ? sg.in[e] : 0u;
+      acc += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive(acc, &total) + carry;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t e = base + k;
+      if (e < sg.n) out[e] = run;
+      run += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[sg.n] = carry;
+}
+
 }  // namespace
 
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
-                 int n_items, uint32_t* item_sums) {
+                 int n_items, uint32_t* item_sums, int max_seg_items) {
   if (n_items <= 0) return;
+  if (max_seg_items <= kScanSingleItems) {
+    hipLaunchKernelGGL(k_scan_single, dim3(n_segs), dim3(kBlock), 0, st, segs);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
   hipLaunchKernelGGL(k_scan_chunks, dim3(n_segs), dim3(kBlock), 0, st, segs, item_sums);
   hipLaunchKernelGGL(k_scan_down, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
