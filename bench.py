@@ -42,8 +42,8 @@ CONTACT_BYTES_PER_CONTACT = 64
 # profile summaries); valid only for the gravity source it was measured on.
 MEASURED_TRAFFIC = {
     # (precision, spheres, default tile): (bytes per launch, sha256[:16] of kernels_gravity.hip)
-    ("fp64", 124958, 512): (2300.8e6, "833efd3db34c079e"),
-    ("fp32", 124958, 1024): (539.8e6, "833efd3db34c079e"),
+    ("fp64", 124958, 512): (2300.4e6, "093ba97f3690bd1f"),
+    ("fp32", 124958, 1024): (539.8e6, "093ba97f3690bd1f"),
 }
 
 
@@ -97,7 +97,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline workload (skip FP32-force, batched and served)")
     ap.add_argument("--piles", type=int, default=256)
-    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--lattice-sides", type=int, nargs="+", default=[50, 100],
+                    help="lattice edge lengths of the contact-path runs (n^3 spheres)")
     ap.add_argument("--fill-steps", type=int, default=10000,
                     help="steps of the box-filling runs (the paper profiles 10^4)")
     ap.add_argument("--box-batch", type=int, default=64, help="box fills batched in one engine")
@@ -223,36 +225,41 @@ def _box(seed_shape):
 
 
 def contact_path_run(args, out):
-    """The contact path alone on a contact-dense periodic lattice (no
-    gravity): every non-gravity kernel of the step, against the HBM roofline."""
+    """The contact path alone on contact-dense periodic lattices (no
+    gravity): every non-gravity kernel of the step, against the HBM roofline,
+    at 125k spheres (launch-latency bound) and at 1M spheres."""
     from paper_2311_11322_amd import dem
     from paper_2311_11322_amd import workloads as W
-    wl = W.dense_lattice(n_side=50)
-    sl = dem.Sim(wl.params)
-    sl.add_workload(wl)
-    sl.step(2)
-    wall = timed_steps(sl, args.steps)          # graph replay, no per-kernel events
-    sl.set_profiling(True)
-    timed_steps(sl, args.steps)
-    pl = sl.profile()
-    n_pairs = sl.counts()[2]
-    sl.close()
-    contact_ms = sum(v for k, v in pl.items() if not k.startswith("_") and k != "gravity") / pl["_steps"]
-    zbar = 2.0 * n_pairs / wl.n_sph
-    bytes_per_sphere = CONTACT_BYTES_FIXED + CONTACT_BYTES_PER_CONTACT * zbar
-    gbs = bytes_per_sphere * wl.n_sph / (contact_ms * 1e-3) / 1e9
-    out["contact_path"] = {
-        "workload": f"periodic lattice of {wl.n_sph} unit spheres (dumbbells + lone), "
-                    f"{n_pairs} contacts (z = {zbar:.2f}), FP64, no gravity",
-        "value": round(wl.n_sph * args.steps / wall, 1), "unit": "sphere-steps/s",
-        "ms_per_step": round(1e3 * wall / args.steps, 4),
-        "kernel_ms_per_step": {k: round(v / pl["_steps"], 4) for k, v in pl.items()
-                               if not k.startswith("_") and k != "gravity"},
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "algorithmic": f"{CONTACT_BYTES_FIXED} B + {CONTACT_BYTES_PER_CONTACT} B x "
-                                    f"z per sphere-step over all contact-path kernels"}}
-    log(f"contact path: {out['contact_path']}")
+    res = []
+    for n_side in args.lattice_sides:
+        wl = W.dense_lattice(n_side=n_side)
+        sl = dem.Sim(wl.params)
+        sl.add_workload(wl)
+        sl.step(2)
+        wall = timed_steps(sl, args.steps)          # graph replay, no per-kernel events
+        sl.set_profiling(True)
+        timed_steps(sl, args.steps)
+        pl = sl.profile()
+        n_pairs = sl.counts()[2]
+        sl.close()
+        kms = {k: v / pl["_steps"] for k, v in pl.items() if not k.startswith("_") and k != "gravity"}
+        contact_ms = sum(kms.values())
+        zbar = 2.0 * n_pairs / wl.n_sph
+        bytes_per_sphere = CONTACT_BYTES_FIXED + CONTACT_BYTES_PER_CONTACT * zbar
+        gbs = bytes_per_sphere * wl.n_sph / (contact_ms * 1e-3) / 1e9
+        res.append({
+            "workload": f"periodic lattice of {wl.n_sph} unit spheres (dumbbells + lone), "
+                        f"{n_pairs} contacts (z = {zbar:.2f}), FP64, no gravity",
+            "value": round(wl.n_sph * args.steps / wall, 1), "unit": "sphere-steps/s",
+            "ms_per_step": round(1e3 * wall / args.steps, 4),
+            "kernel_ms_per_step": {k: round(v, 4) for k, v in kms.items()},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "algorithmic": f"{CONTACT_BYTES_FIXED} B + {CONTACT_BYTES_PER_CONTACT} B "
+                                        "x z per sphere-step over the summed contact-path "
+                                        "kernel times"}})
+        log(f"contact path: {res[-1]}")
+    out["contact_path"] = res[0] if len(res) == 1 else res
 
 
 def walled_runs(args, out, workers):
@@ -426,7 +433,7 @@ def extra_runs(args, w, out, prec):
                            tuning=(tune["gravity_tile"], tune["cell_scale"]))
         st = srv.run(reqs)
         out["served"] = {
-            "workload": f"{len(reqs)} requests, Poisson arrivals at 20/s, collapse or spin-up, "
+            "workload": f"{len(reqs)} requests, Poisson arrivals at 20/s, collapse, spin-up or flyby, "
                         "1k-50k spheres, 100-5000 steps, FP32-force, 64 GiB admission budget",
             "p50_latency_s": round(st["p50_latency_s"], 3),
             "p99_latency_s": round(st["p99_latency_s"], 3),

@@ -365,10 +365,10 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
 }
 
 // Kernel families of one step, in launch order (profiling names).
-constexpr int kNumStages = 15;
+constexpr int kNumStages = 16;
 const char* const kStageNames =
     "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;sorted_copy;search_count;"
-    "scan_pairs;search_write;pairs;gravity;reduce;finish";
+    "scan_pairs;search_write;pairs;gravity;gather;reduce;finish";
 
 // Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
 // mark(k) is called before stage k and mark(kNumStages) after the last.
@@ -410,10 +410,12 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
     launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
   }
   mark(13);
-  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
+  launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(14);
-  launch_finish(st, b.d_table, np, mode, b.cp.dt);
+  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
   mark(15);
+  launch_finish(st, b.d_table, np, mode, b.cp.dt);
+  mark(16);
 }
 
 void enqueue_pass(Batch& b, hipStream_t st, int mode) {

@@ -210,6 +210,7 @@ void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem
                             int precision);
 // Supported tile sizes for a precision (default first); returns the count.
 int gravity_tiles(int precision, int* tiles);
+void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);

@@ -431,12 +431,44 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
 // GetAccelAndTorque (Eqs. 5-7, 9) and the closing half kick
 // ---------------------------------------------------------------------------
 
-// One thread per aggregate.  For each member sphere (in order): its contact
-// force and torque gathered in canonical contact order -- contacts (j, i)
-// with j < i by increasing j, then (i, j) by increasing j -- plus its
-// gravity force.  Then F_A = sum F_i, a_A = F_A / M + g,
-// N_A = sum [ (R b_i) x F_i + tau_i ], and in step mode v_A += h/2 a_A
-// followed by the spin-up increment about +z through the pile's centre.
+// One thread per sphere: its contact force and torque gathered in canonical
+// contact order -- contacts (j, i) with j < i by increasing j, then (i, j) by
+// increasing j (walls last) -- plus its gravity force.
+__global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ piles,
+                                                   const WorkItem* __restrict__ wl) {
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
+  const PileDev& P = piles[w.pile];
+  const int i = w.base + threadIdx.x;
+  if (i >= P.ns || P.status != 0) return;
+  const int ns = P.ns, nxt = P.parity ^ 1;
+  const int cap = P.cap_pairs;
+  const uint32_t* __restrict__ up_off = P.up_off[nxt];
+  double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+  for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
+    const uint32_t p = P.lo_pair[e];
+    for (int k = 0; k < 3; ++k) {
+      f[k] -= P.pF[k * cap + p];
+      t[k] += P.pTj[k * cap + p];
+    }
+  }
+  for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
+    for (int k = 0; k < 3; ++k) {
+      f[k] += P.pF[k * cap + p];
+      t[k] += P.pTi[k * cap + p];
+    }
+  }
+  if (P.G != 0.0)
+    for (int k = 0; k < 3; ++k) f[k] += P.gacc[k * ns + i];
+  for (int k = 0; k < 3; ++k) {
+    P.F[k * ns + i] = f[k];
+    P.tau[k * ns + i] = t[k];
+  }
+}
+
+// One thread per aggregate: F_A = sum F_i, a_A = F_A / M + g,
+// N_A = sum [ (R b_i) x F_i + tau_i ] over the members in order, and in step
+// mode v_A += h/2 a_A followed by the spin-up increment about +z through the
+// pile's centre.
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl,
                                                    ContactParams cp, int mode) {
@@ -445,13 +477,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
   const int A = w.base + threadIdx.x;
   if (A >= P.na || P.status != 0) return;
   const int na = P.na, ns = P.ns, nxt = P.parity ^ 1;
-  const int cap = P.cap_pairs;
-  const uint32_t* __restrict__ up_off = P.up_off[nxt];
   double q[4], R[9];
   for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
   quat_rot(q, R);
   double FA[3] = {0.0, 0.0, 0.0}, NA[3] = {0.0, 0.0, 0.0};
-  const bool grav = P.G != 0.0;
   // members: the contiguous segment, or (ablation of the paper's original
   // routines) every sphere of the pile tested for membership in order
   const bool scan = P.member_scan != 0;
@@ -459,31 +488,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
   const int i_hi = scan ? ns : P.first[A] + P.count[A];
   for (int i = i_lo; i < i_hi; ++i) {
     if (scan && P.agg[i] != A) continue;
-    double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
-    for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
-      const uint32_t p = P.lo_pair[e];
-      for (int k = 0; k < 3; ++k) {
-        f[k] -= P.pF[k * cap + p];
-        t[k] += P.pTj[k * cap + p];
-      }
-    }
-    for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
-      for (int k = 0; k < 3; ++k) {
-        f[k] += P.pF[k * cap + p];
-        t[k] += P.pTi[k * cap + p];
-      }
-    }
-    if (grav)
-      for (int k = 0; k < 3; ++k) f[k] += P.gacc[k * ns + i];
+    const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
     const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
     double d[3], dxf[3];
     rot_apply(R, bb, d);
     cross3(d, f, dxf);
     for (int k = 0; k < 3; ++k) {
-      P.F[k * ns + i] = f[k];
-      P.tau[k * ns + i] = t[k];
       FA[k] += f[k];
-      NA[k] += dxf[k] + t[k];
+      NA[k] += dxf[k] + P.tau[k * ns + i];
     }
   }
   const double M = P.M[A];
@@ -567,6 +579,10 @@ void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl
 void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, double dt) {
   hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), mode,
                      dt);
+}
+
+void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
+  hipLaunchKernelGGL(k_gather, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
