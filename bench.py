@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline workload (skip FP32-force, batched and served)")
     ap.add_argument("--piles", type=int, default=256)
+    ap.add_argument("--big-agg", type=int, default=100000,
+                    help="aggregates of the FP32-force 500k-sphere gravity run (0: skip)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--lattice-sides", type=int, nargs="+", default=[50, 100],
                     help="lattice edge lengths of the contact-path runs (n^3 spheres)")
@@ -344,6 +346,34 @@ def walled_runs(args, out, workers):
     log(f"brazil nut: {out['brazil_nut']}")
 
 
+def _big_collapse(n_agg):
+    from paper_2311_11322_amd import workloads as W
+    return W.collapse_cloud(2, n_agg=n_agg)
+
+
+def big_run(args, out, wbig):
+    """FP32-force gravity at 500k spheres (100,000 aggregates): a few steps."""
+    from paper_2311_11322_amd import dem
+    sb = dem.Sim(wbig.params, precision=dem.PREC_FP32_FORCE)
+    sb.add_workload(wbig)
+    sb.step(1)
+    nbig = 3
+    wall = timed_steps(sb, nbig)
+    sb.set_profiling(True)
+    timed_steps(sb, nbig)
+    pb = sb.profile()
+    sb.close()
+    gb_ms = pb["gravity"] / pb["_steps"]
+    nb = wbig.n_sph
+    achb = GRAVITY_FLOP_PER_PAIR * nb * (nb - 1) / (gb_ms * 1e-3) / 1e12
+    out["fp32_force_500k"] = {
+        "workload": f"collapse, {wbig.n_agg} aggregates of 2-8 spheres ({nb} spheres), FP32-force",
+        "value": round(nb * nbig / wall, 1), "unit": "sphere-steps/s",
+        "ms_per_step": round(1e3 * wall / nbig, 3), "gravity_ms": round(gb_ms, 3),
+        "gravity_frac_of_fp32_peak": round(achb / PEAK_TFLOPS["fp32"], 4)}
+    log(f"fp32-force 500k: {out['fp32_force_500k']}")
+
+
 def extra_runs(args, w, out, prec):
     """The FP32-force form on the same collapse, the batched spin-up piles
     (plain FP64 one pile at a time vs FP32-force batched in one engine) and
@@ -353,6 +383,9 @@ def extra_runs(args, w, out, prec):
     from paper_2311_11322_amd import dem, serve
     from paper_2311_11322_amd import workloads as W
     workers = min(16, len(os.sched_getaffinity(0)))
+    from concurrent.futures import ProcessPoolExecutor
+    big_pool = ProcessPoolExecutor(max_workers=1) if args.big_agg > 0 else None
+    big_fut = big_pool.submit(_big_collapse, args.big_agg) if big_pool else None
     # -- FP32-force form at 125k spheres
     if prec == dem.PREC_FP64:
         s32 = dem.Sim(w.params, precision=dem.PREC_FP32_FORCE)
@@ -441,6 +474,13 @@ def extra_runs(args, w, out, prec):
             "makespan_s": round(st["makespan_s"], 2), "completed": st["completed"],
             "failed": st["failed"]}
         log(f"served: {out['served']}")
+    # -- FP32-force gravity at 500k spheres, placed in the background meanwhile
+    if big_fut is not None:
+        t = time.time()
+        wbig = big_fut.result()
+        big_pool.shutdown()
+        log(f"big collapse: {wbig.n_sph} spheres (waited {time.time() - t:.1f} s)")
+        big_run(args, out, wbig)
 
 
 if __name__ == "__main__":

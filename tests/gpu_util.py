@@ -102,11 +102,13 @@ def compare_states(sim, o: O.Oracle, box=None, tol=1e-12, with_pairs=True):
         # force carries an error of k_n times a few ulp of |r| (the spring
         # history's bound), a sphere sums up to z of them, and the largest
         # force is at least k_n max(delta); carried into torques,
-        # accelerations and the velocities and spins they change
+        # accelerations and the velocities and spins they change (the
+        # spheres' predicted velocities are built from both)
         ns = s["r"].shape[0]
         z = np.bincount(np.concatenate([op["i"], op["j"][op["j"] < ns]]), minlength=ns)
         cond = hist_tolerance(s["r"], op["diag"][:, 4]) * max(1.0, float(z.max()))
-        for k in ("sph_force", "sph_torque", "agg_acc", "agg_torque", "agg_vel", "agg_spin"):
+        for k in ("sph_force", "sph_torque", "agg_acc", "agg_torque", "agg_vel", "agg_spin",
+                  "sph_vel"):
             tols[k] = max(tol, cond)
     if with_pairs:
         keys = oracle_keys(o)

@@ -139,3 +139,35 @@ def test_walled_piles_in_engine_match_alone(D):
         got = s.read_state(pairs=True)
         for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "pair_hist", "sph_force"):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
+
+
+def test_box_fill_full_size_parity(D):
+    """The box-filling workload at its full size (6,400 spheres, 40 x 40 x 240
+    box), floor and aggregate contacts seeded: t0, one step and 20 more
+    against the brute-force oracle, in the configuration the bench runs."""
+    w = W.box_fill(seed=11, floor_seeded=0.3, contact_seeded=True, z_range=(0, 120))
+    say("box fill full size", w.n_sph)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o)
+    sim.step(20)
+    o.step(20)
+    compare_states(sim, o, tol=1e-10)
+    assert (oracle_keys(o) & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)).sum() > 50
+
+
+def test_brazil_nut_full_size_parity(D):
+    """The Brazil-nut set-up at its full size (intruder + 4,000 grain spheres),
+    walls shaken, grains seeded on the floor: t0, one step and 30 more."""
+    w = W.brazil_nut(seed=12, floor_seeded=0.3)
+    say("brazil nut full size", w.n_sph)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o)
+    sim.step(30)
+    o.step(30)
+    compare_states(sim, o, tol=1e-10)
