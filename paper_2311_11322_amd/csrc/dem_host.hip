@@ -70,6 +70,31 @@ int periodic_cells(double L, double cell_min, int bits) {
   return std::max(1, std::min(n, 1 << bits));
 }
 
+// Spheres much larger than the rest -- above twice the median radius, if
+// there are at most kMaxBig of them -- are searched separately, so that the
+// cells can be sized for the others (a boulder among grains).
+void split_big(const double* radius, int64_t ns, double* s_cut, double* s_small, int* n_big) {
+  std::vector<double> r(radius, radius + ns);
+  std::nth_element(r.begin(), r.begin() + ns / 2, r.end());
+  const double cut = 2.0 * r[ns / 2];
+  int64_t nb = 0;
+  double small = 0.0, all = 0.0;
+  for (int64_t i = 0; i < ns; ++i) {
+    all = std::max(all, radius[i]);
+    if (radius[i] > cut) ++nb;
+    else small = std::max(small, radius[i]);
+  }
+  if (nb == 0 || nb > kMaxBig) {
+    *s_cut = INFINITY;
+    *s_small = all;
+    *n_big = 0;
+  } else {
+    *s_cut = cut;
+    *s_small = small;
+    *n_big = (int)nb;
+  }
+}
+
 int choose_bits(int64_t ns) {
   // at least two cells per sphere, 2..10 bits per axis
   int b = (ceil_log2(uint64_t(2 * ns)) + 2) / 3;
@@ -159,8 +184,8 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.bpart, 10 * z.n_rblk);
   L.add(&h.ppart, 3 * z.n_rblk);
   L.add(&h.grid, 1);
-  L.add(&h.cell_cnt, z.cells);
-  L.add(&h.cell_start, z.cells + 1);
+  L.add(&h.cell_cnt, z.cells + 1);          // + the cell of the big spheres
+  L.add(&h.cell_start, z.cells + 2);
   L.add(&h.run_cache, 2 * kRunCache * ns);
   L.add(&h.cnt_up, ns);
   L.add(&h.cnt_lo, ns);
@@ -198,6 +223,8 @@ struct Batch {
   WorkItem* wl_agg = nullptr;
   int n_agg_blk = 0;
   WorkItem* wl_sph = nullptr;
+  WorkItem* wl_big = nullptr;                // (pile, k-th big sphere)
+  int n_big_blk = 0;
   int n_sph_blk = 0;
   // gravity tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
@@ -294,7 +321,7 @@ hipError_t upload(Batch& b, T** dst, const std::vector<T>& src, hipStream_t st) 
 // device table entries must already be in place at slots 0..n-1.
 dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
-  std::vector<WorkItem> wa, wsph;
+  std::vector<WorkItem> wa, wsph, wbig;
   std::vector<GravItem> glg[3];
   int tiles[3] = {0, 0, 0};
   int n_groups = 0;
@@ -307,6 +334,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
     const PileDev& h = s->h;
     for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
     for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
+    for (int k = 0; k < h.n_big; ++k) wbig.push_back({p, k});
     if (h.G != 0.0) {
       b.any_grav = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
@@ -332,12 +360,14 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       segs.push_back(g);
     };
     PileDev* dentry = b.d_table + p;
-    add_seg(sc, ic, h.cell_cnt, h.cell_start, h.cell_start, nullptr, s->sz.cells);
+    add_seg(sc, ic, h.cell_cnt, h.cell_start, h.cell_start, nullptr, s->sz.cells + 1);
     add_seg(sp, ip, h.cnt_up, h.up_off[0], h.up_off[1], &dentry->parity, h.ns);
     add_seg(sp, ip, h.cnt_lo, h.lo_off, h.lo_off, nullptr, h.ns);
   }
   HIPCHK(errsim, upload(b, &b.wl_agg, wa, st));
   HIPCHK(errsim, upload(b, &b.wl_sph, wsph, st));
+  b.n_big_blk = (int)wbig.size();
+  if (!wbig.empty()) HIPCHK(errsim, upload(b, &b.wl_big, wbig, st));
   for (int g = 0; g < 3; ++g) {
     HIPCHK(errsim, upload(b, &b.gl[g], glg[g], st));
     b.n_grav[g] = (int)glg[g].size();
@@ -394,11 +424,13 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(8);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
+  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 0);
   mark(9);
   launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
               b.max_items_pairs);
   mark(10);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
+  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 1);
   mark(11);
   launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   mark(12);
@@ -550,6 +582,9 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
       h.pert_a[q][k] = 0.0;
     }
   }
+  h.s_cut = INFINITY;
+  h.s_small = 0.0;
+  h.n_big = 0;
   h.parity = 0;
   h.status = 0;
   h.step = 0;
@@ -695,10 +730,16 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
     if (agg_vel && !std::isfinite(agg_vel[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite velocity");
     if (agg_spin && !std::isfinite(agg_spin[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite spin");
   }
-  const double cell_min = s->tune.cell_scale * 2.0 * smax;
+  double s_cut, s_small;
+  int n_big;
+  split_big(radius, ns, &s_cut, &s_small, &n_big);
+  const double cell_min = s->tune.cell_scale * 2.0 * s_small;
   dem_status st = alloc_pile(s, n_agg, ns);
   if (st != DEM_OK) return st;
   s->h.cell_min = cell_min;
+  s->h.s_cut = s_cut;
+  s->h.s_small = s_small;
+  s->h.n_big = n_big;
   if (s->prm.periodic) s->h.n_periodic = periodic_cells(s->prm.box[0], cell_min, s->h.bits);
   hipStream_t str = s->stream;
   // constants: membership, radius, mass
@@ -730,7 +771,7 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
   launch_fill_u32(str, s->h.up_off[0], 0u, ns + 1);
   launch_fill_u32(str, s->h.up_off[1], 0u, ns + 1);
   launch_fill_u32(str, s->h.lo_off, 0u, ns + 1);
-  launch_fill_u32(str, s->h.cell_cnt, 0u, s->sz.cells);
+  launch_fill_u32(str, s->h.cell_cnt, 0u, s->sz.cells + 1);
   st = ensure_own_table(s);
   if (st != DEM_OK) return st;
   HIPCHK(s, put_entry(s, s->own.d_table, str));
@@ -946,7 +987,7 @@ dem_status dem_restore_state(dem_sim* s, const dem_state* in) {
       HIPCHK(s, hipStreamSynchronize(st));
     }
   }
-  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells);
+  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells + 1);
   h.status = 0;
   h.fail_step = -1;
   h.step = in->step;
@@ -1038,6 +1079,8 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   HIPCHK(s, hipMemcpyAsync(mass.data(), old.m, ns * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipStreamSynchronize(st));
   const double cell_min = old.cell_min;
+  const double s_cut = old.s_cut, s_small = old.s_small;
+  const int n_big = old.n_big;
   const int nbp = old.n_periodic;
   const int64_t step = old.step;
   free_meta(s->own);
@@ -1047,6 +1090,9 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   if (r != DEM_OK) return r;
   PileDev& h = s->h;
   h.cell_min = cell_min;
+  h.s_cut = s_cut;
+  h.s_small = s_small;
+  h.n_big = n_big;
   h.n_periodic = nbp;
   h.step = step;
   for (int k = 0; k < 3; ++k) {   // the perturber continues where it was
@@ -1168,7 +1214,7 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
   HIPCHK(s, hipMemcpyAsync(h.s, radius, n * 8, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(h.m, ones.data(), n * 8, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(h.agg, agg, n * 4, hipMemcpyHostToDevice, st));
-  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells);
+  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells + 1);
   r = ensure_own_table(s);
   if (r != DEM_OK) return fail(nullptr, r, s->err);
   HIPCHK(s, put_entry(s, s->own.d_table, st));

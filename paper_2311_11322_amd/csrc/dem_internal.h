@@ -18,7 +18,9 @@ constexpr int kHist = 7;           // spring history per contact: xi_t[3], xi_r[
 constexpr int kScanItems = 8;      // elements per thread in the batched scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kScanSingleItems = 4;   // segments of at most this many chunks: one-launch scan
-constexpr int kRunCache = 16;      // contact ids per run kept by the search's find pass
+constexpr int kRunCache = 16;
+constexpr int kMaxBig = 64;        // big spheres per pile searched separately
+constexpr int kBigRun = 2048;      // contacts per run of a big sphere (LDS sort)      // contact ids per run kept by the search's find pass
 
 // status bits of a pile (device-written)
 constexpr int kStCapacity = 1;
@@ -74,7 +76,13 @@ struct PileDev {
   int32_t pad2;
   double box;                // periodic cube side
   double G, soft_frac, spin_dw;
-  double cell_min;           // largest sphere diameter of the pile
+  double cell_min;           // cell side lower bound: largest diameter of the non-big spheres
+  // spheres with radius > s_cut ("big", at most kMaxBig) are not binned: they
+  // sit in one extra cell after the Morton cells and are searched by a block
+  // each; s_small is the largest radius of the others
+  double s_cut, s_small;
+  int32_t n_big;
+  int32_t pad4;
   // uniform field and container walls (host-set)
   int32_t n_walls;
   int32_t pad3;
@@ -198,6 +206,8 @@ void launch_scatter(hipStream_t st, const PileDev* piles, const WorkItem* wl, in
 void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
+void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                       int write);
 void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                   ContactParams cp, int precision);
 // Gravity: records and the per-slot combine cover every pile; the tile-pair

@@ -34,9 +34,14 @@ __global__ __launch_bounds__(kBlock) void k_bin(const PileDev* __restrict__ pile
   if (i >= P.ns || P.status != 0) return;
   const Grid g = *P.grid;
   const int ns = P.ns;
-  int c[3];
-  sphere_cell(P, g, P.r[i], P.r[ns + i], P.r[2 * ns + i], c);
-  const uint32_t key = morton3(c[0], c[1], c[2]);
+  uint32_t key;
+  if (P.n_big > 0 && P.s[i] > P.s_cut) {
+    key = 1u << (3 * P.bits);               // the cell after the Morton cells
+  } else {
+    int c[3];
+    sphere_cell(P, g, P.r[i], P.r[ns + i], P.r[2 * ns + i], c);
+    key = morton3(c[0], c[1], c[2]);
+  }
   P.key[i] = key;
   atomicAdd(&P.cell_cnt[key], 1u);
 }
@@ -168,6 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   const SortedId* __restrict__ sid = P.sid;
   const SortedId me = sid[k];
   const uint32_t i = me.id;
+  if (P.n_big > 0 && k >= ns - P.n_big) return;   // big spheres: k_search_big
   uint32_t* cache_up = P.run_cache + (size_t)k * kRunLds;
   uint32_t* cache_lo = P.run_cache + ((size_t)ns + k) * kRunLds;
 
@@ -248,6 +254,11 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
     rs[q] = ok ? cstart[key] : 0u;
     re[q] = ok ? cstart[key + 1] : 0u;
   }
+  if (lane == 3 && P.n_big > 0) {           // a free slot: the big spheres' cell
+    const uint32_t bk = 1u << (3 * P.bits);
+    rs[3] = cstart[bk];
+    re[3] = cstart[bk + 1];
+  }
   // find mode keeps the first kRunLds ids of each run in LDS; write mode
   // (runs too long for the cache) writes them straight to the runs
   auto emit = [&](uint32_t j) {
@@ -303,6 +314,127 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   }
 }
 
+// One block per big sphere (the k-th, by id, sits at slot ns - n_big + k):
+// its threads split the cells within reach of any other sphere and the big
+// spheres' cell.  Find mode stores the run lengths; write mode gathers both
+// runs in LDS, rank-sorts them and stores them at the scanned offsets.  A run
+// longer than kBigRun is a capacity failure.
+__global__ __launch_bounds__(kBlock) void k_search_big(PileDev* __restrict__ piles,
+                                                       const WorkItem* __restrict__ wl,
+                                                       int write) {
+  __shared__ uint32_t buf_up[kBigRun];
+  __shared__ uint32_t buf_lo[kBigRun];
+  __shared__ uint32_t fill[2];
+  const WorkItem w = wl[blockIdx.x];
+  PileDev& P = piles[w.pile];
+  if (P.status != 0) return;                   // uniform over the block
+  const int ns = P.ns, nxt = P.parity ^ 1;
+  const int k = ns - P.n_big + w.base;
+  const SortedId me = P.sid[k];
+  const SortedGeom mg = P.xg[k];
+  const uint32_t i = me.id;
+  const double x = mg.x, y = mg.y, z = mg.z, si = mg.s;
+  const int ai = me.agg;
+  uint32_t run_up = 0, run_lo = 0;
+  if (write) {
+    const uint32_t tot_up = P.up_off[nxt][ns], tot_lo = P.lo_off[ns];
+    run_up = P.up_off[nxt][i + 1] - P.up_off[nxt][i];
+    run_lo = P.lo_off[i + 1] - P.lo_off[i];
+    if (tot_up > (uint32_t)P.cap_pairs || tot_lo > (uint32_t)P.cap_pairs ||
+        run_up > (uint32_t)kBigRun || run_lo > (uint32_t)kBigRun) {
+      if (threadIdx.x == 0) atomicOr(&P.status, kStCapacity);
+      return;
+    }
+  }
+  if (threadIdx.x == 0) {
+    fill[0] = 0u;
+    fill[1] = 0u;
+  }
+  __syncthreads();
+  const SortedGeom* __restrict__ xg = P.xg;
+  const SortedId* __restrict__ sid = P.sid;
+  const uint32_t* __restrict__ cstart = P.cell_start;
+  const int periodic = P.periodic;
+  const double L = P.box;
+  const Grid& g = *P.grid;
+  const int n = g.n;
+  int c[3];
+  sphere_cell(P, g, x, y, z, c);
+  // reach in cells of any partner: (s_i + s_small) / cell, plus one for rounding
+  const int R = (int)ceil((si + P.s_small) * g.inv_cell) + 1;
+  int start[3], cnt[3];
+  for (int a = 0; a < 3; ++a) {
+    if (periodic) {
+      if (2 * R + 1 >= n) {
+        start[a] = 0;
+        cnt[a] = n;
+      } else {
+        start[a] = c[a] - R;
+        cnt[a] = 2 * R + 1;
+      }
+    } else {
+      const int lo = c[a] - R < 0 ? 0 : c[a] - R;
+      const int hi = c[a] + R > n - 1 ? n - 1 : c[a] + R;
+      start[a] = lo;
+      cnt[a] = hi - lo + 1;
+    }
+  }
+  auto test = [&](uint32_t t) {
+    const SortedId o = sid[t];
+    if (o.agg == ai) return;
+    const SortedGeom cg = xg[t];
+    if (!touching(cg.x - x, cg.y - y, cg.z - z, si + cg.s, periodic, L)) return;
+    const bool up = o.id > i;
+    const uint32_t pos = atomicAdd(&fill[up ? 0 : 1], 1u);
+    if (write) (up ? buf_up : buf_lo)[pos] = o.id;
+  };
+  const int total = cnt[0] * cnt[1] * cnt[2];
+  for (int u = threadIdx.x; u < total; u += kBlock) {
+    int cx = start[0] + u % cnt[0];
+    int cy = start[1] + (u / cnt[0]) % cnt[1];
+    int cz = start[2] + u / (cnt[0] * cnt[1]);
+    if (periodic) {
+      cx += cx < 0 ? n : (cx >= n ? -n : 0);
+      cy += cy < 0 ? n : (cy >= n ? -n : 0);
+      cz += cz < 0 ? n : (cz >= n ? -n : 0);
+    }
+    const uint32_t key = morton3(cx, cy, cz);
+    for (uint32_t t = cstart[key], t1 = cstart[key + 1]; t < t1; ++t) test(t);
+  }
+  const uint32_t bk = 1u << (3 * P.bits);
+  for (uint32_t t = cstart[bk] + threadIdx.x; t < cstart[bk + 1]; t += kBlock) test(t);
+  for (int wi_ = threadIdx.x; wi_ < P.n_walls; wi_ += kBlock) {
+    if (wall_gap(P, wi_, g.wall_d[wi_], x, y, z) < si) {
+      const uint32_t pos = atomicAdd(&fill[0], 1u);
+      if (write) buf_up[pos] = (uint32_t)(ns + wi_);
+    }
+  }
+  __syncthreads();
+  if (!write) {
+    if (threadIdx.x == 0) {
+      P.cnt_up[i] = fill[0];
+      P.cnt_lo[i] = fill[1];
+    }
+    return;
+  }
+  uint32_t* up_out = P.pair_j[nxt] + P.up_off[nxt][i];
+  uint32_t* own_out = P.pair_i + P.up_off[nxt][i];
+  uint32_t* lo_out = P.lo_nbr + P.lo_off[i];
+  for (uint32_t e = threadIdx.x; e < run_up; e += kBlock) {
+    const uint32_t v = buf_up[e];
+    uint32_t r = 0;
+    for (uint32_t f = 0; f < run_up; ++f) r += buf_up[f] < v;
+    up_out[r] = v;
+    own_out[e] = i;
+  }
+  for (uint32_t e = threadIdx.x; e < run_lo; e += kBlock) {
+    const uint32_t v = buf_lo[e];
+    uint32_t r = 0;
+    for (uint32_t f = 0; f < run_lo; ++f) r += buf_lo[f] < v;
+    lo_out[r] = v;
+  }
+}
+
 }  // namespace
 
 void launch_bin(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
@@ -316,6 +448,11 @@ void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, 
 }
 void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
   hipLaunchKernelGGL(k_sorted_copy, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+}
+void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                       int write) {
+  hipLaunchKernelGGL(k_search_big, dim3(nblk), dim3(kBlock), 0, st, const_cast<PileDev*>(piles),
+                     wl, write);
 }
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write) {
   hipLaunchKernelGGL(k_search, dim3(nblk * kLanes), dim3(kBlock), 0, st, const_cast<PileDev*>(piles),

@@ -823,3 +823,81 @@ def _place_around(rng, counts, clusters, base, height, x0, R, p_floor=0.0, max_t
     pos = np.concatenate([placed[a] for a in range(len(counts))])
     radius = np.concatenate([clusters[a][1] for a in range(len(counts))])
     return pos, radius
+
+
+def boulders(seed: int = 13, n_agg: int = 600, n_big: int = 6, big_radius: float = 4.0,
+             phi: float = 0.2, dt: float = 1e-4, vel_sigma: float = 0.05,
+             contact_seeded: bool = True, n_steps: int = 100) -> Workload:
+    """Polydisperse periodic cube: ``n_big`` single-sphere boulders of radius
+    ``big_radius`` among aggregates of 1-8 spheres of radius U[0.8, 1.2].
+    Boulders are placed first (with ``contact_seeded`` every other one
+    touches the previous one, overlap U[1e-5, 1e-3]); then the aggregates by
+    random sequential addition, every other one of the first 10 per boulder
+    (if seeded) set against a random boulder with the same kind of overlap.  The boulders come first in
+    the sphere order."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(1, 9, n_agg).astype(np.int32)
+    clusters = [random_cluster(rng, int(c)) for c in counts]
+    vol = sum(float(sphere_mass(c[1]).sum()) for c in clusters) + n_big * sphere_mass(
+        np.array([big_radius]))[0]
+    L = _box_side(vol, phi)
+
+    def mi(d):
+        return d - L * np.round(d / L)
+
+    bpos = []
+    while len(bpos) < n_big:
+        if contact_seeded and len(bpos) % 2 == 1:
+            u = _unit_vectors(rng, 1)[0]
+            c = np.mod(bpos[-1] + (2 * big_radius - rng.uniform(1e-5, 1e-3)) * u, L)
+            skip = len(bpos) - 1
+        else:
+            c = rng.uniform(0, L, 3)
+            skip = -1
+        ok = all(np.linalg.norm(mi(c - b)) - 2 * big_radius >= MIN_GAP
+                 for k, b in enumerate(bpos) if k != skip)
+        if ok:
+            bpos.append(c)
+    bpos = np.array(bpos)
+    grid = _Grid(np.zeros(3), None, 2.4, periodic=True, box=np.full(3, L))
+    placed = [None] * n_agg
+    order = np.argsort(-counts, kind="stable")
+    for n_done, a in enumerate(order):
+        rel, rad = clusters[a]
+        rel = rel - rel.mean(axis=0)
+        for _ in range(20000):
+            body = rel @ _random_rotation(rng).T
+            seeded = contact_seeded and n_done < 10 * n_big and n_done % 2 == 0
+            if seeded:
+                t = int(rng.integers(n_big))
+                m = int(rng.integers(body.shape[0]))
+                u = _unit_vectors(rng, 1)[0]
+                centre = bpos[t] + (big_radius + rad[m] - rng.uniform(1e-5, 1e-3)) * u - body[m]
+            else:
+                t = -1
+                centre = rng.uniform(0, L, 3)
+            centre = np.mod(centre, L)
+            p = centre + body
+            gb = np.linalg.norm(mi(p[:, None, :] - bpos[None, :, :]), axis=2) \
+                - (rad[:, None] + big_radius)
+            if t >= 0:
+                gb[m, t] = max(gb[m, t], MIN_GAP) if gb[m, t] < 0 else -1.0
+            if (gb < MIN_GAP).any():
+                continue
+            gap, _ = grid.gaps(p, rad)
+            if gap.size and (gap < MIN_GAP).any():
+                continue
+            grid.insert(p, rad)
+            placed[a] = p
+            break
+        else:
+            raise RuntimeError("boulder placement failed; lower the packing")
+    pos = np.concatenate([bpos] + [placed[a] for a in range(n_agg)])
+    radius = np.concatenate([np.full(n_big, big_radius)] + [clusters[a][1] for a in range(n_agg)])
+    counts = np.concatenate([np.ones(n_big, dtype=np.int32), counts]).astype(np.int32)
+    mass = sphere_mass(radius)
+    na = counts.shape[0]
+    params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=1, box=(L, L, L))
+    return Workload("boulders", counts, pos, radius, mass, rng.normal(0.0, vel_sigma, (na, 3)),
+                    np.zeros((na, 3)), params, n_steps,
+                    notes=f"{n_big} boulders R={big_radius}, periodic L={L:.3f}, seed={seed}")

@@ -364,3 +364,24 @@ def test_dense_lattice_parity(D):
     sim.step(2)
     o.step(2)
     compare_states(sim, o, box=L, tol=1e-10)
+
+
+def test_boulders_periodic_parity(D):
+    """Boulders (radius 4) among aggregates of unit-size spheres in a periodic
+    cube: the boulders are searched apart from the cell grid (sized for the
+    small spheres), across the periodic wrap, with boulder-boulder and
+    boulder-aggregate contacts seeded."""
+    say("boulders periodic")
+    w = W.boulders(seed=13)
+    L = w.params["box"][0]
+    sim, o = _pair(D, w)
+    compare_states(sim, o, box=L)
+    p = o.pairs()
+    assert ((p["i"] < 6) & (p["j"] < 6)).sum() >= 2 and (p["j"] >= 6).sum() >= 20
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o, box=L)
+    for _ in range(3):
+        sim.step(20)
+        o.step(20)
+        compare_states(sim, o, box=L, tol=1e-10)
