@@ -395,9 +395,9 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
 }
 
 // Kernel families of one step, in launch order (profiling names).
-constexpr int kNumStages = 16;
+constexpr int kNumStages = 15;
 const char* const kStageNames =
-    "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;sorted_copy;search_count;"
+    "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;search_count;"
     "scan_pairs;search_write;pairs;gravity;gather;reduce;finish";
 
 // Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
@@ -421,19 +421,17 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(6);
   launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(7);
-  launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(8);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
   if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 0);
-  mark(9);
+  mark(8);
   launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
               b.max_items_pairs);
-  mark(10);
+  mark(9);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
   if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 1);
-  mark(11);
+  mark(10);
   launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
-  mark(12);
+  mark(11);
   if (b.any_grav) {
     launch_gravity_records(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
     for (int g = 0; g < b.n_grav_groups; ++g)
@@ -441,13 +439,13 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
                            b.grav_tile[g]);
     launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
   }
-  mark(13);
+  mark(12);
   launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(14);
+  mark(13);
   launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
-  mark(15);
+  mark(14);
   launch_finish(st, b.d_table, np, mode, b.cp.dt);
-  mark(16);
+  mark(15);
 }
 
 void enqueue_pass(Batch& b, hipStream_t st, int mode) {
@@ -1228,7 +1226,6 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
               b.max_items_cells);
   launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  launch_sorted_copy(st, b.d_table, b.wl_sph, b.n_sph_blk);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
   launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
               b.max_items_pairs);

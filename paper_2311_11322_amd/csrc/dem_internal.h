@@ -45,8 +45,8 @@ struct Grid {
   double cell;               // cell side (>= largest sphere diameter)
   double inv_cell;
   double com[3];             // centre of mass of the pile (spin-up forcing)
-  int32_t n;                 // cells per axis
-  int32_t pad;
+  int32_t nc[3];             // cells per axis
+  int32_t nbits[3];          // key bits per axis (sum 3 * bits)
   double t;                  // time of this evaluation
   double wall_d[6];          // plane offset of each wall at time t
   double wall_v[6][3];       // velocity of each wall at time t
@@ -204,7 +204,6 @@ void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, do
 void launch_bin(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_scatter(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
-void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
 void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                        int write);
@@ -284,6 +283,18 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
 
 __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Cell key for per-axis bit counts b: with m = min(b), the Morton code of
+// the low m bits of each coordinate (a block of 2^m cells per axis), then the
+// block's row-major index above it -- a bijection onto [0, 2^(bx+by+bz)),
+// and the plain Morton code when the counts are equal.
+__device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, const int32_t nbits[3]) {
+  const int m = min(nbits[0], min(nbits[1], nbits[2]));
+  const uint32_t lo = (1u << m) - 1u;
+  const uint32_t blk = ((uint32_t)cx >> m) + (((uint32_t)cy >> m) << (nbits[0] - m)) +
+                       (((uint32_t)cz >> m) << (nbits[0] + nbits[1] - 2 * m));
+  return morton3((uint32_t)cx & lo, (uint32_t)cy & lo, (uint32_t)cz & lo) | (blk << (3 * m));
 }
 
 // Cell coordinate of a position on one axis.  Periodic piles wrap the

@@ -387,22 +387,44 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
     return;
   }
   if (P.periodic) {
-    g.n = P.n_periodic;
+    for (int k = 0; k < 3; ++k) {
+      g.nc[k] = P.n_periodic;
+      g.nbits[k] = P.bits;
+    }
     g.lo[0] = g.lo[1] = g.lo[2] = 0.0;
-    g.cell = P.box / (double)g.n;
+    g.cell = P.box / (double)P.n_periodic;
   } else {
-    g.n = 1 << P.bits;
-    double ext = 0.0;
+    // cube cells; the key's 3 * bits bits go one at a time to the axis whose
+    // cells are currently the longest, so an elongated pile (a tall box)
+    // gets more cells along its long axis
+    double ext[3];
+    int b[3] = {0, 0, 0};
     for (int k = 0; k < 3; ++k) {
       g.lo[k] = vals[k];
-      ext = fmax(ext, vals[3 + k] - vals[k]);
+      ext[k] = vals[3 + k] - vals[k];
     }
-    const double fit = ext * (1.0 + 1e-12) / (double)g.n + 1e-300;
-    g.cell = fmax(P.cell_min, fit);
+    for (int t = 0; t < 3 * P.bits; ++t) {
+      int a = -1;
+      double best = -1.0;
+      for (int k = 0; k < 3; ++k) {
+        const double len = ldexp(ext[k], -b[k]);
+        if (b[k] < 10 && len > best) {
+          best = len;
+          a = k;
+        }
+      }
+      ++b[a];
+    }
+    double fit = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      g.nbits[k] = b[k];
+      g.nc[k] = 1 << b[k];
+      fit = fmax(fit, ldexp(ext[k] * (1.0 + 1e-12), -b[k]));
+    }
+    g.cell = fmax(P.cell_min, fit + 1e-300);
   }
   g.inv_cell = 1.0 / g.cell;
   for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
-  g.pad = 0;
   // time of this evaluation: the end of the step being taken, or the
   // current time for an evaluation in place; walls displaced rigidly by
   // A sin(omega t + phase), moving at A omega cos(omega t + phase)

@@ -20,10 +20,9 @@ namespace {
 // Morton code of a sphere's cell on the pile's current grid.
 __device__ __forceinline__ void sphere_cell(const PileDev& P, const Grid& g, double x, double y,
                                             double z, int c[3]) {
-  const int n = g.n;
-  c[0] = cell_coord(x, g.lo[0], g.inv_cell, n, P.periodic, P.box);
-  c[1] = cell_coord(y, g.lo[1], g.inv_cell, n, P.periodic, P.box);
-  c[2] = cell_coord(z, g.lo[2], g.inv_cell, n, P.periodic, P.box);
+  c[0] = cell_coord(x, g.lo[0], g.inv_cell, g.nc[0], P.periodic, P.box);
+  c[1] = cell_coord(y, g.lo[1], g.inv_cell, g.nc[1], P.periodic, P.box);
+  c[2] = cell_coord(z, g.lo[2], g.inv_cell, g.nc[2], P.periodic, P.box);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin(const PileDev* __restrict__ piles,
@@ -40,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const PileDev* __restrict__ pile
   } else {
     int c[3];
     sphere_cell(P, g, P.r[i], P.r[ns + i], P.r[2 * ns + i], c);
-    key = morton3(c[0], c[1], c[2]);
+    key = cell_key(c[0], c[1], c[2], g.nbits);
   }
   P.key[i] = key;
   atomicAdd(&P.cell_cnt[key], 1u);
@@ -61,40 +60,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PileDev* __restrict__ 
 
 // Order each cell's spheres by id, independent of atomic arrival order: the
 // sphere at raw slot k goes to its cell's start plus its rank (the number of
-// smaller ids in the cell).
+// smaller ids in the cell).  The same thread writes the sphere's sorted
+// copies there -- positions and radius for gravity, packed records for the
+// search -- and the inverse permutation.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl) {
   const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
   const int k = w.base + threadIdx.x;
   if (k >= P.ns || P.status != 0) return;
+  const int ns = P.ns;
   const uint32_t* __restrict__ raw = P.sidx_raw;
   const uint32_t i = raw[k];
   const uint32_t key = P.key[i];
   const uint32_t s0 = P.cell_start[key], s1 = P.cell_start[key + 1];
   uint32_t r = 0;
   for (uint32_t t = s0; t < s1; ++t) r += raw[t] < i;
-  P.sidx[s0 + r] = i;
-}
-
-// Sorted copies of positions, radii and aggregate ids (spatially coherent
-// reads in the search and in gravity) and the inverse permutation.
-__global__ __launch_bounds__(kBlock) void k_sorted_copy(const PileDev* __restrict__ piles,
-                                                        const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
-  const PileDev& P = piles[w.pile];
-  const int k = w.base + threadIdx.x;
-  if (k >= P.ns || P.status != 0) return;
-  const int ns = P.ns;
-  const uint32_t i = P.sidx[k];
-  P.slot[i] = (uint32_t)k;
+  const uint32_t d = s0 + r;
+  P.sidx[d] = i;
+  P.slot[i] = d;
   const double x = P.r[i], y = P.r[ns + i], z = P.r[2 * ns + i], s = P.s[i];
-  P.xs[k] = x;
-  P.xs[ns + k] = y;
-  P.xs[2 * ns + k] = z;
-  P.xs[3 * ns + k] = s;
-  P.xg[k] = SortedGeom{x, y, z, s};
-  P.sid[k] = SortedId{P.agg[i], i};
+  P.xs[d] = x;
+  P.xs[ns + d] = y;
+  P.xs[2 * ns + d] = z;
+  P.xs[3 * ns + d] = s;
+  P.xg[d] = SortedGeom{x, y, z, s};
+  P.sid[d] = SortedId{P.agg[i], i};
 }
 
 // Contact test exactly as written d^2 = (dx*dx + dy*dy) + dz*dz < S*S, each
@@ -219,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
   const double L = P.box;
   int c[3];
   sphere_cell(P, g, x, y, z, c);
-  const int n = g.n;
+  const int n = g.nc[0];                  // periodic piles: the same on every axis
   // neighbouring cells along an axis: c-1..c+1, or every cell when a
   // periodic axis has fewer than three (so no cell is visited twice)
   const bool all = periodic && n < 3;
@@ -246,11 +237,11 @@ __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
         cz += cz < 0 ? n : (cz >= n ? -n : 0);
         ok = true;
       } else {
-        ok = cx >= 0 && cx < n && cy >= 0 && cy < n && cz >= 0 && cz < n;
+        ok = cx >= 0 && cx < g.nc[0] && cy >= 0 && cy < g.nc[1] && cz >= 0 && cz < g.nc[2];
       }
     }
     ok = ok && d < 27;
-    const uint32_t key = ok ? morton3(cx, cy, cz) : 0u;
+    const uint32_t key = ok ? cell_key(cx, cy, cz, g.nbits) : 0u;
     rs[q] = ok ? cstart[key] : 0u;
     re[q] = ok ? cstart[key + 1] : 0u;
   }
@@ -357,13 +348,13 @@ __global__ __launch_bounds__(kBlock) void k_search_big(PileDev* __restrict__ pil
   const int periodic = P.periodic;
   const double L = P.box;
   const Grid& g = *P.grid;
-  const int n = g.n;
   int c[3];
   sphere_cell(P, g, x, y, z, c);
   // reach in cells of any partner: (s_i + s_small) / cell, plus one for rounding
   const int R = (int)ceil((si + P.s_small) * g.inv_cell) + 1;
   int start[3], cnt[3];
   for (int a = 0; a < 3; ++a) {
+    const int n = g.nc[a];
     if (periodic) {
       if (2 * R + 1 >= n) {
         start[a] = 0;
@@ -394,11 +385,12 @@ __global__ __launch_bounds__(kBlock) void k_search_big(PileDev* __restrict__ pil
     int cy = start[1] + (u / cnt[0]) % cnt[1];
     int cz = start[2] + u / (cnt[0] * cnt[1]);
     if (periodic) {
+      const int n = g.nc[0];
       cx += cx < 0 ? n : (cx >= n ? -n : 0);
       cy += cy < 0 ? n : (cy >= n ? -n : 0);
       cz += cz < 0 ? n : (cz >= n ? -n : 0);
     }
-    const uint32_t key = morton3(cx, cy, cz);
+    const uint32_t key = cell_key(cx, cy, cz, g.nbits);
     for (uint32_t t = cstart[key], t1 = cstart[key + 1]; t < t1; ++t) test(t);
   }
   const uint32_t bk = 1u << (3 * P.bits);
@@ -445,9 +437,6 @@ void launch_scatter(hipStream_t st, const PileDev* piles, const WorkItem* wl, in
 }
 void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
   hipLaunchKernelGGL(k_cell_sort, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
-}
-void launch_sorted_copy(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
-  hipLaunchKernelGGL(k_sorted_copy, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                        int write) {
