@@ -471,6 +471,8 @@ def extra_runs(args, w, out, prec):
             "p50_latency_s": round(st["p50_latency_s"], 3),
             "p99_latency_s": round(st["p99_latency_s"], 3),
             "sphere_steps_per_s": round(st["sphere_steps_per_s"], 1),
+            "offered_rate_per_s": 20.0,
+            "service_rate_per_s": round(st["service_rate_per_s"], 2),
             "makespan_s": round(st["makespan_s"], 2), "completed": st["completed"],
             "failed": st["failed"]}
         log(f"served: {out['served']}")

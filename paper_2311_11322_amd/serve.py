@@ -219,6 +219,10 @@ class Server:
             "makespan_s": makespan,
             "gpu_busy_s": busy,
             "sphere_steps_per_s": sphere_steps / makespan if makespan > 0 else 0.0,
+            # requests this mix completes per second of engine time: the
+            # highest arrival rate the server sustains for it
+            "service_rate_per_s": (sum(1 for r in requests if r.done is not None and r.status == 0)
+                                   / busy if busy > 0 else 0.0),
         }
 
 
