@@ -33,6 +33,7 @@ class Params(C.Structure):
         ("g", C.c_double * 3), ("n_walls", C.c_int32), ("wall", (C.c_double * 4) * 6),
         ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
         ("shake_phase", C.c_double),
+        ("gravity_tree", C.c_int32), ("theta", C.c_double), ("tree_leaf", C.c_int32),
     ]
 
 
@@ -61,6 +62,8 @@ def lib():
         L.ora_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64]
         L.ora_gravity.argtypes = [_PD, _PD, _PD, C.c_int64, C.c_double, C.c_double, _PI64,
                                   C.c_int64, _PD]
+        L.ora_tree_gravity.argtypes = [_PD, _PD, _PD, C.c_int64, C.c_double, C.c_double,
+                                       C.c_double, C.c_int32, _PD]
         L.ora_set_perturber.argtypes = [C.c_void_p, C.c_double, _PD, _PD]
         L.ora_get_perturber.argtypes = [C.c_void_p, _PD, _PD, _PD]
         L.ora_rotate.argtypes = [_PD, _PD, _PD, _PD, C.c_double, _PD]
@@ -105,6 +108,9 @@ def make_params(d: Dict) -> Params:
             p.shake_amp[w][c] = float(amp[w][c]) if len(amp) else 0.0
     p.shake_omega = float(d.get("shake_omega", 0.0))
     p.shake_phase = float(d.get("shake_phase", 0.0))
+    p.gravity_tree = int(d.get("gravity_tree", 0))
+    p.theta = float(d.get("theta", 0.5))
+    p.tree_leaf = int(d.get("tree_leaf", 16))
     return p
 
 
@@ -225,6 +231,18 @@ def gravity(pos, mass, radius, G, soft_frac, idx=None) -> np.ndarray:
     F = np.zeros((idx.shape[0], 3))
     lib().ora_gravity(_p(pos), _p(mass), _p(radius), n, float(G), float(soft_frac),
                       _p(idx, _PI64), idx.shape[0], _p(F))
+    return F
+
+
+def tree_gravity(pos, mass, radius, G, soft_frac, theta=0.5, leaf=16) -> np.ndarray:
+    """Tree gravity (monopole + quadrupole) on every sphere."""
+    pos = _f64(pos)
+    mass = _f64(mass)
+    radius = _f64(radius)
+    n = mass.shape[0]
+    F = np.zeros((n, 3))
+    lib().ora_tree_gravity(_p(pos), _p(mass), _p(radius), n, float(G), float(soft_frac),
+                           float(theta), int(leaf), _p(F))
     return F
 
 

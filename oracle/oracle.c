@@ -644,6 +644,235 @@ void ora_gravity(const double* pos, const double* mass, const double* radius, in
     }
 }
 
+/* ---- tree gravity ---------------------------------------------------- */
+
+typedef struct {
+    uint32_t prefix;
+    int64_t s, e;          /* range in the sorted order */
+    double M, c[3], Q[6];  /* mass, centre of mass, traceless quadrupole xx yy zz xy xz yz */
+} tnode;
+
+typedef struct {
+    const double *r, *m, *rad;
+    double G, soft_frac, theta;
+    int leaf, bits;
+    double lo[3], cell;
+    int64_t* order;        /* sorted index -> sphere */
+    uint32_t* key;         /* sorted keys */
+    tnode* lev[11];
+    int64_t nlev[11];
+    /* current group */
+    int64_t g0, g1;
+    double bmin[3], bmax[3];
+    double* acc;           /* [3][group size] */
+} tree;
+
+static uint32_t dilate3(uint32_t v)
+{
+    uint32_t r = 0;
+    int b;
+    for (b = 0; b < 10; b++) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+
+static const uint32_t* g_sort_keys;
+static int cmp_sorted(const void* a, const void* b)
+{
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    if (g_sort_keys[x] != g_sort_keys[y]) return g_sort_keys[x] < g_sort_keys[y] ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void node_moments(const tree* t, tnode* nd)
+{
+    int64_t k;
+    int c;
+    double M = 0.0, mc[3] = {0.0, 0.0, 0.0};
+    for (k = nd->s; k < nd->e; k++) {
+        int64_t i = t->order[k];
+        M += t->m[i];
+        for (c = 0; c < 3; c++) mc[c] += t->m[i] * t->r[3 * i + c];
+    }
+    nd->M = M;
+    for (c = 0; c < 3; c++) nd->c[c] = mc[c] / M;
+    for (c = 0; c < 6; c++) nd->Q[c] = 0.0;
+    for (k = nd->s; k < nd->e; k++) {
+        int64_t i = t->order[k];
+        double d[3], d2;
+        for (c = 0; c < 3; c++) d[c] = t->r[3 * i + c] - nd->c[c];
+        d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        nd->Q[0] += t->m[i] * (3.0 * d[0] * d[0] - d2);
+        nd->Q[1] += t->m[i] * (3.0 * d[1] * d[1] - d2);
+        nd->Q[2] += t->m[i] * (3.0 * d[2] * d[2] - d2);
+        nd->Q[3] += t->m[i] * 3.0 * d[0] * d[1];
+        nd->Q[4] += t->m[i] * 3.0 * d[0] * d[2];
+        nd->Q[5] += t->m[i] * 3.0 * d[1] * d[2];
+    }
+}
+
+static const tnode* find_node(const tree* t, int l, uint32_t prefix)
+{
+    int64_t lo = 0, hi = t->nlev[l];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (t->lev[l][mid].prefix < prefix) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < t->nlev[l] && t->lev[l][lo].prefix == prefix) return &t->lev[l][lo];
+    return NULL;
+}
+
+/* force per unit target mass of a node's monopole + quadrupole at R = x - c */
+static void m2p(const tnode* nd, const double* x, double G, double* a)
+{
+    double R[3] = {x[0] - nd->c[0], x[1] - nd->c[1], x[2] - nd->c[2]};
+    double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    double r = sqrt(r2);
+    double ir3 = 1.0 / (r2 * r), ir5 = ir3 / r2, ir7 = ir5 / r2;
+    const double* Q = nd->Q;
+    double QR[3] = {Q[0] * R[0] + Q[3] * R[1] + Q[4] * R[2],
+                    Q[3] * R[0] + Q[1] * R[1] + Q[5] * R[2],
+                    Q[4] * R[0] + Q[5] * R[1] + Q[2] * R[2]};
+    double RQR = R[0] * QR[0] + R[1] * QR[1] + R[2] * QR[2];
+    int c;
+    for (c = 0; c < 3; c++)
+        a[c] += G * (-nd->M * R[c] * ir3 + QR[c] * ir5 - 2.5 * RQR * R[c] * ir7);
+}
+
+static void visit(tree* t, int l, uint32_t prefix)
+{
+    const tnode* nd = find_node(t, l, prefix);
+    int c, o;
+    int64_t g, k;
+    if (!nd) return;
+    /* geometric centre of the node's cube, distance to the group's box */
+    double side = ldexp(t->cell, t->bits - l);
+    double ctr[3], dd[3], dist2, thr;
+    uint32_t ix[3] = {0, 0, 0};
+    int b;
+    for (b = 0; b < l; b++)
+        for (c = 0; c < 3; c++) ix[c] |= ((prefix >> (3 * b + c)) & 1u) << b;
+    for (c = 0; c < 3; c++) {
+        ctr[c] = t->lo[c] + ((double)ix[c] + 0.5) * side;
+        double u = t->bmin[c] - ctr[c], v = ctr[c] - t->bmax[c];
+        dd[c] = u > v ? u : v;
+        if (dd[c] < 0.0) dd[c] = 0.0;
+    }
+    dist2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+    thr = side / t->theta;
+    if (dist2 > thr * thr) {
+        for (g = t->g0; g < t->g1; g++) {
+            int64_t i = t->order[g];
+            double a[3] = {0.0, 0.0, 0.0};
+            m2p(nd, &t->r[3 * i], t->G, a);
+            for (c = 0; c < 3; c++) t->acc[3 * (g - t->g0) + c] += t->m[i] * a[c];
+        }
+        return;
+    }
+    if (nd->e - nd->s <= t->leaf || l == t->bits) {
+        for (g = t->g0; g < t->g1; g++) {
+            int64_t i = t->order[g];
+            double f[3] = {0.0, 0.0, 0.0};
+            for (k = nd->s; k < nd->e; k++) {
+                int64_t j = t->order[k];
+                if (j == i) continue;
+                gravity_pair(t->G, t->soft_frac, &t->r[3 * i], &t->r[3 * j], t->m[i], t->m[j],
+                             t->rad[i], t->rad[j], f);
+            }
+            for (c = 0; c < 3; c++) t->acc[3 * (g - t->g0) + c] += f[c];
+        }
+        return;
+    }
+    for (o = 0; o < 8; o++) visit(t, l + 1, (prefix << 3) | (uint32_t)o);
+}
+
+void ora_tree_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
+                      double G, double soft_frac, double theta, int32_t leaf, double* F)
+{
+    tree t;
+    int64_t i, k;
+    int c, l;
+    double hi[3], ext = 0.0, smax = 0.0;
+    uint32_t* key_of = (uint32_t*)malloc(n * sizeof(uint32_t));
+    memset(&t, 0, sizeof(t));
+    t.r = pos; t.m = mass; t.rad = radius; t.G = G; t.soft_frac = soft_frac;
+    t.theta = theta; t.leaf = leaf;
+    /* depth: about two finest cells per sphere, 2..10 levels */
+    {
+        int lg = 0;
+        while ((int64_t)1 << lg < 2 * n) lg++;
+        t.bits = (lg + 2) / 3;
+        if (t.bits < 2) t.bits = 2;
+        if (t.bits > 10) t.bits = 10;
+    }
+    for (c = 0; c < 3; c++) { t.lo[c] = pos[c]; hi[c] = pos[c]; }
+    for (i = 0; i < n; i++) {
+        for (c = 0; c < 3; c++) {
+            if (pos[3 * i + c] < t.lo[c]) t.lo[c] = pos[3 * i + c];
+            if (pos[3 * i + c] > hi[c]) hi[c] = pos[3 * i + c];
+        }
+        if (radius[i] > smax) smax = radius[i];
+    }
+    for (c = 0; c < 3; c++) if (hi[c] - t.lo[c] > ext) ext = hi[c] - t.lo[c];
+    t.cell = ldexp(ext * (1.0 + 1e-12), -t.bits) + 1e-300;
+    if (t.cell < 2.0 * smax) t.cell = 2.0 * smax;
+    {
+        double inv = 1.0 / t.cell;
+        int nc = 1 << t.bits;
+        for (i = 0; i < n; i++) {
+            int cc[3];
+            for (c = 0; c < 3; c++) {
+                int v = (int)floor((pos[3 * i + c] - t.lo[c]) * inv);
+                cc[c] = v < 0 ? 0 : (v > nc - 1 ? nc - 1 : v);
+            }
+            key_of[i] = dilate3((uint32_t)cc[0]) | (dilate3((uint32_t)cc[1]) << 1) |
+                        (dilate3((uint32_t)cc[2]) << 2);
+        }
+    }
+    t.order = (int64_t*)malloc(n * sizeof(int64_t));
+    t.key = (uint32_t*)malloc(n * sizeof(uint32_t));
+    for (i = 0; i < n; i++) t.order[i] = i;
+    g_sort_keys = key_of;
+    qsort(t.order, n, sizeof(int64_t), cmp_sorted);
+    for (k = 0; k < n; k++) t.key[k] = key_of[t.order[k]];
+    /* nodes of every level: runs of equal prefix */
+    for (l = 0; l <= t.bits; l++) {
+        int sh = 3 * (t.bits - l);
+        t.lev[l] = (tnode*)malloc(n * sizeof(tnode));
+        t.nlev[l] = 0;
+        for (k = 0; k < n;) {
+            uint32_t p = t.key[k] >> sh;
+            int64_t e = k;
+            while (e < n && (t.key[e] >> sh) == p) e++;
+            tnode* nd = &t.lev[l][t.nlev[l]++];
+            nd->prefix = p; nd->s = k; nd->e = e;
+            node_moments(&t, nd);
+            k = e;
+        }
+    }
+    t.acc = (double*)malloc(3 * 64 * sizeof(double));
+    for (t.g0 = 0; t.g0 < n; t.g0 += 64) {
+        t.g1 = t.g0 + 64 < n ? t.g0 + 64 : n;
+        for (c = 0; c < 3; c++) { t.bmin[c] = INFINITY; t.bmax[c] = -INFINITY; }
+        for (k = t.g0; k < t.g1; k++) {
+            i = t.order[k];
+            for (c = 0; c < 3; c++) {
+                if (pos[3 * i + c] < t.bmin[c]) t.bmin[c] = pos[3 * i + c];
+                if (pos[3 * i + c] > t.bmax[c]) t.bmax[c] = pos[3 * i + c];
+            }
+        }
+        memset(t.acc, 0, 3 * 64 * sizeof(double));
+        visit(&t, 0, 0u);
+        for (k = t.g0; k < t.g1; k++) {
+            i = t.order[k];
+            for (c = 0; c < 3; c++) F[3 * i + c] = t.acc[3 * (k - t.g0) + c];
+        }
+    }
+    for (l = 0; l <= t.bits; l++) free(t.lev[l]);
+    free(t.acc); free(t.order); free(t.key); free(key_of);
+}
+
 /* Unsoftened pull of the perturber on sphere i (added to F). */
 static void perturber_pull(const ora_sim* s, int64_t i, double* F)
 {
@@ -736,7 +965,13 @@ static void evaluate(ora_sim* s, int carry_history)
     }
     /* self-gravity, Eq. 4, every j != i including members of the same
      * aggregate (their forces cancel in Eqs. 5-6) */
-    if (s->p.G != 0.0) {
+    if (s->p.G != 0.0 && s->p.gravity_tree) {
+        double* Fg = (double*)malloc(3 * s->ns * sizeof(double));
+        ora_tree_gravity(s->r, s->m, s->s, s->ns, s->p.G, s->p.soft_frac, s->p.theta,
+                         s->p.tree_leaf, Fg);
+        for (i = 0; i < 3 * s->ns; i++) s->F[i] += Fg[i];
+        free(Fg);
+    } else if (s->p.G != 0.0) {
         for (i = 0; i < s->ns; i++) {
             double acc[3] = {0.0, 0.0, 0.0};
             int64_t j;

@@ -39,6 +39,10 @@ typedef struct {
     double wall[6][4];
     double shake_amp[6][3];
     double shake_omega, shake_phase;
+    /* tree gravity instead of the direct sum: opening angle theta, leaf size */
+    int32_t gravity_tree;
+    double theta;
+    int32_t tree_leaf;
 } ora_params;
 
 typedef struct ora_sim ora_sim;
@@ -99,6 +103,19 @@ int64_t ora_find_contacts(const double* pos, const double* radius, const int32_t
 /* Direct-sum softened gravity force on the listed targets. */
 void ora_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
                  double G, double soft_frac, const int64_t* idx, int64_t n_idx, double* F);
+
+/* Tree gravity (monopole + quadrupole about each node's centre of mass).
+ * The tree: a cube grid over the bounding box of the centres -- bits =
+ * ceil(ceil(log2 2n) / 3) levels (2..10), finest cell side
+ * max(2 * largest radius, 1.000000000001 * largest extent / 2^bits) -- with
+ * spheres ordered by (Morton code of their finest cell, index); node (l, p)
+ * holds the spheres whose code has prefix p at level l.  Targets go in
+ * groups of 64 consecutive spheres in that order.  A node is taken as a
+ * multipole when the distance from its cube's centre to the group's bounding
+ * box exceeds side / theta, else as direct (softened) pairs when it holds at
+ * most `leaf` spheres or is a finest cell, else it is opened. */
+void ora_tree_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
+                      double G, double soft_frac, double theta, int32_t leaf, double* F);
 
 /* One fixed Cash-Karp step of the torque-coupled Euler equations for a single
  * body (exposed for the rotation pins).  q[4], wb[3] updated in place; err
