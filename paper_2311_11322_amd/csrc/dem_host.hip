@@ -58,6 +58,8 @@ int ceil_log2(uint64_t v) {
 struct Sizes {
   int64_t na, ns, cap, cells, g_tile, g_nt, n_rblk;
   bool grav;
+  bool tree;
+  int64_t tree_nodes;        // all levels of the pyramid
   int precision;
 };
 
@@ -122,6 +124,8 @@ Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int til
   z.cap = int64_t(c_max) * ns;
   z.cells = int64_t(1) << (3 * choose_bits(ns));
   z.grav = p.G != 0.0;
+  z.tree = z.grav && p.gravity_tree;
+  z.tree_nodes = z.tree ? ((z.cells << 3) - 1) / 7 : 0;
   z.precision = p.precision;
   z.g_tile = tile > 0 ? tile : default_tile(p.precision);
   z.g_nt = (ns + z.g_tile - 1) / z.g_tile;
@@ -174,12 +178,16 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.xg, ns);
   L.add(&h.sid, ns);
   if (z.grav) {
-    // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
-    const int64_t part_vals = z.g_nt * 3 * ns;
     L.add(reinterpret_cast<double**>(&h.jrec), 8 * ns);
-    L.add(&h.ganchor, 4 * z.g_nt);
-    L.add(reinterpret_cast<double**>(&h.gpart), z.precision == 1 ? (part_vals + 1) / 2 : part_vals);
     L.add(&h.gacc, 3 * ns);
+    if (z.tree) {
+      L.add(&h.tmom, 10 * z.tree_nodes);
+    } else {
+      // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
+      const int64_t part_vals = z.g_nt * 3 * ns;
+      L.add(&h.ganchor, 4 * z.g_nt);
+      L.add(reinterpret_cast<double**>(&h.gpart), z.precision == 1 ? (part_vals + 1) / 2 : part_vals);
+    }
   }
   L.add(&h.bpart, 10 * z.n_rblk);
   L.add(&h.ppart, 3 * z.n_rblk);
@@ -225,6 +233,9 @@ struct Batch {
   WorkItem* wl_sph = nullptr;
   WorkItem* wl_big = nullptr;                // (pile, k-th big sphere)
   int n_big_blk = 0;
+  WorkItem* wl_tree[11] = {};                // per pyramid level: (pile, first node)
+  int n_tree[11] = {};
+  bool any_tree = false;
   int n_sph_blk = 0;
   // gravity tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
@@ -321,13 +332,14 @@ hipError_t upload(Batch& b, T** dst, const std::vector<T>& src, hipStream_t st) 
 // device table entries must already be in place at slots 0..n-1.
 dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
-  std::vector<WorkItem> wa, wsph, wbig;
+  std::vector<WorkItem> wa, wsph, wbig, wtree[11];
   std::vector<GravItem> glg[3];
   int tiles[3] = {0, 0, 0};
   int n_groups = 0;
   std::vector<ScanSeg> sc, sp;
   std::vector<ScanItem> ic, ip;
   b.any_grav = false;
+  b.any_tree = false;
   b.all_soft = true;
   for (int p = 0; p < (int)b.members.size(); ++p) {
     const dem_sim* s = b.members[p];
@@ -335,7 +347,12 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
     for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
     for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
     for (int k = 0; k < h.n_big; ++k) wbig.push_back({p, k});
-    if (h.G != 0.0) {
+    if (h.G != 0.0 && h.tree) {
+      b.any_grav = true;
+      b.any_tree = true;
+      for (int l = 0; l <= h.bits; ++l)
+        for (int64_t q = 0; q < (int64_t(1) << (3 * l)); q += kBlock) wtree[l].push_back({p, (int32_t)q});
+    } else if (h.G != 0.0) {
       b.any_grav = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
       // every tile pair (ti <= tj) of the pile: each unordered pair once
@@ -368,6 +385,11 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   HIPCHK(errsim, upload(b, &b.wl_sph, wsph, st));
   b.n_big_blk = (int)wbig.size();
   if (!wbig.empty()) HIPCHK(errsim, upload(b, &b.wl_big, wbig, st));
+  for (int l = 0; l <= 10; ++l) {
+    b.n_tree[l] = (int)wtree[l].size();
+    b.wl_tree[l] = nullptr;
+    if (!wtree[l].empty()) HIPCHK(errsim, upload(b, &b.wl_tree[l], wtree[l], st));
+  }
   for (int g = 0; g < 3; ++g) {
     HIPCHK(errsim, upload(b, &b.gl[g], glg[g], st));
     b.n_grav[g] = (int)glg[g].size();
@@ -438,6 +460,7 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
       launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
     launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.wl_sph, b.n_sph_blk);
   }
   mark(12);
   launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
@@ -500,6 +523,11 @@ dem_status valid_params(const dem_params* p, std::string* why) {
   if (p->n_walls > 0 && p->periodic) return bad("walls need an open (non-periodic) system");
   if (!std::isfinite(p->shake_omega) || !std::isfinite(p->shake_phase))
     return bad("non-finite shaking frequency or phase");
+  if (p->gravity_tree) {
+    if (p->periodic) return bad("tree gravity needs an open (non-periodic) system");
+    if (!(p->tree_theta > 0.0 && p->tree_theta <= 1.0)) return bad("tree_theta must be in (0, 1]");
+    if (p->tree_leaf < 1 || p->tree_leaf > 4096) return bad("tree_leaf must be in 1..4096");
+  }
   for (int w = 0; w < p->n_walls; ++w) {
     double nn = 0.0;
     for (int k = 0; k < 4; ++k)
@@ -563,6 +591,9 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.G = s->prm.G;
   h.soft_frac = s->prm.softening_frac;
   h.spin_dw = s->forcing.spin_dw;
+  h.tree = s->sz.tree ? 1 : 0;
+  h.tree_leaf = s->prm.tree_leaf;
+  h.theta = s->prm.tree_theta;
   h.n_walls = s->prm.n_walls;
   for (int k = 0; k < 3; ++k) h.gfield[k] = s->prm.g[k];
   for (int w = 0; w < 6; ++w) {
@@ -731,6 +762,11 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
   double s_cut, s_small;
   int n_big;
   split_big(radius, ns, &s_cut, &s_small, &n_big);
+  if (s->prm.gravity_tree && s->prm.G != 0.0) {   // the tree covers every sphere
+    s_cut = INFINITY;
+    s_small = smax;
+    n_big = 0;
+  }
   const double cell_min = s->tune.cell_scale * 2.0 * s_small;
   dem_status st = alloc_pile(s, n_agg, ns);
   if (st != DEM_OK) return st;

@@ -90,6 +90,11 @@ struct PileDev {
   double wall[6][4];         // unit normal (into the domain), offset
   double wall_amp[6][3];     // rigid sinusoidal displacement amplitude
   double wall_omega, wall_phase;
+  // tree gravity (host-set)
+  int32_t tree;              // 1: tree instead of the direct sum
+  int32_t tree_leaf;         // nodes of at most this many spheres act as pairs
+  double theta;              // opening angle
+  double* tmom;              // [sum_l 8^l][10] node moments, level l at (8^l - 1) / 7
 
   // device-updated bookkeeping
   int32_t parity;            // which half of each ping-pong pair is current
@@ -223,6 +228,8 @@ void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
+void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level,
+                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
                  int n_items, uint32_t* item_sums, int max_seg_items);

@@ -404,6 +404,10 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
       ext[k] = vals[3 + k] - vals[k];
     }
     for (int t = 0; t < 3 * P.bits; ++t) {
+      if (P.tree) {                      // the tree's pyramid needs a cubic code
+        b[t % 3]++;
+        continue;
+      }
       int a = -1;
       double best = -1.0;
       for (int k = 0; k < 3; ++k) {

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_grav_records(const PileDev* __restri
   const double x = P.xs[k], y = P.xs[ns + k], z = P.xs[2 * ns + k];
   const double e = 0.5 * P.soft_frac * P.xs[3 * ns + k];
   const double m = P.m[P.sidx[k]];
-  if (precision == 1) {
+  if (precision == 1 && !P.tree) {
     const int a = (k / P.g_tile) * P.g_tile;
     const double ax = P.xs[a], ay = P.xs[ns + a], az = P.xs[2 * ns + a];
     Rec32 r;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restri
                                                          const WorkItem* __restrict__ wl) {
   const WorkItem w = wl[blockIdx.x];
   const PileDev& P = piles[w.pile];
-  if (P.status != 0 || P.G == 0.0) return;
+  if (P.status != 0 || P.G == 0.0 || P.tree) return;
   const int k = w.base + threadIdx.x;
   const int ns = P.ns, nt = P.g_nt;
   double pull[3] = {0.0, 0.0, 0.0};
@@ -311,6 +311,229 @@ __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restri
       P.ppart[(w.base / kBlock) * 3 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
+
+// ---------------------------------------------------------------------------
+// Tree gravity: the pyramid of the pile's cubic cell grid.  Node (l, p) is the
+// cube of side cell * 2^(bits - l) whose Morton prefix is p; with the spheres
+// sorted by cell code its spheres are the contiguous slots
+// [cell_start[p << 3(bits-l)], cell_start[(p+1) << 3(bits-l)]).  Each node
+// keeps its mass, centre of mass and traceless quadrupole
+// Q = sum m (3 d d^T - |d|^2 1) about the centre of mass (xx yy zz xy xz yz).
+// ---------------------------------------------------------------------------
+
+constexpr int kMom = 10;           // M, c[3], Q[6]
+constexpr int kTreeStack = 96;     // nodes waiting per wave (depth <= 7 * 10 + 1)
+
+typedef const __attribute__((address_space(4))) double* ConstD;
+typedef const __attribute__((address_space(4))) uint32_t* ConstU;
+
+__device__ __forceinline__ size_t level_offset(int l) { return (((size_t)1 << (3 * l)) - 1) / 7; }
+
+// Finest level: moments of node p from the cell's spheres.
+__device__ void tree_leaf(const PileDev& P, uint32_t p) {
+  const int L = P.bits;
+  const Rec64* __restrict__ rec = (const Rec64*)P.jrec;
+  const uint32_t s0 = P.cell_start[p], s1 = P.cell_start[p + 1];
+  double M = 0.0, mc[3] = {0.0, 0.0, 0.0}, Q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (uint32_t t = s0; t < s1; ++t) {
+    const Rec64 r = rec[t];
+    M += r.m;
+    mc[0] += r.m * r.x;
+    mc[1] += r.m * r.y;
+    mc[2] += r.m * r.z;
+  }
+  double c[3] = {0.0, 0.0, 0.0};
+  if (M > 0.0) {
+    for (int a = 0; a < 3; ++a) c[a] = mc[a] / M;
+    for (uint32_t t = s0; t < s1; ++t) {
+      const Rec64 r = rec[t];
+      const double d[3] = {r.x - c[0], r.y - c[1], r.z - c[2]};
+      const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      Q[0] += r.m * (3.0 * d[0] * d[0] - d2);
+      Q[1] += r.m * (3.0 * d[1] * d[1] - d2);
+      Q[2] += r.m * (3.0 * d[2] * d[2] - d2);
+      Q[3] += r.m * 3.0 * d[0] * d[1];
+      Q[4] += r.m * 3.0 * d[0] * d[2];
+      Q[5] += r.m * 3.0 * d[1] * d[2];
+    }
+  }
+  double* o = P.tmom + (level_offset(L) + p) * kMom;
+  o[0] = M;
+  for (int a = 0; a < 3; ++a) o[1 + a] = c[a];
+  for (int q = 0; q < 6; ++q) o[4 + q] = Q[q];
+}
+
+// Level l < bits: node p from its eight children, combined in order
+// (parallel-axis shift of each child's quadrupole to the node's centre).
+__device__ void tree_up(const PileDev& P, int l, uint32_t p) {
+  const double* ch = P.tmom + (level_offset(l + 1) + ((size_t)p << 3)) * kMom;
+  double M = 0.0, mc[3] = {0.0, 0.0, 0.0};
+  for (int o = 0; o < 8; ++o) {
+    const double m = ch[o * kMom];
+    M += m;
+    for (int a = 0; a < 3; ++a) mc[a] += m * ch[o * kMom + 1 + a];
+  }
+  double c[3] = {0.0, 0.0, 0.0}, Q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (M > 0.0) {
+    for (int a = 0; a < 3; ++a) c[a] = mc[a] / M;
+    for (int o = 0; o < 8; ++o) {
+      const double* q = ch + o * kMom;
+      const double m = q[0];
+      if (m == 0.0) continue;
+      const double d[3] = {q[1] - c[0], q[2] - c[1], q[3] - c[2]};
+      const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      Q[0] += q[4] + m * (3.0 * d[0] * d[0] - d2);
+      Q[1] += q[5] + m * (3.0 * d[1] * d[1] - d2);
+      Q[2] += q[6] + m * (3.0 * d[2] * d[2] - d2);
+      Q[3] += q[7] + m * 3.0 * d[0] * d[1];
+      Q[4] += q[8] + m * 3.0 * d[0] * d[2];
+      Q[5] += q[9] + m * 3.0 * d[1] * d[2];
+    }
+  }
+  double* out = P.tmom + (level_offset(l) + p) * kMom;
+  out[0] = M;
+  for (int a = 0; a < 3; ++a) out[1 + a] = c[a];
+  for (int q = 0; q < 6; ++q) out[4 + q] = Q[q];
+}
+
+// One thread per node of level l of every tree pile: finest-level moments
+// from spheres where l is the pile's depth, else from the level below.
+__global__ __launch_bounds__(kBlock) void k_tree_level(const PileDev* __restrict__ piles,
+                                                       const WorkItem* __restrict__ wl, int l) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0 || l > P.bits) return;
+  const uint32_t p = (uint32_t)(w.base + threadIdx.x);
+  if (p >= (1u << (3 * l))) return;
+  if (l == P.bits) tree_leaf(P, p);
+  else tree_up(P, l, p);
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// One wave per group of 64 consecutive sorted slots.  The wave walks the
+// pyramid from the root with a stack in LDS; every decision is uniform over
+// the wave: a node whose cube centre is farther from the group's bounding box
+// than side / theta acts through its multipoles, a node of at most tree_leaf
+// spheres (or a finest cell) through softened pairs, any other node is
+// opened.  The epilogue stores G m_i sum under the sphere's id and adds the
+// perturber's pull exactly as the direct path's combine does.
+__global__ __launch_bounds__(kBlock) void k_tree_walk(const PileDev* __restrict__ piles,
+                                                      const WorkItem* __restrict__ wl) {
+  __shared__ uint64_t stack[kBlock / 64][kTreeStack];
+  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0 || !P.tree || P.G == 0.0) return;
+  const int ns = P.ns, L = P.bits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = w.base + threadIdx.x;
+  const bool active = k < ns;
+  const ConstRec64 rec = (ConstRec64)P.jrec;
+  const ConstU cstart = (ConstU)P.cell_start;
+  const ConstD mom = (ConstD)P.tmom;
+  const Grid& g = *P.grid;
+  const double cell = g.cell, theta = P.theta;
+  double x = 0.0, y = 0.0, z = 0.0, ei = 0.0;
+  if (active) {
+    const Rec64* r = (const Rec64*)P.jrec + k;
+    x = r->x;
+    y = r->y;
+    z = r->z;
+    ei = r->e;
+  }
+  const double bmin[3] = {wave_min(active ? x : INFINITY), wave_min(active ? y : INFINITY),
+                          wave_min(active ? z : INFINITY)};
+  const double bmax[3] = {wave_max(active ? x : -INFINITY), wave_max(active ? y : -INFINITY),
+                          wave_max(active ? z : -INFINITY)};
+  double acc[3] = {0.0, 0.0, 0.0};
+  const double c15 = kSeries[0], c1875 = kSeries[1];
+  const bool any = w.base + wave * 64 < ns;
+  int sp = 0;
+  if (any) {
+    stack[wave][0] = 0;                  // (level 0, prefix 0)
+    sp = 1;
+  }
+  while (sp > 0) {
+    const uint64_t nd = stack[wave][--sp];
+    // the stack is the wave's: make the node id uniform (scalar loads below)
+    const int l = __builtin_amdgcn_readfirstlane((int)(nd >> 32));
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nd);
+    const int sh = 3 * (L - l);
+    const uint32_t t0 = cstart[(size_t)p << sh], t1 = cstart[(size_t)(p + 1) << sh];
+    if (t1 == t0) continue;
+    // cube centre and its distance to the group's box (rounded step by step)
+    const double side = ldexp(cell, L - l);
+    uint32_t ix[3] = {0u, 0u, 0u};
+    for (int b = 0; b < l; ++b)
+      for (int a = 0; a < 3; ++a) ix[a] |= ((p >> (3 * b + a)) & 1u) << b;
+    double dd[3];
+    for (int a = 0; a < 3; ++a) {
+      const double ctr = __dadd_rn(g.lo[a], __dmul_rn((double)ix[a] + 0.5, side));
+      dd[a] = fmax(fmax(__dadd_rn(bmin[a], -ctr), __dadd_rn(ctr, -bmax[a])), 0.0);
+    }
+    const double dist2 = __dadd_rn(__dadd_rn(__dmul_rn(dd[0], dd[0]), __dmul_rn(dd[1], dd[1])),
+                                   __dmul_rn(dd[2], dd[2]));
+    const double thr = side / theta;
+    if (dist2 > __dmul_rn(thr, thr)) {
+      const ConstD q = mom + (level_offset(l) + p) * kMom;
+      const double R[3] = {x - q[1], y - q[2], z - q[3]};
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double ir3 = 1.0 / (r2 * sqrt(r2)), ir5 = ir3 / r2, ir7 = ir5 / r2;
+      const double QR[3] = {q[4] * R[0] + q[7] * R[1] + q[8] * R[2],
+                            q[7] * R[0] + q[5] * R[1] + q[9] * R[2],
+                            q[8] * R[0] + q[9] * R[1] + q[6] * R[2]};
+      const double RQR = R[0] * QR[0] + R[1] * QR[1] + R[2] * QR[2];
+      for (int a = 0; a < 3; ++a) acc[a] += -q[0] * R[a] * ir3 + QR[a] * ir5 - 2.5 * RQR * R[a] * ir7;
+    } else if (t1 - t0 <= (uint32_t)P.tree_leaf || l == L || sp + 8 > kTreeStack) {
+      for (uint32_t t = t0; t < t1; ++t) {
+        const double dx = rec[t].x - x, dy = rec[t].y - y, dz = rec[t].z - z, e = ei + rec[t].e;
+        const double r2 = dx * dx + dy * dy + dz * dz + e * e;
+        const double c3 = (t == (uint32_t)k) ? 0.0 : rec[t].m * inv_cube<true>(r2, c15, c1875);
+        acc[0] += c3 * dx;
+        acc[1] += c3 * dy;
+        acc[2] += c3 * dz;
+      }
+    } else {
+      for (int o = 7; o >= 0; --o)
+        stack[wave][sp++] = ((uint64_t)(l + 1) << 32) | (uint64_t)((p << 3) | (uint32_t)o);
+    }
+  }
+  // epilogue: as the direct path's combine
+  double pull[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    const uint32_t i = P.sidx[k];
+    const double gm = P.G * P.m[i];
+    for (int a = 0; a < 3; ++a) acc[a] *= gm;
+    if (P.pert_on) {
+      const int nxt = P.parity ^ 1;
+      const double d[3] = {P.pert_r[nxt][0] - x, P.pert_r[nxt][1] - y, P.pert_r[nxt][2] - z};
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double f = gm * P.pert_M / (r2 * sqrt(r2));
+      for (int a = 0; a < 3; ++a) {
+        pull[a] = f * d[a];
+        acc[a] += pull[a];
+      }
+    }
+    for (int a = 0; a < 3; ++a) P.gacc[a * ns + i] = acc[a];
+  }
+  if (!P.pert_on) return;
+  for (int off = 32; off > 0; off >>= 1)
+    for (int a = 0; a < 3; ++a) pull[a] += __shfl_xor(pull[a], off);
+  __shared__ double red[4][3];
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) red[wave][a] = pull[a];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a)
+      P.ppart[(w.base / kBlock) * 3 + a] = ((red[0][a] + red[1][a]) + red[2][a]) + red[3][a];
+}
 }  // namespace
 
 int gravity_tiles(int precision, int* tiles) {
@@ -361,6 +584,14 @@ void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem
     hipLaunchKernelGGL(k_grav_combine<float>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
   else
     hipLaunchKernelGGL(k_grav_combine<double>, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
+}
+
+void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level,
+                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk) {
+  for (int l = 10; l >= 0; --l)
+    if (n_level[l] > 0)
+      hipLaunchKernelGGL(k_tree_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles, wl_level[l], l);
+  hipLaunchKernelGGL(k_tree_walk, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
 }
 
 }  // namespace dem

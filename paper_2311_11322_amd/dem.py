@@ -53,6 +53,7 @@ class dem_params(C.Structure):
         ("g", C.c_double * 3), ("n_walls", C.c_int32), ("walls", (C.c_double * 4) * 6),
         ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
         ("shake_phase", C.c_double),
+        ("gravity_tree", C.c_int32), ("tree_theta", C.c_double), ("tree_leaf", C.c_int32),
     ]
 
 
@@ -178,6 +179,9 @@ def make_params(d: Dict, precision: int = PREC_FP64, max_contacts: int = 0,
             p.shake_amp[w][c] = float(amp[w][c]) if len(amp) else 0.0
     p.shake_omega = float(d.get("shake_omega", 0.0))
     p.shake_phase = float(d.get("shake_phase", 0.0))
+    p.gravity_tree = int(d.get("gravity_tree", 0))
+    p.tree_theta = float(d.get("theta", 0.5))
+    p.tree_leaf = int(d.get("tree_leaf", 16))
     return p
 
 

@@ -1,0 +1,111 @@
+"""Tree gravity on the GPU against the oracle's tree and the exact sum
+(needs an MI355X).  Each test prints its case before the GPU runs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_11322_amd import workloads as W
+from tests.gpu_util import compare_states, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_2311_11322_amd import dem
+    dem.lib()
+    return dem
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _tree(w, theta=0.5, leaf=16):
+    w.params.update(gravity_tree=1, theta=theta, tree_leaf=leaf)
+    return w
+
+
+@pytest.mark.parametrize("theta,leaf", [(0.5, 16), (0.3, 4), (0.8, 64)])
+def test_tree_gravity_parity(D, theta, leaf):
+    """Same tree, same groups, same opening decisions as the oracle's tree:
+    t0, one step and three more within the parity bar."""
+    say("tree parity", theta, leaf)
+    w = _tree(W.collapse_cloud(71, n_agg=500, contact_seeded=True, spin_sigma=0.2), theta, leaf)
+    sim = D.Sim(w.params)
+    sim.add_workload(w)
+    o = O.Oracle(w.params).add_workload(w)
+    compare_states(sim, o)
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o)
+    sim.step(3)
+    o.step(3)
+    compare_states(sim, o, tol=1e-10)
+
+
+def test_tree_with_perturber_parity(D):
+    say("tree + flyby")
+    from paper_2311_11322_amd import serve
+    w = _tree(W.collapse_cloud(72, n_agg=300, contact_seeded=True))
+    serve.add_flyby(w, start_factor=1.2)
+    Mp, rp, vp = w.params["perturber"]
+    sim = serve.make_sim(w, D.PREC_FP64)
+    o = O.Oracle(w.params).set_perturber(Mp, rp, vp).add_workload(w)
+    compare_states(sim, o)
+    sim.step(2)
+    o.step(2)
+    compare_states(sim, o, tol=1e-10)
+    f = sim.get_forcing()
+    orp, ovp, _ = o.perturber()
+    assert rel_err(f["pert_pos"], orp) <= 1e-13
+    assert rel_err(f["pert_vel"], ovp) <= 1e-12
+
+
+def test_tree_at_full_size_against_exact_sum(D):
+    """The 125k-sphere collapse with tree gravity: the force on sampled
+    spheres against the oracle's exact one-at-a-time evaluation (contacts +
+    direct sum) -- the difference is the tree's truncation error only."""
+    w = _tree(W.collapse_cloud(1, n_agg=25000))
+    say("tree full size", w.n_sph)
+    sim = D.Sim(w.params)
+    sim.add_workload(w)
+    F = sim.read_state(["sph_force"])["sph_force"]
+    o = O.Oracle(w.params).add_workload(w, evaluate=False)
+    idx = np.random.default_rng(0).choice(w.n_sph, 192, replace=False)
+    Fo, _ = o.eval_subset(idx)
+    err = np.linalg.norm(F[idx] - Fo, axis=1) / np.linalg.norm(Fo, axis=1)
+    print("tree relative error: max", err.max(), "rms", np.sqrt((err ** 2).mean()))
+    assert np.sqrt((err ** 2).mean()) < 1e-3 and err.max() < 1e-2
+
+
+def test_tree_and_direct_piles_in_one_engine(D):
+    """A tree-gravity pile and a direct-sum pile stepped together give the
+    states each gives alone, bit for bit."""
+    say("engine tree + direct")
+    ws = [_tree(W.collapse_cloud(73, n_agg=400, contact_seeded=True)),
+          W.collapse_cloud(74, n_agg=300, contact_seeded=True)]
+    alone = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        s.step(4)
+        alone.append(s.read_state(pairs=True))
+        s.close()
+    eng = D.Engine(1 << 33)
+    sims = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        eng.attach(s)
+        sims.append(s)
+    assert eng.step(4) == D.DEM_OK
+    for s in list(eng.sims):
+        eng.detach(s)
+    for k, s in enumerate(sims):
+        got = s.read_state(pairs=True)
+        for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "sph_force"):
+            assert np.array_equal(got[f], alone[k][f]), (k, f)
