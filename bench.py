@@ -351,6 +351,24 @@ def _big_collapse(n_agg):
     return W.collapse_cloud(2, n_agg=n_agg)
 
 
+def tree_run(w, steps, theta=0.5, leaf=16):
+    """Tree gravity (FP64) on a workload: ms per step and gravity ms."""
+    from paper_2311_11322_amd import dem
+    prm = dict(w.params, gravity_tree=1, theta=theta, tree_leaf=leaf)
+    st = dem.Sim(prm)
+    st.add_workload(w)
+    st.step(1)
+    wall = timed_steps(st, steps)
+    st.set_profiling(True)
+    timed_steps(st, steps)
+    pt = st.profile()
+    st.close()
+    return {"value": round(w.n_sph * steps / wall, 1), "unit": "sphere-steps/s",
+            "ms_per_step": round(1e3 * wall / steps, 4),
+            "gravity_ms": round(pt["gravity"] / pt["_steps"], 4),
+            "theta": theta, "leaf": leaf}
+
+
 def big_run(args, out, wbig):
     """FP32-force gravity at 500k spheres (100,000 aggregates): a few steps."""
     from paper_2311_11322_amd import dem
@@ -372,6 +390,8 @@ def big_run(args, out, wbig):
         "ms_per_step": round(1e3 * wall / nbig, 3), "gravity_ms": round(gb_ms, 3),
         "gravity_frac_of_fp32_peak": round(achb / PEAK_TFLOPS["fp32"], 4)}
     log(f"fp32-force 500k: {out['fp32_force_500k']}")
+    out["tree_500k"] = dict(tree_run(wbig, 5), workload=f"collapse, {nb} spheres, tree gravity, FP64")
+    log(f"tree 500k: {out['tree_500k']}")
 
 
 def extra_runs(args, w, out, prec):
@@ -402,6 +422,11 @@ def extra_runs(args, w, out, prec):
                              "gravity_ms": round(g_ms, 4),
                              "gravity_frac_of_fp32_peak": round(ach / PEAK_TFLOPS["fp32"], 4)}
         log(f"fp32-force: {out['fp32_force']}")
+    if prec == dem.PREC_FP64:
+        out["tree"] = dict(tree_run(w, args.steps),
+                           workload=f"collapse, {w.n_sph} spheres, tree gravity (monopole + "
+                                    "quadrupole), FP64")
+        log(f"tree: {out['tree']}")
     contact_path_run(args, out)
     # -- the paper's efficiency experiment: original (full-scan) vs improved
     #    (contiguous) member search, on its collapse shape (2e4 spheres)

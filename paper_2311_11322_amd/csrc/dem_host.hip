@@ -182,6 +182,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
     L.add(&h.gacc, 3 * ns);
     if (z.tree) {
       L.add(&h.tmom, 10 * z.tree_nodes);
+      L.add(&h.tpart, 64 * 3 * ns);
     } else {
       // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
       const int64_t part_vals = z.g_nt * 3 * ns;

@@ -95,6 +95,7 @@ struct PileDev {
   int32_t tree_leaf;         // nodes of at most this many spheres act as pairs
   double theta;              // opening angle
   double* tmom;              // [sum_l 8^l][10] node moments, level l at (8^l - 1) / 7
+  double* tpart;             // [64][3][ns] tree sum per level-2 subtree, by sorted slot
 
   // device-updated bookkeeping
   int32_t parity;            // which half of each ping-pong pair is current

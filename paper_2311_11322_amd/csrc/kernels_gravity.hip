@@ -323,6 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restri
 
 constexpr int kMom = 10;           // M, c[3], Q[6]
 constexpr int kTreeStack = 96;     // nodes waiting per wave (depth <= 7 * 10 + 1)
+constexpr int kTreeSplit = 2;      // a group's walk is split over the 8^2 subtrees of level 2
+constexpr int kTreeParts = 1 << (3 * kTreeSplit);
 
 typedef const __attribute__((address_space(4))) double* ConstD;
 typedef const __attribute__((address_space(4))) uint32_t* ConstU;
@@ -418,6 +420,14 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// A double held by lane c, in every lane.
+__device__ __forceinline__ double bcast(double v, int c) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), c);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), c);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // One wave per group of 64 consecutive sorted slots.  The wave walks the
 // pyramid from the root with a stack in LDS; every decision is uniform over
 // the wave: a node whose cube centre is farther from the group's bounding box
@@ -428,7 +438,9 @@ __device__ __forceinline__ double wave_max(double v) {
 __global__ __launch_bounds__(kBlock) void k_tree_walk(const PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl) {
   __shared__ uint64_t stack[kBlock / 64][kTreeStack];
-  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const WorkItem w = wl[blk / kTreeParts];
+  const int part = blk % kTreeParts;     // the level-2 subtree this block walks (octal digits)
   const PileDev& P = piles[w.pile];
   if (P.status != 0 || !P.tree || P.G == 0.0) return;
   const int ns = P.ns, L = P.bits;
@@ -455,65 +467,172 @@ __global__ __launch_bounds__(kBlock) void k_tree_walk(const PileDev* __restrict_
   double acc[3] = {0.0, 0.0, 0.0};
   const double c15 = kSeries[0], c1875 = kSeries[1];
   const bool any = w.base + wave * 64 < ns;
+  // softened pairs with the spheres of slots [t0, t1) (uniform)
+  auto pairs = [&](uint32_t t0, uint32_t t1) {
+    for (uint32_t t = t0; t < t1; ++t) {
+      const double dx = rec[t].x - x, dy = rec[t].y - y, dz = rec[t].z - z, e = ei + rec[t].e;
+      const double r2 = dx * dx + dy * dy + dz * dz + e * e;
+      const double c3 = (t == (uint32_t)k) ? 0.0 : rec[t].m * inv_cube<true>(r2, c15, c1875);
+      acc[0] += c3 * dx;
+      acc[1] += c3 * dy;
+      acc[2] += c3 * dz;
+    }
+  };
   int sp = 0;
   if (any) {
-    stack[wave][0] = 0;                  // (level 0, prefix 0)
-    sp = 1;
+    // the root is never accepted (the group lies inside it and theta <= 1);
+    // a root with few spheres is one set of pairs (part 0's block), else it
+    // is opened; above level 2 each block follows only its own digits
+    const uint32_t n0 = cstart[(size_t)1 << (3 * L)] - cstart[0];
+    if (n0 <= (uint32_t)P.tree_leaf) {
+      if (part == 0) pairs(cstart[0], cstart[(size_t)1 << (3 * L)]);
+    } else {
+      stack[wave][sp++] = 0;             // (level 0, prefix 0)
+    }
   }
   while (sp > 0) {
     const uint64_t nd = stack[wave][--sp];
-    // the stack is the wave's: make the node id uniform (scalar loads below)
-    const int l = __builtin_amdgcn_readfirstlane((int)(nd >> 32));
-    const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nd);
+    // the stack is the wave's: make the node id uniform
+    const int lp = __builtin_amdgcn_readfirstlane((int)(nd >> 32));
+    const uint32_t pp = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nd);
+    // lanes 0..7 classify the eight children of the opened node at once
+    const int l = lp + 1;
     const int sh = 3 * (L - l);
-    const uint32_t t0 = cstart[(size_t)p << sh], t1 = cstart[(size_t)(p + 1) << sh];
-    if (t1 == t0) continue;
-    // cube centre and its distance to the group's box (rounded step by step)
     const double side = ldexp(cell, L - l);
-    uint32_t ix[3] = {0u, 0u, 0u};
-    for (int b = 0; b < l; ++b)
-      for (int a = 0; a < 3; ++a) ix[a] |= ((p >> (3 * b + a)) & 1u) << b;
-    double dd[3];
-    for (int a = 0; a < 3; ++a) {
-      const double ctr = __dadd_rn(g.lo[a], __dmul_rn((double)ix[a] + 0.5, side));
-      dd[a] = fmax(fmax(__dadd_rn(bmin[a], -ctr), __dadd_rn(ctr, -bmax[a])), 0.0);
-    }
-    const double dist2 = __dadd_rn(__dadd_rn(__dmul_rn(dd[0], dd[0]), __dmul_rn(dd[1], dd[1])),
-                                   __dmul_rn(dd[2], dd[2]));
-    const double thr = side / theta;
-    if (dist2 > __dmul_rn(thr, thr)) {
-      const ConstD q = mom + (level_offset(l) + p) * kMom;
-      const double R[3] = {x - q[1], y - q[2], z - q[3]};
-      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-      const double ir3 = 1.0 / (r2 * sqrt(r2)), ir5 = ir3 / r2, ir7 = ir5 / r2;
-      const double QR[3] = {q[4] * R[0] + q[7] * R[1] + q[8] * R[2],
-                            q[7] * R[0] + q[5] * R[1] + q[9] * R[2],
-                            q[8] * R[0] + q[9] * R[1] + q[6] * R[2]};
-      const double RQR = R[0] * QR[0] + R[1] * QR[1] + R[2] * QR[2];
-      for (int a = 0; a < 3; ++a) acc[a] += -q[0] * R[a] * ir3 + QR[a] * ir5 - 2.5 * RQR * R[a] * ir7;
-    } else if (t1 - t0 <= (uint32_t)P.tree_leaf || l == L || sp + 8 > kTreeStack) {
-      for (uint32_t t = t0; t < t1; ++t) {
-        const double dx = rec[t].x - x, dy = rec[t].y - y, dz = rec[t].z - z, e = ei + rec[t].e;
-        const double r2 = dx * dx + dy * dy + dz * dz + e * e;
-        const double c3 = (t == (uint32_t)k) ? 0.0 : rec[t].m * inv_cube<true>(r2, c15, c1875);
-        acc[0] += c3 * dx;
-        acc[1] += c3 * dy;
-        acc[2] += c3 * dz;
+    const uint32_t p = (pp << 3) | (uint32_t)(lane & 7);
+    uint32_t t0 = 0, t1 = 0;
+    int kind = 0;                        // 0 empty, 1 multipole, 2 pairs, 3 open
+    if (lane < 8) {
+      t0 = P.cell_start[(size_t)p << sh];
+      t1 = P.cell_start[(size_t)(p + 1) << sh];
+      if (t1 > t0) {
+        uint32_t ix[3] = {0u, 0u, 0u};
+        for (int b = 0; b < l; ++b)
+          for (int a = 0; a < 3; ++a) ix[a] |= ((p >> (3 * b + a)) & 1u) << b;
+        double dd[3];
+        for (int a = 0; a < 3; ++a) {
+          const double ctr = __dadd_rn(g.lo[a], __dmul_rn((double)ix[a] + 0.5, side));
+          dd[a] = fmax(fmax(__dadd_rn(bmin[a], -ctr), __dadd_rn(ctr, -bmax[a])), 0.0);
+        }
+        const double dist2 = __dadd_rn(__dadd_rn(__dmul_rn(dd[0], dd[0]), __dmul_rn(dd[1], dd[1])),
+                                       __dmul_rn(dd[2], dd[2]));
+        const double thr = side / theta;
+        if (dist2 > __dmul_rn(thr, thr)) kind = 1;
+        else if (t1 - t0 <= (uint32_t)P.tree_leaf || l == L) kind = 2;
+        else kind = 3;
       }
-    } else {
-      for (int o = 7; o >= 0; --o)
-        stack[wave][sp++] = ((uint64_t)(l + 1) << 32) | (uint64_t)((p << 3) | (uint32_t)o);
+      if (lp < kTreeSplit) {
+        // above the split: only this block's child; a child that is not
+        // opened there is handled by the block whose lower digits are zero
+        const int digit = (part >> (3 * (kTreeSplit - 1 - lp))) & 7;
+        const int lower = part & ((1 << (3 * (kTreeSplit - 1 - lp))) - 1);
+        if (lane != digit || (kind != 3 && lower != 0)) kind = 0;
+      }
     }
+    // multipoles: each accepted child's moments, broadcast from its lane
+    double q[kMom];
+    if (kind == 1) {
+      const double* src = P.tmom + (level_offset(l) + p) * kMom;
+      for (int c = 0; c < kMom; ++c) q[c] = src[c];
+    }
+    for (int c = 0; c < 8; ++c) {
+      const int kc = __builtin_amdgcn_readlane(kind, c);
+      if (kc == 1) {
+        double m[kMom];
+        for (int j = 0; j < kMom; ++j) m[j] = bcast(q[j], c);
+        const double R[3] = {x - m[1], y - m[2], z - m[3]};
+        const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+        // inverse powers from the hardware rsqrt estimate y0 and e = 1 - r2 y0^2:
+        // r^-2 = y0^2 (1 + e + e^2 + ...), r^-3 = y0^3 (1 + 3e/2 + 15e^2/8 + ...)
+        const double y0 = __builtin_amdgcn_rsq(r2);
+        const double y2 = y0 * y0;
+        const double e = fma(-r2, y2, 1.0);
+        const double ir2 = fma(y2, fma(e, e, e), y2);
+        const double y3 = y2 * y0;
+        const double ir3 = fma(y3 * e, fma(e, c1875, c15), y3);
+        const double ir5 = ir3 * ir2, ir7 = ir5 * ir2;
+        const double QR[3] = {m[4] * R[0] + m[7] * R[1] + m[8] * R[2],
+                              m[7] * R[0] + m[5] * R[1] + m[9] * R[2],
+                              m[8] * R[0] + m[9] * R[1] + m[6] * R[2]};
+        const double RQR = R[0] * QR[0] + R[1] * QR[1] + R[2] * QR[2];
+        for (int a = 0; a < 3; ++a)
+          acc[a] += -m[0] * R[a] * ir3 + QR[a] * ir5 - 2.5 * RQR * R[a] * ir7;
+      }
+    }
+    // pairs: the leaf children's spheres, concatenated and loaded 64 at a time
+    // (one per lane), then broadcast one by one
+    {
+      uint32_t pre[8], cnt[8], beg[8], total = 0;
+      for (int c = 0; c < 8; ++c) {
+        const bool leafc = __builtin_amdgcn_readlane(kind, c) == 2;
+        beg[c] = (uint32_t)__builtin_amdgcn_readlane((int)t0, c);
+        cnt[c] = leafc ? (uint32_t)__builtin_amdgcn_readlane((int)t1, c) - beg[c] : 0u;
+        pre[c] = total;
+        total += cnt[c];
+      }
+      for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+        const uint32_t f = b0 + (uint32_t)lane;
+        uint32_t ts = 0;
+        for (int c = 0; c < 8; ++c)
+          if (f >= pre[c] && f < pre[c] + cnt[c]) ts = beg[c] + (f - pre[c]);
+        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0, se = 0.0;
+        if (f < total) {
+          const Rec64* r = (const Rec64*)P.jrec + ts;
+          sx = r->x;
+          sy = r->y;
+          sz = r->z;
+          sm = r->m;
+          se = r->e;
+        }
+        const int nb = (int)min(64u, total - b0);
+        for (int j = 0; j < nb; ++j) {
+          const uint32_t tj = (uint32_t)__builtin_amdgcn_readlane((int)ts, j);
+          const double dx = bcast(sx, j) - x, dy = bcast(sy, j) - y, dz = bcast(sz, j) - z;
+          const double e = ei + bcast(se, j);
+          const double r2 = dx * dx + dy * dy + dz * dz + e * e;
+          const double c3 = (tj == (uint32_t)k) ? 0.0 : bcast(sm, j) * inv_cube<true>(r2, c15, c1875);
+          acc[0] += c3 * dx;
+          acc[1] += c3 * dy;
+          acc[2] += c3 * dz;
+        }
+      }
+    }
+    // opened children go on the stack, the lowest popped first
+    for (int c = 7; c >= 0; --c) {
+      if (__builtin_amdgcn_readlane(kind, c) == 3) {
+        if (lane == 0) stack[wave][sp] = ((uint64_t)l << 32) | (uint64_t)((pp << 3) | (uint32_t)c);
+        ++sp;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  // epilogue: as the direct path's combine
+  // this subtree's part of the sum, by slot
+  if (active)
+    for (int a = 0; a < 3; ++a) P.tpart[((size_t)part * 3 + a) * ns + k] = acc[a];
+}
+
+// One thread per sorted slot: the subtree parts in order, G m_i, and the
+// perturber's pull, exactly as the direct path's combine.
+__global__ __launch_bounds__(kBlock) void k_tree_combine(const PileDev* __restrict__ piles,
+                                                         const WorkItem* __restrict__ wl) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0 || !P.tree || P.G == 0.0) return;
+  const int ns = P.ns;
+  const int k = w.base + threadIdx.x;
   double pull[3] = {0.0, 0.0, 0.0};
-  if (active) {
+  if (k < ns) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int o = 0; o < kTreeParts; ++o)
+      for (int a = 0; a < 3; ++a) acc[a] += P.tpart[((size_t)o * 3 + a) * ns + k];
     const uint32_t i = P.sidx[k];
     const double gm = P.G * P.m[i];
     for (int a = 0; a < 3; ++a) acc[a] *= gm;
     if (P.pert_on) {
       const int nxt = P.parity ^ 1;
-      const double d[3] = {P.pert_r[nxt][0] - x, P.pert_r[nxt][1] - y, P.pert_r[nxt][2] - z};
+      const double d[3] = {P.pert_r[nxt][0] - P.xs[k], P.pert_r[nxt][1] - P.xs[ns + k],
+                           P.pert_r[nxt][2] - P.xs[2 * ns + k]};
       const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       const double f = gm * P.pert_M / (r2 * sqrt(r2));
       for (int a = 0; a < 3; ++a) {
@@ -527,7 +646,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_walk(const PileDev* __restrict_
   for (int off = 32; off > 0; off >>= 1)
     for (int a = 0; a < 3; ++a) pull[a] += __shfl_xor(pull[a], off);
   __shared__ double red[4][3];
-  if (lane == 0)
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
     for (int a = 0; a < 3; ++a) red[wave][a] = pull[a];
   __syncthreads();
   if (threadIdx.x == 0)
@@ -591,7 +711,8 @@ void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level
   for (int l = 10; l >= 0; --l)
     if (n_level[l] > 0)
       hipLaunchKernelGGL(k_tree_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles, wl_level[l], l);
-  hipLaunchKernelGGL(k_tree_walk, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
+  hipLaunchKernelGGL(k_tree_walk, dim3(n_sph_blk * kTreeParts), dim3(kBlock), 0, st, piles, wl_sph);
+  hipLaunchKernelGGL(k_tree_combine, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
 }
 
 }  // namespace dem
