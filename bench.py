@@ -47,6 +47,15 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Executed FP64 FLOP of the tree walk per launch (64 x SQ_INSTS_VALU_FLOPS_FP64
+# from rocprofv3 --pmc), for the tree run's roofline; valid only for the
+# gravity source it was measured on.
+MEASURED_TREE_FLOP = {
+    # (spheres, opening angle, leaf): (FLOP per launch, sha256[:16] of kernels_gravity.hip)
+    (124958, 0.5, 32): (1.787e10, "eebcb06f4cc46d31"),
+}
+
+
 def gravity_source_hash():
     import hashlib
     path = os.path.join(ROOT, "paper_2311_11322_amd", "csrc", "kernels_gravity.hip")
@@ -88,6 +97,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--gravity", choices=["direct", "tree"], default="direct",
+                    help="gravity of the headline run: exact direct sum, or the tree "
+                         "(opening angle 0.5, leaves of 32, FP64)")
     ap.add_argument("--n-agg", type=int, default=25000)
     ap.add_argument("--gravity-tile", type=int, default=0, help="0: library default")
     ap.add_argument("--cell-scale", type=float, default=1.0)
@@ -143,6 +155,8 @@ def main():
     w = W.collapse_cloud(1, n_agg=args.n_agg)
     log(f"workload: {w.n_agg} aggregates, {w.n_sph} spheres ({time.time() - t:.1f} s to place)")
     prec = dem.PREC_FP32_FORCE if args.precision == "fp32" else dem.PREC_FP64
+    if args.gravity == "tree":
+        w.params.update(gravity_tree=1, theta=0.5, tree_leaf=32)
     torch.cuda.init()
     alloc = dem.TorchAllocator(0)
     sim = dem.Sim(w.params, precision=prec, allocator=alloc, stream=dem.torch_stream())
@@ -176,16 +190,25 @@ def main():
     n = w.n_sph
     grav_ms = prof["gravity"] / prof["_steps"]
     flop = GRAVITY_FLOP_PER_PAIR * n * (n - 1)
+    if args.gravity == "tree":
+        mt = MEASURED_TREE_FLOP.get((n, 0.5, 32))
+        flop = mt[0] if mt and mt[1] == gravity_source_hash() else float("nan")
     achieved = flop / (grav_ms * 1e-3) / 1e12
     dt_key = "fp32" if prec == dem.PREC_FP32_FORCE else "fp64"
     tile = args.gravity_tile or dem.gravity_tiles(prec)[0]
     meas = MEASURED_TRAFFIC.get((dt_key, n, tile))
-    traffic = meas[0] if meas and meas[1] == gravity_source_hash() else None
-    roofline = {"kernel": "gravity", "bound": "alu", "achieved": round(achieved, 3),
+    traffic = (meas[0] if meas and meas[1] == gravity_source_hash() and args.gravity == "direct"
+               else None)
+    roofline = {"kernel": "gravity" if args.gravity == "direct" else "gravity (tree)",
+                "bound": "alu", "achieved": round(achieved, 3) if achieved == achieved else None,
                 "peak": PEAK_TFLOPS[dt_key], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[dt_key], 4), "traffic": traffic,
+                "frac": round(achieved / PEAK_TFLOPS[dt_key], 4) if achieved == achieved else None,
+                "traffic": traffic,
                 "avg_ms": round(grav_ms, 4),
-                "algorithmic": f"{GRAVITY_FLOP_PER_PAIR} FLOP x N(N-1) ordered pairs per launch"}
+                "algorithmic": (f"{GRAVITY_FLOP_PER_PAIR} FLOP x N(N-1) ordered pairs per launch"
+                                if args.gravity == "direct" else
+                                "FP64 FLOP the tree kernels execute per launch (64 x "
+                                "SQ_INSTS_VALU_FLOPS_FP64, rocprofv3 --pmc)")}
     per_kernel = {k: round(v / prof["_steps"], 4) for k, v in prof.items() if not k.startswith("_")}
     state = sim.read_state(["agg_pos"])
     out = {
@@ -196,7 +219,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"gravitational collapse, {w.n_agg} aggregates of 2-8 spheres "
                                f"({w.n_sph} spheres), ball at packing 0.15, G=1, softening 0.5, "
-                               f"dt=5e-4, {'plain FP64' if prec == 0 else 'FP32-force'}",
+                               f"dt=5e-4, {'plain FP64' if prec == 0 else 'FP32-force'}"
+                               + (", tree gravity (opening angle 0.5, leaves of 32)"
+                                  if args.gravity == "tree" else ""),
                    "n_spheres": w.n_sph, "n_aggregates": w.n_agg, "contacts": state["n_pairs"]},
         "graph_replay_value": round(graph_value, 1),
         "kernel_ms_per_step": per_kernel,
