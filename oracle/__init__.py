@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
         ("shake_phase", C.c_double),
         ("gravity_tree", C.c_int32), ("theta", C.c_double), ("tree_leaf", C.c_int32),
+        ("tree_order", C.c_int32),
     ]
 
 
@@ -63,7 +64,7 @@ def lib():
         L.ora_gravity.argtypes = [_PD, _PD, _PD, C.c_int64, C.c_double, C.c_double, _PI64,
                                   C.c_int64, _PD]
         L.ora_tree_gravity.argtypes = [_PD, _PD, _PD, C.c_int64, C.c_double, C.c_double,
-                                       C.c_double, C.c_int32, _PD]
+                                       C.c_double, C.c_int32, C.c_int32, _PD]
         L.ora_set_perturber.argtypes = [C.c_void_p, C.c_double, _PD, _PD]
         L.ora_get_perturber.argtypes = [C.c_void_p, _PD, _PD, _PD]
         L.ora_rotate.argtypes = [_PD, _PD, _PD, _PD, C.c_double, _PD]
@@ -111,6 +112,7 @@ def make_params(d: Dict) -> Params:
     p.gravity_tree = int(d.get("gravity_tree", 0))
     p.theta = float(d.get("theta", 0.5))
     p.tree_leaf = int(d.get("tree_leaf", 16))
+    p.tree_order = int(d.get("tree_order", 4))
     return p
 
 
@@ -234,15 +236,15 @@ def gravity(pos, mass, radius, G, soft_frac, idx=None) -> np.ndarray:
     return F
 
 
-def tree_gravity(pos, mass, radius, G, soft_frac, theta=0.5, leaf=16) -> np.ndarray:
-    """Tree gravity (monopole + quadrupole) on every sphere."""
+def tree_gravity(pos, mass, radius, G, soft_frac, theta=0.5, leaf=16, order=4) -> np.ndarray:
+    """Tree gravity (multipoles to order 2 or 4) on every sphere."""
     pos = _f64(pos)
     mass = _f64(mass)
     radius = _f64(radius)
     n = mass.shape[0]
     F = np.zeros((n, 3))
     lib().ora_tree_gravity(_p(pos), _p(mass), _p(radius), n, float(G), float(soft_frac),
-                           float(theta), int(leaf), _p(F))
+                           float(theta), int(leaf), int(order), _p(F))
     return F
 
 

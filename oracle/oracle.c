@@ -649,13 +649,16 @@ void ora_gravity(const double* pos, const double* mass, const double* radius, in
 typedef struct {
     uint32_t prefix;
     int64_t s, e;          /* range in the sorted order */
-    double M, c[3], Q[6];  /* mass, centre of mass, traceless quadrupole xx yy zz xy xz yz */
+    double M, c[3];        /* mass, centre of mass */
+    double Ms1, Ms2;       /* sum m s, sum m s^2 (s = sphere radius) */
+    /* raw moments about the centre of mass: sum m d_i d_j (d_k (d_l)) */
+    double M2[3][3], M3[3][3][3], M4[3][3][3][3];
 } tnode;
 
 typedef struct {
     const double *r, *m, *rad;
     double G, soft_frac, theta;
-    int leaf, bits;
+    int leaf, bits, mp_order;  /* highest multipole order kept */
     double lo[3], cell;
     int64_t* order;        /* sorted index -> sphere */
     uint32_t* key;         /* sorted keys */
@@ -696,18 +699,25 @@ static void node_moments(const tree* t, tnode* nd)
     }
     nd->M = M;
     for (c = 0; c < 3; c++) nd->c[c] = mc[c] / M;
-    for (c = 0; c < 6; c++) nd->Q[c] = 0.0;
+    nd->Ms1 = nd->Ms2 = 0.0;
+    memset(nd->M2, 0, sizeof(nd->M2));
+    memset(nd->M3, 0, sizeof(nd->M3));
+    memset(nd->M4, 0, sizeof(nd->M4));
     for (k = nd->s; k < nd->e; k++) {
         int64_t i = t->order[k];
-        double d[3], d2;
+        double d[3], m = t->m[i];
+        int a, b, e, f;
         for (c = 0; c < 3; c++) d[c] = t->r[3 * i + c] - nd->c[c];
-        d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        nd->Q[0] += t->m[i] * (3.0 * d[0] * d[0] - d2);
-        nd->Q[1] += t->m[i] * (3.0 * d[1] * d[1] - d2);
-        nd->Q[2] += t->m[i] * (3.0 * d[2] * d[2] - d2);
-        nd->Q[3] += t->m[i] * 3.0 * d[0] * d[1];
-        nd->Q[4] += t->m[i] * 3.0 * d[0] * d[2];
-        nd->Q[5] += t->m[i] * 3.0 * d[1] * d[2];
+        nd->Ms1 += m * t->rad[i];
+        nd->Ms2 += m * t->rad[i] * t->rad[i];
+        for (a = 0; a < 3; a++)
+            for (b = 0; b < 3; b++) {
+                nd->M2[a][b] += m * d[a] * d[b];
+                for (e = 0; e < 3; e++) {
+                    nd->M3[a][b][e] += m * d[a] * d[b] * d[e];
+                    for (f = 0; f < 3; f++) nd->M4[a][b][e][f] += m * d[a] * d[b] * d[e] * d[f];
+                }
+            }
     }
 }
 
@@ -723,21 +733,88 @@ static const tnode* find_node(const tree* t, int l, uint32_t prefix)
     return NULL;
 }
 
-/* force per unit target mass of a node's monopole + quadrupole at R = x - c */
-static void m2p(const tnode* nd, const double* x, double G, double* a)
+/* Force per unit target mass of a node at R = x - c, from the expansion
+ * 1/|R - d| = sum_n (2n-1)!!/n! [d^n]_traceless . R^n / R^(2n+1).  With
+ * S_n = Q_n . R^n (Q_n the traceless part of the raw moment M_n) and
+ * V_n = Q_n . R^(n-1) = grad S_n / n, the pull is
+ * G sum_n c_n [n V_n / R^(2n+1) - (2n+1) S_n R / R^(2n+3)], c_n = (2n-1)!!/n!;
+ * the dipole vanishes about the centre of mass.  Orders n <= the tree's order.
+ *
+ * The pairs are Plummer-softened, 1/sqrt(|R - d|^2 + eps^2): the eps^2 term
+ * of that expansion, -eps^2 / (2 R^3), is of the quadrupole's order and is
+ * kept, with E = sum_j m_j eps_ij^2 = (f/2)^2 (s_i^2 M + 2 s_i sum m s + sum m s^2)
+ * for eps_ij = f (s_i + s_j)/2; its pull is +3/2 G E R / R^5. */
+static void m2p(const tnode* nd, const double* x, double si, const tree* t, double* acc)
 {
+    const int order = t->mp_order;
     double R[3] = {x[0] - nd->c[0], x[1] - nd->c[1], x[2] - nd->c[2]};
     double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
     double r = sqrt(r2);
-    double ir3 = 1.0 / (r2 * r), ir5 = ir3 / r2, ir7 = ir5 / r2;
-    const double* Q = nd->Q;
-    double QR[3] = {Q[0] * R[0] + Q[3] * R[1] + Q[4] * R[2],
-                    Q[3] * R[0] + Q[1] * R[1] + Q[5] * R[2],
-                    Q[4] * R[0] + Q[5] * R[1] + Q[2] * R[2]};
-    double RQR = R[0] * QR[0] + R[1] * QR[1] + R[2] * QR[2];
-    int c;
-    for (c = 0; c < 3; c++)
-        a[c] += G * (-nd->M * R[c] * ir3 + QR[c] * ir5 - 2.5 * RQR * R[c] * ir7);
+    double S[5] = {0, 0, 0, 0, 0}, V[5][3];
+    int a, b, e, f, n;
+    memset(V, 0, sizeof(V));
+    S[0] = nd->M;
+    if (order >= 2) {
+        double tr = nd->M2[0][0] + nd->M2[1][1] + nd->M2[2][2];
+        for (a = 0; a < 3; a++) {
+            double v = 0.0;
+            for (b = 0; b < 3; b++) v += nd->M2[a][b] * R[b];
+            V[2][a] = v - tr * R[a] / 3.0;
+            S[2] += v * R[a];
+        }
+        S[2] -= tr * r2 / 3.0;
+    }
+    if (order >= 3) {
+        double tv[3], tR = 0.0;
+        for (a = 0; a < 3; a++) {
+            tv[a] = nd->M3[0][0][a] + nd->M3[1][1][a] + nd->M3[2][2][a];
+            tR += tv[a] * R[a];
+        }
+        for (a = 0; a < 3; a++) {
+            double v = 0.0;
+            for (b = 0; b < 3; b++)
+                for (e = 0; e < 3; e++) v += nd->M3[a][b][e] * R[b] * R[e];
+            V[3][a] = v - (2.0 * R[a] * tR + r2 * tv[a]) / 5.0;
+            S[3] += v * R[a];
+        }
+        S[3] -= 3.0 / 5.0 * r2 * tR;
+    }
+    if (order >= 4) {
+        double U[3][3], UR[3] = {0, 0, 0}, URR = 0.0, sU = 0.0;
+        for (a = 0; a < 3; a++)
+            for (b = 0; b < 3; b++)
+                U[a][b] = nd->M4[0][0][a][b] + nd->M4[1][1][a][b] + nd->M4[2][2][a][b];
+        for (a = 0; a < 3; a++) {
+            for (b = 0; b < 3; b++) UR[a] += U[a][b] * R[b];
+            URR += UR[a] * R[a];
+            sU += U[a][a];
+        }
+        for (a = 0; a < 3; a++) {
+            double v = 0.0;
+            for (b = 0; b < 3; b++)
+                for (e = 0; e < 3; e++)
+                    for (f = 0; f < 3; f++) v += nd->M4[a][b][e][f] * R[b] * R[e] * R[f];
+            V[4][a] = v - 3.0 / 7.0 * (R[a] * URR + r2 * UR[a]) + 3.0 / 35.0 * r2 * R[a] * sU;
+            S[4] += v * R[a];
+        }
+        S[4] += -6.0 / 7.0 * r2 * URR + 3.0 / 35.0 * r2 * r2 * sU;
+    }
+    {
+        const double cn[5] = {1.0, 0.0, 1.5, 2.5, 4.375};
+        double irn = 1.0 / r;               /* 1 / R^(2n+1), n = 0 */
+        for (n = 0; n <= order && n <= 4; n++) {
+            if (n > 0) irn /= r2;
+            if (n == 1) continue;
+            for (a = 0; a < 3; a++)
+                acc[a] += t->G * cn[n] * (n * V[n][a] * irn - (2 * n + 1) * S[n] * R[a] * irn / r2);
+        }
+        if (order >= 2) {
+            double hf = 0.5 * t->soft_frac;
+            double E = hf * hf * (si * si * nd->M + 2.0 * si * nd->Ms1 + nd->Ms2);
+            double ir5 = 1.0 / (r2 * r2 * r);
+            for (a = 0; a < 3; a++) acc[a] += t->G * 1.5 * E * R[a] * ir5;
+        }
+    }
 }
 
 static void visit(tree* t, int l, uint32_t prefix)
@@ -765,7 +842,7 @@ static void visit(tree* t, int l, uint32_t prefix)
         for (g = t->g0; g < t->g1; g++) {
             int64_t i = t->order[g];
             double a[3] = {0.0, 0.0, 0.0};
-            m2p(nd, &t->r[3 * i], t->G, a);
+            m2p(nd, &t->r[3 * i], t->rad[i], t, a);
             for (c = 0; c < 3; c++) t->acc[3 * (g - t->g0) + c] += t->m[i] * a[c];
         }
         return;
@@ -788,7 +865,8 @@ static void visit(tree* t, int l, uint32_t prefix)
 }
 
 void ora_tree_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
-                      double G, double soft_frac, double theta, int32_t leaf, double* F)
+                      double G, double soft_frac, double theta, int32_t leaf, int32_t order,
+                      double* F)
 {
     tree t;
     int64_t i, k;
@@ -797,7 +875,7 @@ void ora_tree_gravity(const double* pos, const double* mass, const double* radiu
     uint32_t* key_of = (uint32_t*)malloc(n * sizeof(uint32_t));
     memset(&t, 0, sizeof(t));
     t.r = pos; t.m = mass; t.rad = radius; t.G = G; t.soft_frac = soft_frac;
-    t.theta = theta; t.leaf = leaf;
+    t.theta = theta; t.leaf = leaf; t.mp_order = order;
     /* depth: about two finest cells per sphere, 2..10 levels */
     {
         int lg = 0;
@@ -839,7 +917,10 @@ void ora_tree_gravity(const double* pos, const double* mass, const double* radiu
     /* nodes of every level: runs of equal prefix */
     for (l = 0; l <= t.bits; l++) {
         int sh = 3 * (t.bits - l);
-        t.lev[l] = (tnode*)malloc(n * sizeof(tnode));
+        int64_t runs = 0;
+        for (k = 0; k < n; k++)
+            if (k == 0 || (t.key[k] >> sh) != (t.key[k - 1] >> sh)) runs++;
+        t.lev[l] = (tnode*)malloc((size_t)runs * sizeof(tnode));
         t.nlev[l] = 0;
         for (k = 0; k < n;) {
             uint32_t p = t.key[k] >> sh;
@@ -968,7 +1049,7 @@ static void evaluate(ora_sim* s, int carry_history)
     if (s->p.G != 0.0 && s->p.gravity_tree) {
         double* Fg = (double*)malloc(3 * s->ns * sizeof(double));
         ora_tree_gravity(s->r, s->m, s->s, s->ns, s->p.G, s->p.soft_frac, s->p.theta,
-                         s->p.tree_leaf, Fg);
+                         s->p.tree_leaf, s->p.tree_order, Fg);
         for (i = 0; i < 3 * s->ns; i++) s->F[i] += Fg[i];
         free(Fg);
     } else if (s->p.G != 0.0) {

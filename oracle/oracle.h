@@ -43,6 +43,7 @@ typedef struct {
     int32_t gravity_tree;
     double theta;
     int32_t tree_leaf;
+    int32_t tree_order;  /* 2: monopole + quadrupole; 4: up to hexadecapole */
 } ora_params;
 
 typedef struct ora_sim ora_sim;
@@ -104,7 +105,8 @@ int64_t ora_find_contacts(const double* pos, const double* radius, const int32_t
 void ora_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
                  double G, double soft_frac, const int64_t* idx, int64_t n_idx, double* F);
 
-/* Tree gravity (monopole + quadrupole about each node's centre of mass).
+/* Tree gravity (multipoles about each node's centre of mass up to the
+ * quadrupole, order 2, or the hexadecapole, order 4).
  * The tree: a cube grid over the bounding box of the centres -- bits =
  * ceil(ceil(log2 2n) / 3) levels (2..10), finest cell side
  * max(2 * largest radius, 1.000000000001 * largest extent / 2^bits) -- with
@@ -115,7 +117,8 @@ void ora_gravity(const double* pos, const double* mass, const double* radius, in
  * box exceeds side / theta, else as direct (softened) pairs when it holds at
  * most `leaf` spheres or is a finest cell, else it is opened. */
 void ora_tree_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
-                      double G, double soft_frac, double theta, int32_t leaf, double* F);
+                      double G, double soft_frac, double theta, int32_t leaf, int32_t order,
+                      double* F);
 
 /* One fixed Cash-Karp step of the torque-coupled Euler equations for a single
  * body (exposed for the rotation pins).  q[4], wb[3] updated in place; err
