@@ -376,10 +376,10 @@ def _big_collapse(n_agg):
     return W.collapse_cloud(2, n_agg=n_agg)
 
 
-def tree_run(w, steps, theta=0.5, leaf=16):
+def tree_run(w, steps, theta=0.5, leaf=16, order=4):
     """Tree gravity (FP64) on a workload: ms per step and gravity ms."""
     from paper_2311_11322_amd import dem
-    prm = dict(w.params, gravity_tree=1, theta=theta, tree_leaf=leaf)
+    prm = dict(w.params, gravity_tree=1, theta=theta, tree_leaf=leaf, tree_order=order)
     st = dem.Sim(prm)
     st.add_workload(w)
     st.step(1)
@@ -391,7 +391,7 @@ def tree_run(w, steps, theta=0.5, leaf=16):
     return {"value": round(w.n_sph * steps / wall, 1), "unit": "sphere-steps/s",
             "ms_per_step": round(1e3 * wall / steps, 4),
             "gravity_ms": round(pt["gravity"] / pt["_steps"], 4),
-            "theta": theta, "leaf": leaf}
+            "theta": theta, "leaf": leaf, "order": order}
 
 
 def big_run(args, out, wbig):

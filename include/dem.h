@@ -85,15 +85,19 @@ typedef struct {
     double shake_amp[6][3];
     double shake_omega, shake_phase;
     /* Tree gravity instead of the exact direct sum (the paper's own gravity
-     * is a tree code, Sec. 2): a node of the pyramid of the pile's cubic
-     * cell grid acts on a group of 64 spheres through its monopole and
-     * quadrupole when its cube's centre is farther from the group's bounding
-     * box than side / tree_theta, through softened pairs when it holds at most
-     * tree_leaf spheres; FP64 in both precisions.  Needs an open system;
-     * 0 < tree_theta <= 1, 1 <= tree_leaf <= 4096. */
+     * is a tree code with multipoles to hexadecapole order, Sec. 2): a node
+     * of the pyramid of the pile's cubic cell grid acts on a group of 64
+     * spheres through its multipoles about its centre of mass, to order
+     * tree_order (2: quadrupole, 4: hexadecapole), plus the eps^2 term of the
+     * softened kernel's expansion, when its cube's centre is farther from the
+     * group's bounding box than side / tree_theta; through softened pairs
+     * when it holds at most tree_leaf spheres; FP64 in both precisions.
+     * Needs an open system; 0 < tree_theta <= 1, 1 <= tree_leaf <= 4096,
+     * tree_order 2 or 4. */
     int32_t gravity_tree;
     double tree_theta;
     int32_t tree_leaf;
+    int32_t tree_order;
 } dem_params;
 
 typedef struct {

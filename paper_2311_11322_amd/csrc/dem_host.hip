@@ -181,7 +181,8 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
     L.add(reinterpret_cast<double**>(&h.jrec), 8 * ns);
     L.add(&h.gacc, 3 * ns);
     if (z.tree) {
-      L.add(&h.tmom, 10 * z.tree_nodes);
+      L.add(&h.tmom, kMom * z.tree_nodes);
+      L.add(&h.traw, kRaw * z.tree_nodes);
       L.add(&h.tpart, 64 * 3 * ns);
     } else {
       // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
@@ -237,6 +238,7 @@ struct Batch {
   WorkItem* wl_tree[11] = {};                // per pyramid level: (pile, first node)
   int n_tree[11] = {};
   bool any_tree = false;
+  bool tree_order[2] = {false, false};       // some tree pile of order 2, 4
   int n_sph_blk = 0;
   // gravity tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
@@ -341,6 +343,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   std::vector<ScanItem> ic, ip;
   b.any_grav = false;
   b.any_tree = false;
+  b.tree_order[0] = b.tree_order[1] = false;
   b.all_soft = true;
   for (int p = 0; p < (int)b.members.size(); ++p) {
     const dem_sim* s = b.members[p];
@@ -351,6 +354,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
     if (h.G != 0.0 && h.tree) {
       b.any_grav = true;
       b.any_tree = true;
+      b.tree_order[h.tree_order == 4 ? 1 : 0] = true;
       for (int l = 0; l <= h.bits; ++l)
         for (int64_t q = 0; q < (int64_t(1) << (3 * l)); q += kBlock) wtree[l].push_back({p, (int32_t)q});
     } else if (h.G != 0.0) {
@@ -461,7 +465,8 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
       launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
     launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
-    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.wl_sph, b.n_sph_blk);
+    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.wl_sph, b.n_sph_blk,
+                               b.tree_order);
   }
   mark(12);
   launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
@@ -528,6 +533,7 @@ dem_status valid_params(const dem_params* p, std::string* why) {
     if (p->periodic) return bad("tree gravity needs an open (non-periodic) system");
     if (!(p->tree_theta > 0.0 && p->tree_theta <= 1.0)) return bad("tree_theta must be in (0, 1]");
     if (p->tree_leaf < 1 || p->tree_leaf > 4096) return bad("tree_leaf must be in 1..4096");
+    if (p->tree_order != 2 && p->tree_order != 4) return bad("tree_order must be 2 or 4");
   }
   for (int w = 0; w < p->n_walls; ++w) {
     double nn = 0.0;
@@ -595,6 +601,7 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.tree = s->sz.tree ? 1 : 0;
   h.tree_leaf = s->prm.tree_leaf;
   h.theta = s->prm.tree_theta;
+  h.tree_order = s->prm.tree_order;
   h.n_walls = s->prm.n_walls;
   for (int k = 0; k < 3; ++k) h.gfield[k] = s->prm.g[k];
   for (int w = 0; w < 6; ++w) {

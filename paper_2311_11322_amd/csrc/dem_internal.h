@@ -18,9 +18,12 @@ constexpr int kHist = 7;           // spring history per contact: xi_t[3], xi_r[
 constexpr int kScanItems = 8;      // elements per thread in the batched scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kScanSingleItems = 4;   // segments of at most this many chunks: one-launch scan
-constexpr int kRunCache = 16;
+constexpr int kRunCache = 16;      // contact ids per run kept by the search's find pass
 constexpr int kMaxBig = 64;        // big spheres per pile searched separately
-constexpr int kBigRun = 2048;      // contacts per run of a big sphere (LDS sort)      // contact ids per run kept by the search's find pass
+constexpr int kBigRun = 2048;      // contacts per run of a big sphere (LDS sort)
+constexpr int kMom = 40;           // per tree node: M, c[3], sum m e, sum m e^2, traceless
+                                   // Q2[6], Q3[10], Q4[15], 3 unused
+constexpr int kRaw = 32;           // per tree node: raw M2[6], M3[10], M4[15], 1 unused
 
 // status bits of a pile (device-written)
 constexpr int kStCapacity = 1;
@@ -94,7 +97,10 @@ struct PileDev {
   int32_t tree;              // 1: tree instead of the direct sum
   int32_t tree_leaf;         // nodes of at most this many spheres act as pairs
   double theta;              // opening angle
-  double* tmom;              // [sum_l 8^l][10] node moments, level l at (8^l - 1) / 7
+  int32_t tree_order;        // highest multipole order: 2 or 4
+  int32_t pad5;
+  double* tmom;              // [sum_l 8^l][kMom] node moments, level l at (8^l - 1) / 7
+  double* traw;              // [sum_l 8^l][kRaw] raw moments about each node's centre of mass
   double* tpart;             // [64][3][ns] tree sum per level-2 subtree, by sorted slot
 
   // device-updated bookkeeping
@@ -229,8 +235,9 @@ void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
+// any_order[0], [1]: some tree pile of multipole order 2, 4
 void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level,
-                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk);
+                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk, const bool* any_order);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
                  int n_items, uint32_t* item_sums, int max_seg_items);

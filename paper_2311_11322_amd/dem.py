@@ -54,6 +54,7 @@ class dem_params(C.Structure):
         ("shake_amp", (C.c_double * 3) * 6), ("shake_omega", C.c_double),
         ("shake_phase", C.c_double),
         ("gravity_tree", C.c_int32), ("tree_theta", C.c_double), ("tree_leaf", C.c_int32),
+        ("tree_order", C.c_int32),
     ]
 
 
@@ -182,6 +183,7 @@ def make_params(d: Dict, precision: int = PREC_FP64, max_contacts: int = 0,
     p.gravity_tree = int(d.get("gravity_tree", 0))
     p.tree_theta = float(d.get("theta", 0.5))
     p.tree_leaf = int(d.get("tree_leaf", 16))
+    p.tree_order = int(d.get("tree_order", 4))
     return p
 
 

@@ -48,7 +48,12 @@ def test_parameter_validation_on_host():
                 dict(walls=[(0.0, 0.0, 1.0, 0.0)], periodic=1, box=(9.0, 9.0, 9.0)),
                 dict(walls=[(0.0, 0.0, 1.0, float("inf"))]),
                 dict(walls=[(0.0, 0.0, 1.0, 0.0)], shake_amp=[(0.0, 0.0, float("nan"))]),
-                dict(g=(0.0, 0.0, float("nan")))):
+                dict(g=(0.0, 0.0, float("nan"))),
+                dict(G=1.0, gravity_tree=1, tree_order=3),
+                dict(G=1.0, gravity_tree=1, tree_order=0),
+                dict(G=1.0, gravity_tree=1, theta=1.5),
+                dict(G=1.0, gravity_tree=1, tree_leaf=0),
+                dict(G=1.0, gravity_tree=1, periodic=1, box=(9.0, 9.0, 9.0))):
         p = dict(good, **bad)
         with pytest.raises(dem.DemError) as ei:
             dem.Sim(p)
