@@ -41,7 +41,7 @@ CONTACT_BYTES_PER_CONTACT = 64
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (see the
 # profile summaries); valid only for the gravity source it was measured on.
 MEASURED_TRAFFIC = {
-    # (precision, spheres, default tile): (bytes per launch, sha256[:16] of kernels_gravity.hip)
+    # (precision, spheres, default tile): (bytes per launch, source_hash("kernels_gravity.hip"))
     ("fp64", 124958, 512): (2300.4e6, "093ba97f3690bd1f"),
     ("fp32", 124958, 1024): (539.8e6, "093ba97f3690bd1f"),
 }
@@ -51,16 +51,20 @@ MEASURED_TRAFFIC = {
 # from rocprofv3 --pmc), for the tree run's roofline; valid only for the
 # gravity source it was measured on.
 MEASURED_TREE_FLOP = {
-    # (spheres, opening angle, leaf): (FLOP per launch, sha256[:16] of kernels_gravity.hip)
-    (124958, 0.5, 32): (1.787e10, "eebcb06f4cc46d31"),
+    # (spheres, opening angle, leaf, order): (FLOP per launch, source_hash("kernels_tree.hip"))
+    (124958, 0.5, 32, 4): (float("nan"), ""),
 }
 
 
-def gravity_source_hash():
+def source_hash(name):
+    """sha256[:16] of a gravity kernel source together with the header the
+    gravity sources share."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2311_11322_amd", "csrc", "kernels_gravity.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in (name, "gravity_common.h"):
+        with open(os.path.join(ROOT, "paper_2311_11322_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -156,7 +160,7 @@ def main():
     log(f"workload: {w.n_agg} aggregates, {w.n_sph} spheres ({time.time() - t:.1f} s to place)")
     prec = dem.PREC_FP32_FORCE if args.precision == "fp32" else dem.PREC_FP64
     if args.gravity == "tree":
-        w.params.update(gravity_tree=1, theta=0.5, tree_leaf=32)
+        w.params.update(gravity_tree=1, theta=0.5, tree_leaf=32, tree_order=4)
     torch.cuda.init()
     alloc = dem.TorchAllocator(0)
     sim = dem.Sim(w.params, precision=prec, allocator=alloc, stream=dem.torch_stream())
@@ -191,13 +195,14 @@ def main():
     grav_ms = prof["gravity"] / prof["_steps"]
     flop = GRAVITY_FLOP_PER_PAIR * n * (n - 1)
     if args.gravity == "tree":
-        mt = MEASURED_TREE_FLOP.get((n, 0.5, 32))
-        flop = mt[0] if mt and mt[1] == gravity_source_hash() else float("nan")
+        mt = MEASURED_TREE_FLOP.get((n, 0.5, 32, 4))
+        flop = mt[0] if mt and mt[1] == source_hash("kernels_tree.hip") else float("nan")
     achieved = flop / (grav_ms * 1e-3) / 1e12
     dt_key = "fp32" if prec == dem.PREC_FP32_FORCE else "fp64"
     tile = args.gravity_tile or dem.gravity_tiles(prec)[0]
     meas = MEASURED_TRAFFIC.get((dt_key, n, tile))
-    traffic = (meas[0] if meas and meas[1] == gravity_source_hash() and args.gravity == "direct"
+    traffic = (meas[0] if meas and meas[1] == source_hash("kernels_gravity.hip")
+               and args.gravity == "direct"
                else None)
     roofline = {"kernel": "gravity" if args.gravity == "direct" else "gravity (tree)",
                 "bound": "alu", "achieved": round(achieved, 3) if achieved == achieved else None,
