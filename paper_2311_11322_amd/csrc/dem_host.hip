@@ -356,7 +356,10 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       b.any_tree = true;
       b.tree_order[h.tree_order == 4 ? 1 : 0] = true;
       for (int l = 0; l <= h.bits; ++l)
-        for (int64_t q = 0; q < (int64_t(1) << (3 * l)); q += kBlock) wtree[l].push_back({p, (int32_t)q});
+        // the finest level: 256 nodes per block; above it eight lanes per node
+        for (int64_t q = 0, step = l == h.bits ? kBlock : kBlock / 8; q < (int64_t(1) << (3 * l));
+             q += step)
+          wtree[l].push_back({p, (int32_t)q});
     } else if (h.G != 0.0) {
       b.any_grav = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;

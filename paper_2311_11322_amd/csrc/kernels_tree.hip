@@ -118,9 +118,15 @@ __device__ __forceinline__ void traceless(const double* raw, double* q) {
         }
 }
 
+// An empty node stores only its zero mass: readers look at the mass first.
 __device__ __forceinline__ void store_node(const PileDev& P, size_t node, double M,
                                            const double c[3], double me1, double me2,
                                            const double* raw) {
+  double* o = P.tmom + node * kMom;
+  if (M == 0.0) {
+    o[0] = 0.0;
+    return;
+  }
   double q[kMom];
 #pragma unroll
   for (int u = 0; u < kMom; ++u) q[u] = 0.0;
@@ -131,7 +137,6 @@ __device__ __forceinline__ void store_node(const PileDev& P, size_t node, double
   q[4] = me1;
   q[5] = me2;
   traceless(raw, q);
-  double* o = P.tmom + node * kMom;
 #pragma unroll
   for (int u = 0; u < kMom; ++u) o[u] = q[u];
   double* r = P.traw + node * kRaw;
@@ -179,72 +184,92 @@ __device__ __forceinline__ double binom(int n, int k) {
   return (k == 0 || k == n) ? 1.0 : (n == 2 ? 2.0 : (n == 3 ? 3.0 : (k == 2 ? 6.0 : 4.0)));
 }
 
-// Level l < bits: node p from its eight children in order.  Each child's raw
-// moments are moved from its centre of mass to the node's (d -> d + delta:
-// the binomial expansion of sum m (d + delta)^n, term by term per exponent).
-__device__ void tree_up(const PileDev& P, int l, uint32_t p) {
-  const size_t first = level_offset(l + 1) + ((size_t)p << 3);
-  const double* ch = P.tmom + first * kMom;
-  const double* chr = P.traw + first * kRaw;
-  double M = 0.0, mc[3] = {0.0, 0.0, 0.0}, me1 = 0.0, me2 = 0.0;
-  for (int o = 0; o < 8; ++o) {
-    const double m = ch[o * kMom];
-    M += m;
-    for (int a = 0; a < 3; ++a) mc[a] += m * ch[o * kMom + 1 + a];
-    me1 += ch[o * kMom + 4];
-    me2 += ch[o * kMom + 5];
+// Sum over the eight lanes of an aligned group, in the order
+// ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7)), the same in every lane.
+__device__ __forceinline__ double sum8(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+// Level l < bits: node p from its eight children, child o in lane o of an
+// aligned group of eight lanes.  Each child's raw moments are moved from its
+// centre of mass to the node's (d -> d + delta: the binomial expansion of
+// sum m (d + delta)^n, term by term per exponent), then the eight are summed.
+__device__ void tree_up8(const PileDev& P, int l, uint32_t p, int o, bool valid) {
+  const size_t child = level_offset(l + 1) + ((size_t)p << 3) + (size_t)o;
+  double m = 0.0, co[3] = {0.0, 0.0, 0.0}, e1 = 0.0, e2 = 0.0;
+  if (valid) {
+    const double* q = P.tmom + child * kMom;
+    m = q[0];
+    if (m != 0.0) {
+      co[0] = q[1];
+      co[1] = q[2];
+      co[2] = q[3];
+      e1 = q[4];
+      e2 = q[5];
+    }
   }
+  const double M = sum8(m);
+  const double mc[3] = {sum8(m * co[0]), sum8(m * co[1]), sum8(m * co[2])};
+  const double me1 = sum8(e1), me2 = sum8(e2);
   double c[3] = {0.0, 0.0, 0.0}, raw[kRaw];
 #pragma unroll
   for (int u = 0; u < kRaw; ++u) raw[u] = 0.0;
-  if (M > 0.0) {
+  if (M > 0.0)
     for (int a = 0; a < 3; ++a) c[a] = mc[a] / M;
-    for (int o = 0; o < 8; ++o) {
-      const double* q = ch + o * kMom;
-      const double m = q[0];
-      if (m == 0.0) continue;
-      const double* cr = chr + o * kRaw;
-      const double dl[3] = {q[1] - c[0], q[2] - c[1], q[3] - c[2]};
+  if (m != 0.0) {
+    double cr[kRaw];
+    const double* src = P.traw + child * kRaw;
 #pragma unroll
-      for (int n = 2; n <= 4; ++n) {
-        const int off = n == 2 ? kR2 : (n == 3 ? kR3 : kR4);
+    for (int u = 0; u < kRaw; ++u) cr[u] = src[u];
+    const double dl[3] = {co[0] - c[0], co[1] - c[1], co[2] - c[2]};
 #pragma unroll
-        for (int i = n; i >= 0; --i)
+    for (int n = 2; n <= 4; ++n) {
+      const int off = n == 2 ? kR2 : (n == 3 ? kR3 : kR4);
 #pragma unroll
-          for (int j = n - i; j >= 0; --j) {
-            const int k = n - i - j;
-            double v = 0.0;
+      for (int i = n; i >= 0; --i)
 #pragma unroll
-            for (int i1 = 0; i1 <= i; ++i1)
+        for (int j = n - i; j >= 0; --j) {
+          const int k = n - i - j;
+          double v = 0.0;
 #pragma unroll
-              for (int j1 = 0; j1 <= j; ++j1)
+          for (int i1 = 0; i1 <= i; ++i1)
 #pragma unroll
-                for (int k1 = 0; k1 <= k; ++k1) {
-                  const int n1 = i1 + j1 + k1;
-                  if (n1 == 1) continue;
-                  v += binom(i, i1) * binom(j, j1) * binom(k, k1) *
-                       child_raw(cr, m, n1, i1, j1) *
-                       (ipow(dl[0], i - i1) * ipow(dl[1], j - j1) * ipow(dl[2], k - k1));
-                }
-            raw[off + sym_index(n, i, j)] += v;
-          }
-      }
+            for (int j1 = 0; j1 <= j; ++j1)
+#pragma unroll
+              for (int k1 = 0; k1 <= k; ++k1) {
+                const int n1 = i1 + j1 + k1;
+                if (n1 == 1) continue;
+                v += binom(i, i1) * binom(j, j1) * binom(k, k1) * child_raw(cr, m, n1, i1, j1) *
+                     (ipow(dl[0], i - i1) * ipow(dl[1], j - j1) * ipow(dl[2], k - k1));
+              }
+          raw[off + sym_index(n, i, j)] = v;
+        }
     }
   }
-  store_node(P, level_offset(l) + p, M, c, me1, me2, raw);
+#pragma unroll
+  for (int u = 0; u < 31; ++u) raw[u] = sum8(raw[u]);
+  if (valid && o == 0) store_node(P, level_offset(l) + p, M, c, me1, me2, raw);
 }
 
-// One thread per node of level l of every tree pile: finest-level moments
-// from spheres where l is the pile's depth, else from the level below.
+// Finest level of a pile: one thread per node from its spheres (a block
+// covers 256 nodes).  Other levels: eight lanes per node from its children
+// (a block covers 32 nodes).
 __global__ __launch_bounds__(kBlock) void k_tree_level(const PileDev* __restrict__ piles,
                                                        const WorkItem* __restrict__ wl, int l) {
   const WorkItem w = wl[blockIdx.x];
   const PileDev& P = piles[w.pile];
   if (P.status != 0 || l > P.bits) return;
-  const uint32_t p = (uint32_t)(w.base + threadIdx.x);
-  if (p >= (1u << (3 * l))) return;
-  if (l == P.bits) tree_leaf(P, p);
-  else tree_up(P, l, p);
+  const uint32_t nl = 1u << (3 * l);
+  if (l == P.bits) {
+    const uint32_t p = (uint32_t)(w.base + threadIdx.x);
+    if (p < nl) tree_leaf(P, p);
+  } else {
+    const uint32_t p = (uint32_t)w.base + (threadIdx.x >> 3);
+    tree_up8(P, l, p, threadIdx.x & 7, p < nl);
+  }
 }
 
 // Pull per unit mass at R = x - c of a node's moments q (uniform over the
