@@ -184,6 +184,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
       L.add(&h.tmom, kMom * z.tree_nodes);
       L.add(&h.traw, kRaw * z.tree_nodes);
       L.add(&h.tpart, 64 * 3 * ns);
+      L.add(&h.tbox, 6 * ((ns + 63) / 64));
     } else {
       // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
       const int64_t part_vals = z.g_nt * 3 * ns;

@@ -102,6 +102,7 @@ struct PileDev {
   double* tmom;              // [sum_l 8^l][kMom] node moments, level l at (8^l - 1) / 7
   double* traw;              // [sum_l 8^l][kRaw] raw moments about each node's centre of mass
   double* tpart;             // [64][3][ns] tree sum per level-2 subtree, by sorted slot
+  double* tbox;              // [ceil(ns / 64)][6] bounding box (min xyz, max xyz) of each group
 
   // device-updated bookkeeping
   int32_t parity;            // which half of each ping-pong pair is current

@@ -356,6 +356,31 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// One wave per group of 64 consecutive sorted slots: the group's bounding box.
+__global__ __launch_bounds__(kBlock) void k_tree_boxes(const PileDev* __restrict__ piles,
+                                                       const WorkItem* __restrict__ wl) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0 || !P.tree || P.G == 0.0) return;
+  const int ns = P.ns;
+  const int g0 = w.base + (threadIdx.x & ~63);
+  if (g0 >= ns) return;
+  const int k = w.base + threadIdx.x;
+  const bool active = k < ns;
+  double x = 0.0, y = 0.0, z = 0.0;
+  if (active) {
+    const Rec64* r = (const Rec64*)P.jrec + k;
+    x = r->x;
+    y = r->y;
+    z = r->z;
+  }
+  const double b[6] = {wave_min(active ? x : INFINITY), wave_min(active ? y : INFINITY),
+                       wave_min(active ? z : INFINITY), wave_max(active ? x : -INFINITY),
+                       wave_max(active ? y : -INFINITY), wave_max(active ? z : -INFINITY)};
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 6; ++a) P.tbox[(size_t)(g0 / 64) * 6 + a] = b[a];
+}
+
 // One wave per group of 64 consecutive sorted slots.  The wave walks the
 // pyramid from the root with a stack of opened nodes in LDS.  Each pass takes
 // up to eight opened nodes off the stack and classifies their 64 children at
@@ -373,6 +398,17 @@ __device__ __forceinline__ double wave_max(double v) {
 constexpr int kTreeBatchMax = 512;
 constexpr int kTreeStack = kTreeBatchMax + 56 + 63 + 9;   // 640 node ids per wave
 static_assert(kTreeStack >= kTreeBatchMax + 56 + 63, "tree stack bound");
+
+// Every third bit of v (bits 0, 3, 6, ...) packed together: one axis of a
+// Morton code of up to ten levels.
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v ^ (v >> 2)) & 0x030c30c3u;
+  v = (v ^ (v >> 4)) & 0x0300f00fu;
+  v = (v ^ (v >> 8)) & 0xff0000ffu;
+  v = (v ^ (v >> 16)) & 0x000003ffu;
+  return v;
+}
 
 // node id: (1 << 3l) | p, the level in the position of the leading bit
 __device__ __forceinline__ int node_level(uint32_t id) { return (31 - __clz(id)) / 3; }
@@ -435,10 +471,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(const PileDev* __restrict__ pi
     z = r->z;
     ei = r->e;
   }
-  const double bmin[3] = {wave_min(active ? x : INFINITY), wave_min(active ? y : INFINITY),
-                          wave_min(active ? z : INFINITY)};
-  const double bmax[3] = {wave_max(active ? x : -INFINITY), wave_max(active ? y : -INFINITY),
-                          wave_max(active ? z : -INFINITY)};
+  const ConstD box = (ConstD)P.tbox + (size_t)(w.base / 64) * 6;
+  const double bmin[3] = {box[0], box[1], box[2]};
+  const double bmax[3] = {box[3], box[4], box[5]};
   double acc[3] = {0.0, 0.0, 0.0};
   const double c15 = kSeries[0], c1875 = kSeries[1];
   int sp = 0;
@@ -477,9 +512,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(const PileDev* __restrict__ pi
       t1 = cstart[(size_t)(p + 1) << sh];
       if (t1 > t0) {
         const double side = ldexp(cell, L - l);
-        uint32_t ix[3] = {0u, 0u, 0u};
-        for (int b = 0; b < l; ++b)
-          for (int a = 0; a < 3; ++a) ix[a] |= ((p >> (3 * b + a)) & 1u) << b;
+        const uint32_t ix[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
         double dd[3];
         for (int a = 0; a < 3; ++a) {
           const double ctr = __dadd_rn(g.lo[a], __dmul_rn((double)ix[a] + 0.5, side));
@@ -593,6 +626,7 @@ void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level
   for (int l = 10; l >= 0; --l)
     if (n_level[l] > 0)
       hipLaunchKernelGGL(k_tree_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles, wl_level[l], l);
+  hipLaunchKernelGGL(k_tree_boxes, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
   if (any_order[0])
     hipLaunchKernelGGL(k_tree_walk<2>, dim3(n_sph_blk * 4 * kTreeParts), dim3(64), 0, st, piles,
                        wl_sph);
