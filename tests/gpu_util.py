@@ -28,14 +28,16 @@ def sum_scales(o: O.Oracle):
     relative to the sum of the terms' magnitudes, not to the result: forces
     that nearly cancel (a sphere squeezed evenly by its neighbours) or torques
     of purely normal forces (zero up to rounding) are compared against these
-    scales.  Per sphere: sum of |F| over its contacts, and sum of
-    |tau| + l |F| (lever times force); per aggregate: the members' force
-    scale over M, and sum of |b| F-scale + torque scale."""
+    scales.  Per sphere: sum of |F| over its contacts plus the magnitude of
+    its total force (which covers the gravity terms: an aggregate alone in
+    space has a torque of its members' mutual pulls that is zero up to
+    rounding), and sum of |tau| + l |F| (lever times force); per aggregate:
+    the members' force scale over M, and sum of |b| F-scale + torque scale."""
     a = o.aggregates()
     s = o.spheres()
     p = o.pairs()
     ns = s["r"].shape[0]
-    SF = np.zeros(ns)
+    SF = np.linalg.norm(s["F"], axis=1) if ns else np.zeros(0)
     ST = np.zeros(ns)
     if p["i"].size:
         F = np.linalg.norm(p["force"][:, 0:3], axis=1)

@@ -49,6 +49,25 @@ def test_tree_gravity_parity(D, theta, leaf, order):
     compare_states(sim, o, tol=1e-10)
 
 
+@pytest.mark.parametrize("n_agg,leaf,order", [(1, 16, 4), (3, 4, 4), (3, 16, 2), (12, 4, 4),
+                                               (40, 4, 4), (40, 64, 2)])
+def test_tree_small_piles_parity(D, n_agg, leaf, order):
+    """Piles of 2 to 192 spheres: a root of at most tree_leaf spheres acting
+    as one set of pairs, finest cells above the split level, groups shorter
+    than a wave.  Random spins and velocities keep every compared quantity
+    above rounding noise (a lone aggregate's own pulls cancel)."""
+    say("tree small pile", n_agg, leaf, order)
+    w = _tree(W.collapse_cloud(80 + n_agg, n_agg=n_agg, spin_sigma=0.3, vel_sigma=0.1), 0.5, leaf,
+              order)
+    sim = D.Sim(w.params)
+    sim.add_workload(w)
+    o = O.Oracle(w.params).add_workload(w)
+    compare_states(sim, o)
+    sim.step(2)
+    o.step(2)
+    compare_states(sim, o, tol=1e-10)
+
+
 def test_tree_with_perturber_parity(D):
     say("tree + flyby")
     from paper_2311_11322_amd import serve
