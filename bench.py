@@ -89,10 +89,17 @@ def cpu_baseline(w, n_sample, seconds_cap):
         t_used += time.perf_counter() - t0
         done += len(sl)
     per_sphere = t_used / done
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / per_sphere, "unit": "sphere-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"t0 force evaluation of {done} of {w.n_sph} spheres at full N "
                       f"(brute-force contacts + direct-sum gravity, single thread, "
-                      f"{t_used:.1f} s), scaled by N to a whole step"}
+                      f"{t_used:.1f} s), scaled by N to a whole step",
+            "host_cores_allowed": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
 def main():
