@@ -68,6 +68,26 @@ def test_tree_small_piles_parity(D, n_agg, leaf, order):
     compare_states(sim, o, tol=1e-10)
 
 
+def test_tree_in_fp32_force_form(D):
+    """FP32 contact forces beside the tree (FP64 in both forms): per-sphere
+    force within 1e-5 of the oracle's tree, contact list exact, positions
+    after a step within 1e-12."""
+    say("tree fp32-force")
+    w = _tree(W.collapse_cloud(76, n_agg=300, contact_seeded=True, spin_sigma=0.3, vel_sigma=0.1))
+    sim = D.Sim(w.params, precision=D.PREC_FP32_FORCE)
+    sim.add_workload(w)
+    o = O.Oracle(w.params).add_workload(w)
+    g = sim.read_state(["sph_force"], pairs=True)
+    assert rel_err(g["sph_force"], o.spheres()["F"]) <= 1e-5
+    sim.step(1)
+    o.step(1)
+    g = sim.read_state(["sph_force", "agg_pos"], pairs=True)
+    keys = (o.pairs()["i"].astype(np.uint64) << np.uint64(32)) | o.pairs()["j"].astype(np.uint64)
+    assert np.array_equal(g["pair_keys"], keys)
+    assert rel_err(g["sph_force"], o.spheres()["F"]) <= 1e-5
+    assert rel_err(g["agg_pos"], o.aggregates()["rA"]) <= 1e-12
+
+
 def test_tree_with_perturber_parity(D):
     say("tree + flyby")
     from paper_2311_11322_amd import serve
