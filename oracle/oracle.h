@@ -106,7 +106,10 @@ void ora_gravity(const double* pos, const double* mass, const double* radius, in
                  double G, double soft_frac, const int64_t* idx, int64_t n_idx, double* F);
 
 /* Tree gravity (multipoles about each node's centre of mass up to the
- * quadrupole, order 2, or the hexadecapole, order 4).
+ * quadrupole, order 2, or the hexadecapole, order 4; with order >= 2 also the
+ * eps^2 term of the softened kernel's expansion, which is of the
+ * quadrupole's order).  The paper takes its expansions to hexadecapole order
+ * (Sec. 2) and gives no other detail of its tree.
  * The tree: a cube grid over the bounding box of the centres -- bits =
  * ceil(ceil(log2 2n) / 3) levels (2..10), finest cell side
  * max(2 * largest radius, 1.000000000001 * largest extent / 2^bits) -- with
