@@ -442,19 +442,43 @@ __device__ __forceinline__ void leaf_pairs(ConstRec64 rec, uint32_t t, double x,
 }
 
 // One workgroup of one wave per (group of 64 sorted slots, level-2 subtree).
+// Dispatch order, heaviest first on every XCD: workgroups go round-robin to
+// the 8 XCDs, each XCD takes an eighth of the groups (contiguous, so their
+// trees share its L2), and within an XCD the waves are issued rank by rank:
+// rank r of a group walks the subtree whose digits are those of the group's
+// own level-2 cube XOR r, so the own cube (the near field, most of the work)
+// goes first, then its siblings, then the far octants.  The grid holds
+// kTreeParts waves for each of 8 * ceil(groups / 8) groups; padding returns.
 template <int ORDER>
 __global__ __launch_bounds__(64) void k_tree_walk(const PileDev* __restrict__ piles,
-                                                  const WorkItem* __restrict__ wl) {
+                                                  const WorkItem* __restrict__ wl, int n_items) {
   __shared__ uint32_t stack[kTreeStack];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int gi = blk / kTreeParts;       // the group: a quarter of a work item's block
-  WorkItem w = wl[gi >> 2];
+  const int xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const int gx = gridDim.x / kXcds / kTreeParts;   // groups per XCD
+  const int rank = j / gx, gi = xcd * gx + j % gx;
+  if ((gi >> 2) >= n_items) return;
+  WorkItem w = wl[gi >> 2];              // the group: a quarter of a work item's block
   w.base += (gi & 3) * 64;
-  const int part = blk % kTreeParts;     // the level-2 subtree this wave walks (octal digits)
   const PileDev& P = piles[w.pile];
   if (P.status != 0 || !P.tree || P.G == 0.0 || P.tree_order != ORDER) return;
   const int ns = P.ns, L = P.bits;
   if (w.base >= ns) return;
+  int part = rank;                       // the level-2 subtree this wave walks (octal digits)
+  static_assert(kTreeSplit == 2, "the rank order below reads two digits");
+  {
+    // the level-1 and level-2 digits of the cell of the group's first sphere
+    // (a tree pile has at least two levels)
+    const Rec64* r0 = (const Rec64*)P.jrec + w.base;
+    const double xyz[3] = {r0->x, r0->y, r0->z};
+    const Grid& g0 = *P.grid;
+    int d1 = 0, d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int c = cell_coord(xyz[a], g0.lo[a], g0.inv_cell, 1 << L, 0, 0.0);
+      d1 |= ((c >> (L - 1)) & 1) << a;
+      d2 |= ((c >> (L - 2)) & 1) << a;
+    }
+    part = ((d1 << 3) | d2) ^ rank;
+  }
   const int lane = threadIdx.x;
   const int k = w.base + lane;
   const bool active = k < ns;
@@ -626,13 +650,15 @@ void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level
   for (int l = 10; l >= 0; --l)
     if (n_level[l] > 0)
       hipLaunchKernelGGL(k_tree_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles, wl_level[l], l);
+  // four groups per work item, padded to a multiple of the XCD count
+  const int walk_blocks = ((n_sph_blk * 4 + kXcds - 1) / kXcds) * kXcds * kTreeParts;
   hipLaunchKernelGGL(k_tree_boxes, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
   if (any_order[0])
-    hipLaunchKernelGGL(k_tree_walk<2>, dim3(n_sph_blk * 4 * kTreeParts), dim3(64), 0, st, piles,
-                       wl_sph);
+    hipLaunchKernelGGL(k_tree_walk<2>, dim3(walk_blocks), dim3(64), 0, st, piles, wl_sph,
+                       n_sph_blk);
   if (any_order[1])
-    hipLaunchKernelGGL(k_tree_walk<4>, dim3(n_sph_blk * 4 * kTreeParts), dim3(64), 0, st, piles,
-                       wl_sph);
+    hipLaunchKernelGGL(k_tree_walk<4>, dim3(walk_blocks), dim3(64), 0, st, piles, wl_sph,
+                       n_sph_blk);
   hipLaunchKernelGGL(k_tree_combine, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
 }
 
