@@ -29,14 +29,17 @@ def _tree(w, theta=0.5, leaf=16, order=4):
     return w
 
 
-@pytest.mark.parametrize("theta,leaf,order", [(0.5, 16, 4), (0.3, 4, 4), (0.8, 64, 4),
-                                              (0.5, 16, 2), (0.8, 64, 2)])
-def test_tree_gravity_parity(D, theta, leaf, order):
+@pytest.mark.parametrize("theta,leaf,order,soft", [(0.5, 16, 4, 0.5), (0.3, 4, 4, 0.5),
+                                                   (0.8, 64, 4, 0.5), (0.5, 16, 2, 0.5),
+                                                   (0.8, 64, 2, 0.5), (0.5, 16, 4, 0.0)])
+def test_tree_gravity_parity(D, theta, leaf, order, soft):
     """Same tree, same groups, same opening decisions as the oracle's tree:
-    t0, one step and three more within the parity bar."""
-    say("tree parity", theta, leaf, order)
+    t0, one step and three more within the parity bar (softened, and
+    unsoftened where each sphere's own term must be skipped)."""
+    say("tree parity", theta, leaf, order, soft)
     w = _tree(W.collapse_cloud(71, n_agg=500, contact_seeded=True, spin_sigma=0.2), theta, leaf,
               order)
+    w.params["soft_frac"] = soft
     sim = D.Sim(w.params)
     sim.add_workload(w)
     o = O.Oracle(w.params).add_workload(w)
