@@ -53,6 +53,7 @@ MEASURED_TRAFFIC = {
 MEASURED_TREE_FLOP = {
     # (spheres, opening angle, leaf, order): (FLOP per launch, source_hash("kernels_tree.hip"))
     (124958, 0.5, 32, 4): (3.665e10, "9bd8e9cc1c2c2a96"),
+    (999660, 0.5, 32, 4): (3.844e11, "9bd8e9cc1c2c2a96"),
 }
 
 
