@@ -541,6 +541,23 @@ def extra_runs(args, w, out, prec):
             "makespan_s": round(st["makespan_s"], 2), "completed": st["completed"],
             "failed": st["failed"]}
         log(f"served: {out['served']}")
+        # the same stream under shortest-remaining-work-first chunks (up to
+        # 1e10 gravity pairs per step attached at a time)
+        reqs_s = [serve.Request(r.rid, r.kind, r.workload, r.steps, r.arrival) for r in reqs]
+        srv_s = serve.Server(64 << 30, precision=dem.PREC_FP32_FORCE, chunk_steps=50,
+                             tuning=(tune["gravity_tile"], tune["cell_scale"]), policy="srpt",
+                             pairs_per_step_cap=1e10)
+        st_s = srv_s.run(reqs_s)
+        out["served_srpt"] = {
+            "workload": "the same requests and arrivals; each chunk steps the runs with the least "
+                        "remaining work (spheres^2 x steps) up to 1e10 gravity pairs per step",
+            "p50_latency_s": round(st_s["p50_latency_s"], 3),
+            "p99_latency_s": round(st_s["p99_latency_s"], 3),
+            "sphere_steps_per_s": round(st_s["sphere_steps_per_s"], 1),
+            "service_rate_per_s": round(st_s["service_rate_per_s"], 2),
+            "makespan_s": round(st_s["makespan_s"], 2), "completed": st_s["completed"],
+            "failed": st_s["failed"]}
+        log(f"served (srpt): {out['served_srpt']}")
         # the first half of the same requests offered at 80 % of the measured
         # service rate (same workloads, arrival times stretched)
         rate2 = round(0.8 * st["service_rate_per_s"], 2)

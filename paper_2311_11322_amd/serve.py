@@ -6,6 +6,10 @@
   time, are admitted while the engine's HBM budget allows (footprint from the
   library), join the running batch at the next chunk boundary, and leave it
   when their step count is reached; latency is completion minus arrival.
+  Policy "fifo" steps every admitted run in every chunk; policy "srpt" steps,
+  chunk by chunk, the runs with the least remaining work (spheres^2 x steps
+  left) up to a cap on gravity pairs per step, the others staying resident
+  on the device, detached, until they are among the shortest again.
 
 All stepping runs in the HIP library; this module only schedules.
 """
@@ -132,7 +136,12 @@ class Server:
     """Continuous batching of DEM runs on one engine."""
 
     def __init__(self, hbm_budget_bytes: int, precision: int = dem.PREC_FP32_FORCE,
-                 chunk_steps: int = 50, tuning=None, capture_state: bool = False):
+                 chunk_steps: int = 50, tuning=None, capture_state: bool = False,
+                 policy: str = "fifo", pairs_per_step_cap: float = 5e9):
+        if policy not in ("fifo", "srpt"):
+            raise ValueError("policy must be 'fifo' or 'srpt'")
+        self.policy = policy
+        self.cap = float(pairs_per_step_cap)
         self.engine = dem.Engine(hbm_budget_bytes)
         self.budget = int(hbm_budget_bytes)
         self.used = 0
@@ -141,6 +150,7 @@ class Server:
         self.tuning = tuning
         self.capture = capture_state
         self.active: Dict[int, List] = {}    # rid -> [request, sim, remaining, bytes]
+        self.attached: set = set()           # rids attached to the engine
         self.log: List[str] = []
 
     def footprint(self, w) -> int:
@@ -151,7 +161,6 @@ class Server:
         if self.used + need > self.budget:
             return False
         sim = make_sim(req.workload, self.precision, self.tuning)
-        self.engine.attach(sim)
         self.active[req.rid] = [req, sim, req.steps, need]
         self.used += need
         req.admitted = now
@@ -159,7 +168,9 @@ class Server:
 
     def _finish(self, rid: int, now: float, status: int = 0):
         req, sim, _rem, need = self.active.pop(rid)
-        self.engine.detach(sim)
+        if rid in self.attached:
+            self.engine.detach(sim)
+            self.attached.discard(rid)
         req.status = status
         req.result = {"bulk_radius": bulk_radius(sim), "steps": sim.read_state(["agg_mass"])["step"]}
         if self.capture:
@@ -167,6 +178,21 @@ class Server:
         req.done = now
         sim.close()
         self.used -= need
+
+    def _select(self) -> set:
+        """The runs stepped in the next chunk."""
+        if self.policy == "fifo":
+            return set(self.active)
+        order = sorted(self.active, key=lambda rid: (
+            self.active[rid][0].workload.n_sph ** 2 * self.active[rid][2], rid))
+        run, pairs = set(), 0.0
+        for rid in order:
+            p = float(self.active[rid][0].workload.n_sph) ** 2
+            if run and pairs + p > self.cap:
+                continue
+            run.add(rid)
+            pairs += p
+        return run
 
     def run(self, requests: Sequence[Request], clock=time.perf_counter) -> Dict:
         """Serve requests with their arrival offsets in real time."""
@@ -193,12 +219,19 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                 continue
-            n = min(self.chunk, min(v[2] for v in self.active.values()))
+            run = self._select()
+            for rid in list(self.attached - run):
+                self.engine.detach(self.active[rid][1])
+                self.attached.discard(rid)
+            for rid in sorted(run - self.attached):
+                self.engine.attach(self.active[rid][1])
+                self.attached.add(rid)
+            n = min(self.chunk, min(self.active[rid][2] for rid in run))
             s0 = clock()
             code = self.engine.step(n)
             busy += clock() - s0
             now = clock() - t0
-            for rid in list(self.active):
+            for rid in sorted(run):
                 req, sim, rem, _ = self.active[rid]
                 st = sim.status()
                 sphere_steps += req.workload.n_sph * n

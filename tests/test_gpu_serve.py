@@ -22,14 +22,18 @@ def D():
     return dem
 
 
-def test_served_stream_matches_alone(D):
+@pytest.mark.parametrize("policy", ["fifo", "srpt"])
+def test_served_stream_matches_alone(D, policy):
     """Requests of different sizes arrive while others run; every served
-    result equals the same request run alone, bit for bit."""
+    result equals the same request run alone, bit for bit.  Under "srpt" a
+    small pair cap keeps one or two runs attached per chunk, so runs are
+    detached and re-attached many times on the way."""
     from paper_2311_11322_amd import serve
-    say("served stream vs alone")
+    say("served stream vs alone", policy)
     reqs = serve.request_stream(seed=11, n_requests=6, rate_per_s=50.0, nmin=300, nmax=2500,
                                 smin=10, smax=60)
-    srv = serve.Server(1 << 34, precision=D.PREC_FP32_FORCE, chunk_steps=8, capture_state=True)
+    srv = serve.Server(1 << 34, precision=D.PREC_FP32_FORCE, chunk_steps=8, capture_state=True,
+                       policy=policy, pairs_per_step_cap=2.5e6)
     stats = srv.run(reqs)
     assert stats["completed"] == len(reqs)
     for r in reqs:
