@@ -240,6 +240,7 @@ struct Batch {
   int n_tree[11] = {};
   bool any_tree = false;
   bool tree_order[2] = {false, false};       // some tree pile of order 2, 4
+  unsigned tree_leaf_levels = 0;             // bit l: level l is some tree pile's finest
   int n_sph_blk = 0;
   // gravity tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
@@ -345,6 +346,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   b.any_grav = false;
   b.any_tree = false;
   b.tree_order[0] = b.tree_order[1] = false;
+  b.tree_leaf_levels = 0;
   b.all_soft = true;
   for (int p = 0; p < (int)b.members.size(); ++p) {
     const dem_sim* s = b.members[p];
@@ -356,6 +358,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       b.any_grav = true;
       b.any_tree = true;
       b.tree_order[h.tree_order == 4 ? 1 : 0] = true;
+      b.tree_leaf_levels |= 1u << h.bits;
       for (int l = 0; l <= h.bits; ++l)
         // the finest level: 256 nodes per block; above it eight lanes per node
         for (int64_t q = 0, step = l == h.bits ? kBlock : kBlock / 8; q < (int64_t(1) << (3 * l));
@@ -469,8 +472,8 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
       launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
     launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
-    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.wl_sph, b.n_sph_blk,
-                               b.tree_order);
+    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
+                               b.n_sph_blk, b.tree_order);
   }
   mark(12);
   launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);

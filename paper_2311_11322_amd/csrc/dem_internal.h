@@ -237,8 +237,10 @@ void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
                    ContactParams cp, int mode);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
 // any_order[0], [1]: some tree pile of multipole order 2, 4
+// leaf_levels: bit l set when level l is some pile's finest
 void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level,
-                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk, const bool* any_order);
+                 const int* n_level, unsigned leaf_levels, const WorkItem* wl_sph, int n_sph_blk,
+                 const bool* any_order);
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t n);
 void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem* items,
                  int n_items, uint32_t* item_sums, int max_seg_items);

@@ -127,21 +127,18 @@ __device__ __forceinline__ void store_node(const PileDev& P, size_t node, double
     o[0] = 0.0;
     return;
   }
-  double q[kMom];
-#pragma unroll
-  for (int u = 0; u < kMom; ++u) q[u] = 0.0;
-  q[0] = M;
-  q[1] = c[0];
-  q[2] = c[1];
-  q[3] = c[2];
-  q[4] = me1;
-  q[5] = me2;
-  traceless(raw, q);
-#pragma unroll
-  for (int u = 0; u < kMom; ++u) o[u] = q[u];
+  // stored as computed (the traceless parts straight to memory)
   double* r = P.traw + node * kRaw;
 #pragma unroll
   for (int u = 0; u < kRaw; ++u) r[u] = u < 31 ? raw[u] : 0.0;
+  o[0] = M;
+  o[1] = c[0];
+  o[2] = c[1];
+  o[3] = c[2];
+  o[4] = me1;
+  o[5] = me2;
+  traceless(raw, o);
+  o[37] = o[38] = o[39] = 0.0;
 }
 
 // Finest level: moments of node p from the cell's spheres.
@@ -255,21 +252,26 @@ __device__ void tree_up8(const PileDev& P, int l, uint32_t p, int o, bool valid)
 }
 
 // Finest level of a pile: one thread per node from its spheres (a block
-// covers 256 nodes).  Other levels: eight lanes per node from its children
-// (a block covers 32 nodes).
-__global__ __launch_bounds__(kBlock) void k_tree_level(const PileDev* __restrict__ piles,
-                                                       const WorkItem* __restrict__ wl, int l) {
+// covers 256 nodes).  A separate kernel from the levels above, whose eight
+// lanes per node need many more registers.
+__global__ __launch_bounds__(kBlock) void k_tree_leaf_level(const PileDev* __restrict__ piles,
+                                                            const WorkItem* __restrict__ wl, int l) {
   const WorkItem w = wl[blockIdx.x];
   const PileDev& P = piles[w.pile];
-  if (P.status != 0 || l > P.bits) return;
-  const uint32_t nl = 1u << (3 * l);
-  if (l == P.bits) {
-    const uint32_t p = (uint32_t)(w.base + threadIdx.x);
-    if (p < nl) tree_leaf(P, p);
-  } else {
-    const uint32_t p = (uint32_t)w.base + (threadIdx.x >> 3);
-    tree_up8(P, l, p, threadIdx.x & 7, p < nl);
-  }
+  if (P.status != 0 || l != P.bits) return;
+  const uint32_t p = (uint32_t)(w.base + threadIdx.x);
+  if (p < (1u << (3 * l))) tree_leaf(P, p);
+}
+
+// Levels below a pile's finest: eight lanes per node from its children (a
+// block covers 32 nodes).
+__global__ __launch_bounds__(kBlock) void k_tree_up_level(const PileDev* __restrict__ piles,
+                                                          const WorkItem* __restrict__ wl, int l) {
+  const WorkItem w = wl[blockIdx.x];
+  const PileDev& P = piles[w.pile];
+  if (P.status != 0 || l >= P.bits) return;
+  const uint32_t p = (uint32_t)w.base + (threadIdx.x >> 3);
+  tree_up8(P, l, p, threadIdx.x & 7, p < (1u << (3 * l)));
 }
 
 // Pull per unit mass at R = x - c of a node's moments q (uniform over the
@@ -646,10 +648,17 @@ __global__ __launch_bounds__(kBlock) void k_tree_combine(const PileDev* __restri
 }  // namespace
 
 void launch_tree(hipStream_t st, const PileDev* piles, WorkItem* const* wl_level,
-                 const int* n_level, const WorkItem* wl_sph, int n_sph_blk, const bool* any_order) {
-  for (int l = 10; l >= 0; --l)
-    if (n_level[l] > 0)
-      hipLaunchKernelGGL(k_tree_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles, wl_level[l], l);
+                 const int* n_level, unsigned leaf_levels, const WorkItem* wl_sph, int n_sph_blk,
+                 const bool* any_order) {
+  for (int l = 10; l >= 0; --l) {
+    if (n_level[l] <= 0) continue;
+    if (leaf_levels >> l & 1u)
+      hipLaunchKernelGGL(k_tree_leaf_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles,
+                         wl_level[l], l);
+    if ((leaf_levels >> (l + 1)) != 0u)   // some pile is deeper than l
+      hipLaunchKernelGGL(k_tree_up_level, dim3(n_level[l]), dim3(kBlock), 0, st, piles,
+                         wl_level[l], l);
+  }
   // four groups per work item, padded to a multiple of the XCD count
   const int walk_blocks = ((n_sph_blk * 4 + kXcds - 1) / kXcds) * kXcds * kTreeParts;
   hipLaunchKernelGGL(k_tree_boxes, dim3(n_sph_blk), dim3(kBlock), 0, st, piles, wl_sph);
