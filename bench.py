@@ -52,8 +52,8 @@ MEASURED_TRAFFIC = {
 # gravity source it was measured on.
 MEASURED_TREE_FLOP = {
     # (spheres, opening angle, leaf, order): (FLOP per launch, source_hash("kernels_tree.hip"))
-    (124958, 0.5, 32, 4): (3.665e10, "9bd8e9cc1c2c2a96"),
-    (999660, 0.5, 32, 4): (3.844e11, "9bd8e9cc1c2c2a96"),
+    (124958, 0.5, 32, 4): (3.665e10, "48139f1037f488a0"),
+    (999660, 0.5, 32, 4): (3.844e11, "48139f1037f488a0"),
 }
 
 
