@@ -157,3 +157,36 @@ def test_tree_and_direct_piles_in_one_engine(D):
         got = s.read_state(pairs=True)
         for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "sph_force"):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
+
+
+def test_tree_piles_of_different_depths_in_one_engine(D):
+    """Tree piles of 2 to 5 pyramid levels (and both orders, different
+    opening angles and leaves) batched with a direct-sum pile: a level is the
+    finest of one pile while others build it from their children, and every
+    pile's state equals its state alone, bit for bit."""
+    say("engine, tree piles of different depths")
+    specs = [(3, 0.5, 16, 4), (60, 0.6, 8, 2), (2500, 0.5, 32, 4), (400, 0.8, 64, 4)]
+    ws = [_tree(W.collapse_cloud(90 + k, n_agg=n, contact_seeded=True, spin_sigma=0.2), th, lf,
+                od) for k, (n, th, lf, od) in enumerate(specs)]
+    ws.append(W.collapse_cloud(95, n_agg=200, contact_seeded=True))
+    alone = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        s.step(3)
+        alone.append(s.read_state(pairs=True))
+        s.close()
+    eng = D.Engine(1 << 33)
+    sims = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.add_workload(w)
+        eng.attach(s)
+        sims.append(s)
+    assert eng.step(3) == D.DEM_OK
+    for s in list(eng.sims):
+        eng.detach(s)
+    for k, s in enumerate(sims):
+        got = s.read_state(pairs=True)
+        for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "sph_force"):
+            assert np.array_equal(got[f], alone[k][f]), (k, f)
