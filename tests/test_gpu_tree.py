@@ -190,3 +190,25 @@ def test_tree_piles_of_different_depths_in_one_engine(D):
         got = s.read_state(pairs=True)
         for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "sph_force"):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
+
+
+def test_tree_checkpoint_restore_bit_identical(D):
+    """A tree pile checkpointed after 3 steps and restored into a fresh
+    system continues exactly as the original."""
+    say("tree checkpoint/restore")
+    w = _tree(W.collapse_cloud(77, n_agg=300, contact_seeded=True, spin_sigma=0.3))
+    a = D.Sim(w.params)
+    a.add_workload(w)
+    a.step(3)
+    ck = a.checkpoint()
+    a.step(4)
+    ref = a.read_state(pairs=True)
+    b = D.Sim(w.params)
+    b.add_workload(w)
+    b.restore(ck)
+    b.step(4)
+    got = b.read_state(pairs=True)
+    for k in ("agg_pos", "agg_vel", "agg_acc", "agg_torque", "agg_quat", "pair_keys", "pair_hist",
+              "sph_force"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert got["step"] == ref["step"] == 7
