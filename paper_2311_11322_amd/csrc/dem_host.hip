@@ -248,6 +248,7 @@ struct Batch {
   int grav_tile[3] = {0, 0, 0};
   int n_grav_groups = 0;
   bool any_grav = false;
+  bool any_direct = false;                   // some pile with the exact sum
   bool all_soft = true;
   ScanSeg* seg_cells = nullptr;
   ScanItem* item_cells = nullptr;
@@ -344,6 +345,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   std::vector<ScanSeg> sc, sp;
   std::vector<ScanItem> ic, ip;
   b.any_grav = false;
+  b.any_direct = false;
   b.any_tree = false;
   b.tree_order[0] = b.tree_order[1] = false;
   b.tree_leaf_levels = 0;
@@ -366,6 +368,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
           wtree[l].push_back({p, (int32_t)q});
     } else if (h.G != 0.0) {
       b.any_grav = true;
+      b.any_direct = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
       // every tile pair (ti <= tj) of the pile: each unordered pair once
       int g = 0;
@@ -471,7 +474,7 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
     for (int g = 0; g < b.n_grav_groups; ++g)
       launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
-    launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    if (b.any_direct) launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
     if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
                                b.n_sph_blk, b.tree_order);
   }
