@@ -65,6 +65,25 @@ def test_box_fill_parity(D, shape):
         compare_states(sim, o, tol=1e-10)
 
 
+@pytest.mark.parametrize("gravity", ["direct", "tree"])
+def test_walled_box_with_self_gravity_parity(D, gravity):
+    """Walls, the uniform field and self-gravity in one pile (exact sum, or
+    the tree): the same bar as without gravity."""
+    say("walled box + self-gravity", gravity)
+    w = _small_box(shape="mixed", seed=9)
+    w.params.update(G=0.05)
+    if gravity == "tree":
+        w.params.update(gravity_tree=1, theta=0.5, tree_leaf=16, tree_order=4)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    sim.step(1)
+    o.step(1)
+    compare_states(sim, o)
+    sim.step(10)
+    o.step(10)
+    compare_states(sim, o, tol=1e-10)
+
+
 def test_box_fill_wall_contacts_form_and_break(D):
     """Aggregates dropped from just above the floor hit it and bounce: the
     wall contacts of the last step agree with the oracle throughout."""
