@@ -301,6 +301,23 @@ def test_invalid_input_rejected(D):
     assert ei.value.code == D.DEM_ERR_STATE
 
 
+def test_spin_up_parity(D):
+    """Spin-up forcing (the body-frame spin increment after the second kick,
+    Sec. 4.1) on the exact sum against the oracle: three steps within the
+    parity bar."""
+    say("direct + spin-up")
+    w = W.collapse_cloud(78, n_agg=300, contact_seeded=True, spin_sigma=0.1)
+    w.params["spin_dw"] = 1e-3
+    sim = D.Sim(w.params)
+    sim.add_workload(w)
+    sim.set_forcing(w.params["spin_dw"])
+    o = O.Oracle(w.params).add_workload(w)
+    compare_states(sim, o)
+    sim.step(3)
+    o.step(3)
+    compare_states(sim, o, tol=1e-10)
+
+
 def test_engine_alone_vs_mix_bit_identical(D):
     say("engine alone vs mix")
     piles = W.pile_batch(seed=3, n_piles=6, nmin=300, nmax=3000, n_steps=5)

@@ -212,3 +212,20 @@ def test_tree_checkpoint_restore_bit_identical(D):
               "sph_force"):
         assert np.array_equal(got[k], ref[k]), k
     assert got["step"] == ref["step"] == 7
+
+
+def test_tree_with_spin_up_parity(D):
+    """Spin-up forcing (the YORP-like ramp) on a tree pile against the
+    oracle: three steps within the parity bar."""
+    say("tree + spin-up")
+    w = _tree(W.collapse_cloud(78, n_agg=300, contact_seeded=True, spin_sigma=0.1))
+    w.params["spin_dw"] = 1e-3
+    sim = D.Sim(w.params)
+    sim.add_workload(w)
+    sim.set_forcing(w.params["spin_dw"])
+    o = O.Oracle(w.params).add_workload(w)
+    compare_states(sim, o)
+    sim.step(3)
+    o.step(3)
+    compare_states(sim, o, tol=1e-10)
+
