@@ -173,21 +173,21 @@ def test_lone_spheres_and_large_aggregate(D):
 # ---------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
-def cfg1():
+def collapse125k():
     return W.collapse_cloud(1, n_agg=25000)
 
 
-def test_full_size_initial_forces_sampled(D, cfg1):
+def test_full_size_initial_forces_sampled(D, collapse125k):
     """At 125k spheres in the benchmark's launch configuration: the t0 force
     on 192 sampled spheres equals the oracle's one-sphere-at-a-time
     evaluation (contacts by brute force, direct-sum gravity)."""
-    say("full size sampled", cfg1.n_sph)
-    sim = D.Sim(cfg1.params)
-    sim.add_workload(cfg1)
+    say("full size sampled", collapse125k.n_sph)
+    sim = D.Sim(collapse125k.params)
+    sim.add_workload(collapse125k)
     g = sim.read_state(["sph_force", "sph_torque"])
-    o = O.Oracle(cfg1.params).add_workload(cfg1, evaluate=False)
+    o = O.Oracle(collapse125k.params).add_workload(collapse125k, evaluate=False)
     rng = np.random.default_rng(9)
-    idx = np.sort(rng.choice(cfg1.n_sph, 192, replace=False))
+    idx = np.sort(rng.choice(collapse125k.n_sph, 192, replace=False))
     F, T = o.eval_subset(idx)
     assert rel_err(g["sph_force"][idx], F) <= 1e-12
     assert np.abs(g["sph_torque"][idx] - T).max() <= 1e-12 * max(np.abs(F).max(), 1.0)
@@ -198,7 +198,7 @@ def test_full_size_initial_forces_sampled(D, cfg1):
     a1 = sim.read_state(["agg_vel", "agg_mass", "agg_acc"])
     P1 = (a1["agg_mass"][:, None] * a1["agg_vel"]).sum(0)
     Fscale = (a1["agg_mass"][:, None] * np.abs(a1["agg_acc"])).sum()
-    assert np.abs(P1 - P0).max() <= 1e-12 * Fscale * 2 * cfg1.params["dt"]
+    assert np.abs(P1 - P0).max() <= 1e-12 * Fscale * 2 * collapse125k.params["dt"]
 
 
 # ---------------------------------------------------------------------------
