@@ -32,9 +32,16 @@ __device__ __forceinline__ double ror1(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Series coefficients of the rsqrt correction, read from memory so that the
-// compiler keeps them in registers instead of re-materialising literals.
-__constant__ double kSeries[2] = {1.5, 1.875};
+// Series coefficients of the rsqrt correction, held in VGPRs for the whole
+// kernel.  Left as literals, the compiler re-materialises 1.5 into the
+// accumulator of a two-operand FMA at every use (a VOP3 FMA takes no 64-bit
+// literal): one extra move per pair.  The empty asm statement only hides the
+// values from constant folding; it emits no instruction.
+__device__ __forceinline__ void series_coeffs(double& c15, double& c1875) {
+  c15 = 1.5;
+  c1875 = 1.875;
+  asm("" : "+v"(c15), "+v"(c1875));
+}
 
 // r^-3 of a softened squared distance, FP64.
 template <bool SOFT>

@@ -81,7 +81,8 @@ __global__ __launch_bounds__(64) void k_grav_tiles(const PileDev* __restrict__ p
   const int i0 = it.ti * B, j0 = it.tj * B;
   const int j1 = min(j0 + B, ns);
   const bool diag = it.ti == it.tj;
-  const double c15 = kSeries[0], c1875 = kSeries[1];
+  double c15, c1875;
+  series_coeffs(c15, c1875);
 
   // tile-pair anchor offset (FP32 form): d = (x_j - A_J) - ((x_i - A_I) - (A_J - A_I))
   T sx = 0, sy = 0, sz = 0;

@@ -501,7 +501,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(const PileDev* __restrict__ pi
   const double bmin[3] = {box[0], box[1], box[2]};
   const double bmax[3] = {box[3], box[4], box[5]};
   double acc[3] = {0.0, 0.0, 0.0};
-  const double c15 = kSeries[0], c1875 = kSeries[1];
+  double c15, c1875;
+  series_coeffs(c15, c1875);
   int sp = 0;
   {
     // the root is never accepted (the group lies inside it and theta <= 1);
