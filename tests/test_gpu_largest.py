@@ -1,0 +1,85 @@
+"""The largest single-system workload the benchmark times: the collapse of
+100,000 aggregates of 2-8 spheres (499,762 spheres), seed 2, in the plain
+FP64 form, the FP32-force form and with tree gravity.  At this size the
+oracle evaluates sampled spheres one at a time (brute-force contacts and the
+exact direct sum over all 499,762 sources).  Needs an MI355X.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_11322_amd import workloads as W
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_2311_11322_amd import dem
+    dem.lib()
+    return dem
+
+
+@pytest.fixture(scope="module")
+def collapse500k():
+    return W.collapse_cloud(2, n_agg=100000)
+
+
+@pytest.fixture(scope="module")
+def sampled(collapse500k):
+    """Oracle force and torque on 192 sampled spheres at t0."""
+    w = collapse500k
+    idx = np.sort(np.random.default_rng(11).choice(w.n_sph, 192, replace=False))
+    o = O.Oracle(w.params).add_workload(w, evaluate=False)
+    F, T = o.eval_subset(idx)
+    return idx, F, T
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _forces(D, w, params, precision):
+    sim = D.Sim(params, precision=precision)
+    sim.add_workload(w)
+    g = sim.read_state(["sph_force", "sph_torque"])
+    sim.close()
+    return g["sph_force"], g["sph_torque"]
+
+
+def test_largest_collapse_fp64_sampled(D, collapse500k, sampled):
+    w = collapse500k
+    say("largest collapse, plain FP64", w.n_sph)
+    idx, F, T = sampled
+    g, t = _forces(D, w, w.params, D.PREC_FP64)
+    assert rel_err(g[idx], F) <= 1e-12
+    assert np.abs(t[idx] - T).max() <= 1e-12 * max(np.abs(F).max(), 1.0)
+
+
+def test_largest_collapse_fp32_force_sampled(D, collapse500k, sampled):
+    """FP32 pair arithmetic on tile-relative coordinates with FP64 sums:
+    within the FP32-force bar (1e-5, max norm) at 500k sources per sphere."""
+    w = collapse500k
+    say("largest collapse, FP32-force", w.n_sph)
+    idx, F, T = sampled
+    g, _ = _forces(D, w, w.params, D.PREC_FP32_FORCE)
+    err = rel_err(g[idx], F)
+    print("FP32-force max-norm error", err)
+    assert err <= 1e-5
+
+
+def test_largest_collapse_tree_sampled(D, collapse500k, sampled):
+    """Tree gravity (hexadecapole order, opening angle 0.5, leaves of 32):
+    the difference from the exact sum is the tree's truncation error."""
+    w = collapse500k
+    say("largest collapse, tree", w.n_sph)
+    idx, F, T = sampled
+    prm = dict(w.params, gravity_tree=1, theta=0.5, tree_leaf=32, tree_order=4)
+    g, _ = _forces(D, w, prm, D.PREC_FP64)
+    err = np.linalg.norm(g[idx] - F, axis=1) / np.linalg.norm(F, axis=1)
+    print("tree relative error: max", err.max(), "rms", np.sqrt((err ** 2).mean()))
+    assert np.sqrt((err ** 2).mean()) < 1e-4 and err.max() < 1e-3
