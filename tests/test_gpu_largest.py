@@ -1,9 +1,16 @@
-"""The largest single-system workload the benchmark times: the collapse of
-100,000 aggregates of 2-8 spheres (499,762 spheres), seed 2, in the plain
-FP64 form, the FP32-force form and with tree gravity.  At this size the
-oracle evaluates sampled spheres one at a time (brute-force contacts and the
-exact direct sum over all 499,762 sources).  Needs an MI355X.
+"""The largest workloads the benchmark times.
+
+* The collapse of 100,000 aggregates of 2-8 spheres (499,762 spheres),
+  seed 2, in the plain FP64 form, the FP32-force form and with tree gravity.
+  At this size the oracle evaluates sampled spheres one at a time
+  (brute-force contacts and the exact direct sum over all sources).
+* The 256 spin-up piles (1.31M spheres) in one engine, FP32-force, with the
+  tuning the benchmark's autotuner picks; after one batched step, four piles
+  from the smallest to the largest are checked against the oracle's own step.
+
+Needs an MI355X.
 """
+import os
 import sys
 
 import numpy as np
@@ -83,3 +90,37 @@ def test_largest_collapse_tree_sampled(D, collapse500k, sampled):
     err = np.linalg.norm(g[idx] - F, axis=1) / np.linalg.norm(F, axis=1)
     print("tree relative error: max", err.max(), "rms", np.sqrt((err ** 2).mean()))
     assert np.sqrt((err ** 2).mean()) < 1e-4 and err.max() < 1e-3
+
+
+@pytest.fixture(scope="module")
+def piles256():
+    return W.pile_batch(seed=3, n_piles=256, workers=min(16, len(os.sched_getaffinity(0))))
+
+
+def test_batched_256_piles_sampled(D, piles256):
+    from paper_2311_11322_amd import serve
+    piles = piles256
+    say("256 piles in one engine, FP32-force", sum(p.n_sph for p in piles))
+    sims = [serve.make_sim(p, D.PREC_FP32_FORCE, tuning=(512, 1.0)) for p in piles]
+    eng = D.Engine(1 << 36)
+    for s in sims:
+        eng.attach(s)
+    assert eng.step(1) == D.DEM_OK
+    for s in sims:
+        eng.detach(s)
+    eng.close()
+    order = np.argsort([p.n_sph for p in piles], kind="stable")
+    for k in (order[0], order[len(order) // 3], order[2 * len(order) // 3], order[-1]):
+        p = piles[k]
+        say("pile", int(k), p.n_sph)
+        o = O.Oracle(p.params).add_workload(p)
+        o.step(1)
+        g = sims[k].read_state(["sph_force", "agg_pos", "sph_pos"], pairs=True)
+        op = o.pairs()
+        keys = (op["i"].astype(np.uint64) << np.uint64(32)) | op["j"].astype(np.uint64)
+        assert np.array_equal(g["pair_keys"], keys), k
+        assert rel_err(g["sph_force"], o.spheres()["F"]) <= 1e-5, k
+        assert rel_err(g["agg_pos"], o.aggregates()["rA"]) <= 1e-12, k
+        assert rel_err(g["sph_pos"], o.spheres()["r"]) <= 1e-12, k
+    for s in sims:
+        s.close()
