@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--fill-steps", type=int, default=10000,
                     help="steps of the box-filling runs (the paper profiles 10^4)")
     ap.add_argument("--box-batch", type=int, default=64, help="box fills batched in one engine")
-    ap.add_argument("--only", choices=["contact_path", "walled"], default=None,
+    ap.add_argument("--only", choices=["contact_path", "walled", "batched"], default=None,
                     help="run only this section and print its result (for profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
@@ -156,10 +156,13 @@ def main():
     if args.only:
         dem.lib()
         part = {}
+        workers = min(16, len(os.sched_getaffinity(0)))
         if args.only == "contact_path":
             contact_path_run(args, part)
+        elif args.only == "batched":
+            batched_run(args, part, workers, plain=False)
         else:
-            walled_runs(args, part, min(16, len(os.sched_getaffinity(0))))
+            walled_runs(args, part, workers)
         print(json.dumps(part), flush=True)
         return
 
@@ -434,6 +437,52 @@ def big_run(args, out, wbig):
     log(f"tree 500k: {out['tree_500k']}")
 
 
+def batched_run(args, out, workers, plain=True):
+    """The spin-up piles in one engine, FP32-force, with the tuning the
+    autotuner picks (or, for a profiler run of this section alone, the
+    --gravity-tile / --cell-scale given); with ``plain``, also the same piles
+    in plain FP64 one at a time.  Returns the tuning."""
+    from paper_2311_11322_amd import dem, serve
+    from paper_2311_11322_amd import workloads as W
+    t = time.time()
+    piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)
+    n_tot = sum(p.n_sph for p in piles)
+    log(f"{len(piles)} piles, {n_tot} spheres ({time.time() - t:.1f} s to place)")
+    if not plain and args.gravity_tile:
+        tune = {"gravity_tile": args.gravity_tile, "cell_scale": args.cell_scale}
+    else:
+        tune = serve.autotune(piles, dem.PREC_FP32_FORCE, steps=3)
+    log(f"tuning: tile {tune['gravity_tile']}, cell scale {tune['cell_scale']}")
+    bsteps = max(5, args.steps // 2)
+    batch = serve.run_batch(piles, bsteps, dem.PREC_FP32_FORCE,
+                            tuning=(tune["gravity_tile"], tune["cell_scale"]), warmup=2)
+    for s in batch["sims"]:
+        s.close()
+    out["batched"] = {
+        "workload": f"{len(piles)} independent spin-up piles, 500-20000 spheres each "
+                    f"(log-uniform), {n_tot} spheres, FP32-force, one engine",
+        "value": round(batch["sphere_steps_per_s"], 1), "unit": "sphere-steps/s",
+        "ms_per_step": round(batch["ms_per_step"], 4),
+        "gravity_pairs_per_step": batch["sum_n2"],
+        "tuning": {"gravity_tile": tune["gravity_tile"], "cell_scale": tune["cell_scale"]}}
+    if plain:
+        # the same piles, FP64, one at a time
+        plain_time = 0.0
+        for p in piles:
+            sp = dem.Sim(p.params)
+            sp.add_workload(p)
+            sp.set_forcing(p.params["spin_dw"])
+            sp.step(1)
+            plain_time += timed_steps(sp, bsteps)
+            sp.close()
+        plain_value = n_tot * bsteps / plain_time
+        out["batched"].update(
+            plain_fp64_one_pile_at_a_time=round(plain_value, 1),
+            speedup_vs_plain=round(batch["sphere_steps_per_s"] / plain_value, 2))
+    log(f"batched: {out['batched']}")
+    return tune
+
+
 def extra_runs(args, w, out, prec):
     """The FP32-force form on the same collapse, the batched spin-up piles
     (plain FP64 one pile at a time vs FP32-force batched in one engine) and
@@ -489,38 +538,7 @@ def extra_runs(args, w, out, prec):
         "speedup": round(abl[1][0] / abl[0][0], 3)}
     log(f"member search ablation: {out['member_search_ablation']}")
     walled_runs(args, out, workers)
-    # -- batched spin-up piles
-    t = time.time()
-    piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)
-    n_tot = sum(p.n_sph for p in piles)
-    log(f"{len(piles)} piles, {n_tot} spheres ({time.time() - t:.1f} s to place)")
-    tune = serve.autotune(piles, dem.PREC_FP32_FORCE, steps=3)
-    log(f"autotuned: tile {tune['gravity_tile']}, cell scale {tune['cell_scale']}")
-    bsteps = max(5, args.steps // 2)
-    batch = serve.run_batch(piles, bsteps, dem.PREC_FP32_FORCE,
-                            tuning=(tune["gravity_tile"], tune["cell_scale"]), warmup=2)
-    for s in batch["sims"]:
-        s.close()
-    # plain: the same piles, FP64, one at a time
-    plain_time = 0.0
-    for p in piles:
-        sp = dem.Sim(p.params)
-        sp.add_workload(p)
-        sp.set_forcing(p.params["spin_dw"])
-        sp.step(1)
-        plain_time += timed_steps(sp, bsteps)
-        sp.close()
-    plain_value = n_tot * bsteps / plain_time
-    out["batched"] = {
-        "workload": f"{len(piles)} independent spin-up piles, 500-20000 spheres each "
-                    f"(log-uniform), {n_tot} spheres, FP32-force, one engine",
-        "value": round(batch["sphere_steps_per_s"], 1), "unit": "sphere-steps/s",
-        "ms_per_step": round(batch["ms_per_step"], 4),
-        "gravity_pairs_per_step": batch["sum_n2"],
-        "tuning": {"gravity_tile": tune["gravity_tile"], "cell_scale": tune["cell_scale"]},
-        "plain_fp64_one_pile_at_a_time": round(plain_value, 1),
-        "speedup_vs_plain": round(batch["sphere_steps_per_s"] / plain_value, 2)}
-    log(f"batched: {out['batched']}")
+    tune = batched_run(args, out, workers)
     # -- served stream
     if args.requests > 0:
         t = time.time()

@@ -491,39 +491,93 @@ __global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ p
   }
 }
 
+// One member's share of F_A and N_A: f_i and (R b_i) x f_i + tau_i.
+__device__ __forceinline__ void add_member(const double R[9], const double f[3],
+                                           const double bb[3], const double tau[3], double FA[3],
+                                           double NA[3]) {
+  double d[3], dxf[3];
+  rot_apply(R, bb, d);
+  cross3(d, f, dxf);
+  for (int k = 0; k < 3; ++k) {
+    FA[k] += f[k];
+    NA[k] += dxf[k] + tau[k];
+  }
+}
+
 // One thread per aggregate: F_A = sum F_i, a_A = F_A / M + g,
 // N_A = sum [ (R b_i) x F_i + tau_i ] over the members in order, and in step
 // mode v_A += h/2 a_A followed by the spin-up increment about +z through the
-// pile's centre.
+// pile's centre.  A wave's 64 aggregates own one contiguous run of spheres;
+// the run passes through the wave's LDS slice 64 spheres at a time (one
+// coalesced load per array), and each lane adds the members that fall in the
+// slice, in member order.  (Read straight from memory, lanes ~5 spheres
+// apart re-fetch each line once per member: the lines leave L2 between a
+// wave's member iterations.)
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl,
                                                    ContactParams cp, int mode) {
+  __shared__ double sh_all[kBlock / 64][9][64];
   const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
-  const int A = w.base + threadIdx.x;
-  if (A >= P.na || P.status != 0) return;
   const int na = P.na, ns = P.ns, nxt = P.parity ^ 1;
-  double q[4], R[9];
-  for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
-  quat_rot(q, R);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a0 = w.base + wv * 64;               // the wave's first aggregate
+  if (a0 >= na || P.status != 0) return;         // uniform over the wave
+  const int A = a0 + lane;
+  const bool own = A < na;
+  double (*sh)[64] = sh_all[wv];
+  double R[9];
+  if (own) {
+    double q[4];
+    for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
+    quat_rot(q, R);
+  }
   double FA[3] = {0.0, 0.0, 0.0}, NA[3] = {0.0, 0.0, 0.0};
-  // members: the contiguous segment, or (ablation of the paper's original
-  // routines) every sphere of the pile tested for membership in order
-  const bool scan = P.member_scan != 0;
-  const int i_lo = scan ? 0 : P.first[A];
-  const int i_hi = scan ? ns : P.first[A] + P.count[A];
-  for (int i = i_lo; i < i_hi; ++i) {
-    if (scan && P.agg[i] != A) continue;
-    const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
-    const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
-    double d[3], dxf[3];
-    rot_apply(R, bb, d);
-    cross3(d, f, dxf);
-    for (int k = 0; k < 3; ++k) {
-      FA[k] += f[k];
-      NA[k] += dxf[k] + P.tau[k * ns + i];
+  if (P.member_scan != 0) {
+    // ablation of the paper's original routines: every sphere of the pile
+    // tested for membership, in order
+    if (own)
+      for (int i = 0; i < ns; ++i) {
+        if (P.agg[i] != A) continue;
+        const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
+        const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
+        const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
+        add_member(R, f, bb, tau, FA, NA);
+      }
+  } else {
+    const int a_last = min(a0 + 64, na) - 1;
+    const int s0 = P.first[a0], s1 = P.first[a_last] + P.count[a_last];
+    const int m0 = own ? P.first[A] : 0, m1 = own ? m0 + P.count[A] : 0;
+    for (int c0 = s0; c0 < s1; c0 += 64) {
+      const int t = c0 + lane;
+      if (t < s1) {
+        // all nine loads in flight before the first LDS store (the stores
+        // would otherwise order the generic loads behind them)
+        double v[9];
+        for (int k = 0; k < 3; ++k) {
+          v[k] = P.F[k * ns + t];
+          v[3 + k] = P.b[k * ns + t];
+          v[6 + k] = P.tau[k * ns + t];
+        }
+        for (int k = 0; k < 9; ++k) sh[k][lane] = v[k];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = max(m0, c0), i1 = min(m1, c0 + 64); i < i1; ++i) {
+        const int l = i - c0;
+        const double f[3] = {sh[0][l], sh[1][l], sh[2][l]};
+        const double bb[3] = {sh[3][l], sh[4][l], sh[5][l]};
+        const double tau[3] = {sh[6][l], sh[7][l], sh[8][l]};
+        add_member(R, f, bb, tau, FA, NA);
+      }
+      // every lane has read the slice before the next pass overwrites it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+  if (!own) return;
   const double M = P.M[A];
   double a[3];
   for (int k = 0; k < 3; ++k) {

@@ -35,18 +35,61 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* total)
   return before + x - v;
 }
 
+// One thread's kScanItems consecutive elements: two 16-byte accesses when the
+// run lies inside the segment and the array is 16-byte aligned, else one
+// guarded access per element (zeros past the end).
+static_assert(kScanItems == 8, "runs are read as two 16-byte vectors");
+
+__device__ __forceinline__ bool whole_run(const void* p, int64_t base, int64_t n) {
+  return base + kScanItems <= n && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+__device__ __forceinline__ void load_run(const uint32_t* __restrict__ in, int64_t base, int64_t n,
+                                         uint32_t v[kScanItems]) {
+  if (whole_run(in, base, n)) {
+    const uint4 a = *reinterpret_cast<const uint4*>(in + base);
+    const uint4 b = *reinterpret_cast<const uint4*>(in + base + 4);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+    v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = base + k < n ? in[base + k] : 0u;
+  }
+}
+
+__device__ __forceinline__ void store_run(uint32_t* __restrict__ out, int64_t base, int64_t n,
+                                          const uint32_t r[kScanItems]) {
+  if (whole_run(out, base, n)) {
+    *reinterpret_cast<uint4*>(out + base) = make_uint4(r[0], r[1], r[2], r[3]);
+    *reinterpret_cast<uint4*>(out + base + 4) = make_uint4(r[4], r[5], r[6], r[7]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < n) out[base + k] = r[k];
+  }
+}
+
+// Exclusive prefix of a run, starting from run0.
+__device__ __forceinline__ void run_prefix(const uint32_t v[kScanItems], uint32_t run0,
+                                           uint32_t r[kScanItems]) {
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    r[k] = run0;
+    run0 += v[k];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const ScanSeg* __restrict__ segs,
                                                         const ScanItem* __restrict__ items,
                                                         uint32_t* __restrict__ sums) {
   const ScanItem it = items[blockIdx.x];
   const ScanSeg sg = segs[it.seg];
   const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  load_run(sg.in, base, sg.n, v);
   uint32_t acc = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
-    if (e < sg.n) acc += sg.in[e];
-  }
+  for (int k = 0; k < kScanItems; ++k) acc += v[k];
   uint32_t total;
   block_exclusive(acc, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
@@ -79,22 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict_
   const ScanSeg sg = segs[it.seg];
   uint32_t* __restrict__ out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
   const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
+  uint32_t v[kScanItems], r[kScanItems];
+  load_run(sg.in, base, sg.n, v);
   uint32_t acc = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
-    v[k] = e < sg.n ? sg.in[e] : 0u;
-    acc += v[k];
-  }
+  for (int k = 0; k < kScanItems; ++k) acc += v[k];
   uint32_t total;
-  uint32_t run = block_exclusive(acc, &total) + sums[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
-    if (e < sg.n) out[e] = run;
-    run += v[k];
-  }
+  run_prefix(v, block_exclusive(acc, &total) + sums[blockIdx.x], r);
+  store_run(out, base, sg.n, r);
 }
 
 // One block per segment scans the whole segment chunk by chunk, carrying the
@@ -105,22 +140,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_single(const ScanSeg* __restric
   uint32_t carry = 0;
   for (int c = 0; c < sg.n_items; ++c) {
     const int64_t base = (int64_t)c * kScanChunk + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
+    uint32_t v[kScanItems], r[kScanItems];
+    load_run(sg.in, base, sg.n, v);
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t e = base + k;
-      v[k] = e < sg.n ? sg.in[e] : 0u;
-      acc += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) acc += v[k];
     uint32_t total;
-    uint32_t run = block_exclusive(acc, &total) + carry;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t e = base + k;
-      if (e < sg.n) out[e] = run;
-      run += v[k];
-    }
+    run_prefix(v, block_exclusive(acc, &total) + carry, r);
+    store_run(out, base, sg.n, r);
     carry += total;
   }
   if (threadIdx.x == 0) out[sg.n] = carry;
