@@ -249,6 +249,7 @@ struct Batch {
   int n_grav_groups = 0;
   bool any_grav = false;
   bool any_direct = false;                   // some pile with the exact sum
+  bool reduce_stage = false;                 // member reduction through LDS
   bool all_soft = true;
   ScanSeg* seg_cells = nullptr;
   ScanItem* item_cells = nullptr;
@@ -350,10 +351,12 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   b.tree_order[0] = b.tree_order[1] = false;
   b.tree_leaf_levels = 0;
   b.all_soft = true;
+  int64_t tot_na = 0;
   for (int p = 0; p < (int)b.members.size(); ++p) {
     const dem_sim* s = b.members[p];
     const PileDev& h = s->h;
     for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
+    tot_na += h.na;
     for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
     for (int k = 0; k < h.n_big; ++k) wbig.push_back({p, k});
     if (h.G != 0.0 && h.tree) {
@@ -419,6 +422,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   HIPCHK(errsim, upload(b, &b.sums_cells, zc, st));
   HIPCHK(errsim, upload(b, &b.sums_pairs, zp, st));
   b.n_agg_blk = (int)wa.size();
+  b.reduce_stage = tot_na >= kReduceStageMin;
   b.n_sph_blk = (int)wsph.size();
   b.max_items_cells = b.max_items_pairs = 0;
   for (const ScanSeg& g : sc) b.max_items_cells = std::max(b.max_items_cells, (int)g.n_items);
@@ -481,7 +485,7 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
   mark(12);
   launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
   mark(13);
-  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
+  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode, b.reduce_stage);
   mark(14);
   launch_finish(st, b.d_table, np, mode, b.cp.dt);
   mark(15);

@@ -233,8 +233,12 @@ void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem
 // Supported tile sizes for a precision (default first); returns the count.
 int gravity_tiles(int precision, int* tiles);
 void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
+// Aggregates in one launch from which the member reduction stages its
+// members through LDS (below it, direct member reads are faster: few waves,
+// and the members stay in L2 between a wave's member iterations).
+constexpr int64_t kReduceStageMin = 131072;
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
-                   ContactParams cp, int mode);
+                   ContactParams cp, int mode, bool stage);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);
 // any_order[0], [1]: some tree pile of multipole order 2, 4
 // leaf_levels: bit l set when level l is some pile's finest

@@ -507,15 +507,17 @@ __device__ __forceinline__ void add_member(const double R[9], const double f[3],
 // One thread per aggregate: F_A = sum F_i, a_A = F_A / M + g,
 // N_A = sum [ (R b_i) x F_i + tau_i ] over the members in order, and in step
 // mode v_A += h/2 a_A followed by the spin-up increment about +z through the
-// pile's centre.  A wave's 64 aggregates own one contiguous run of spheres;
-// the run passes through the wave's LDS slice 64 spheres at a time (one
-// coalesced load per array), and each lane adds the members that fall in the
-// slice, in member order.  (Read straight from memory, lanes ~5 spheres
-// apart re-fetch each line once per member: the lines leave L2 between a
-// wave's member iterations.)
+// pile's centre.  Members are added in member order, read in one of two
+// ways with the same arithmetic:
+// * direct (launches of few aggregates): each lane reads its members;
+// * staged (many aggregates): lanes ~5 spheres apart would re-fetch each
+//   line once per member, the lines leaving L2 between a wave's member
+//   iterations, so a wave's 64 aggregates -- one contiguous run of
+//   spheres -- pass through the wave's LDS slice 64 spheres at a time (one
+//   coalesced load per array) and each lane adds the members in the slice.
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl,
-                                                   ContactParams cp, int mode) {
+                                                   ContactParams cp, int mode, int stage) {
   __shared__ double sh_all[kBlock / 64][9][64];
   const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
   const PileDev& P = piles[w.pile];
@@ -544,23 +546,38 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
         const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
         add_member(R, f, bb, tau, FA, NA);
       }
+  } else if (!stage) {
+    if (own)
+      for (int i = P.first[A], i1 = i + P.count[A]; i < i1; ++i) {
+        const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
+        const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
+        const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
+        add_member(R, f, bb, tau, FA, NA);
+      }
   } else {
     const int a_last = min(a0 + 64, na) - 1;
     const int s0 = P.first[a0], s1 = P.first[a_last] + P.count[a_last];
     const int m0 = own ? P.first[A] : 0, m1 = own ? m0 + P.count[A] : 0;
-    for (int c0 = s0; c0 < s1; c0 += 64) {
-      const int t = c0 + lane;
-      if (t < s1) {
-        // all nine loads in flight before the first LDS store (the stores
-        // would otherwise order the generic loads behind them)
-        double v[9];
+    // Loads through the global address space: a generic load would also
+    // count against the LDS wait counter that the slice reads wait on.  The
+    // next slice's nine loads are in flight while the lanes add this one.
+    typedef const __attribute__((address_space(1))) double* GlobalD;
+    const GlobalD gF = (GlobalD)P.F, gb = (GlobalD)P.b, gt = (GlobalD)P.tau;
+    double v[9];
+    auto fetch = [&](int c) {
+      const int t = c + lane;
+      if (t < s1)
         for (int k = 0; k < 3; ++k) {
-          v[k] = P.F[k * ns + t];
-          v[3 + k] = P.b[k * ns + t];
-          v[6 + k] = P.tau[k * ns + t];
+          v[k] = gF[k * ns + t];
+          v[3 + k] = gb[k * ns + t];
+          v[6 + k] = gt[k * ns + t];
         }
+    };
+    fetch(s0);
+    for (int c0 = s0; c0 < s1; c0 += 64) {
+      if (c0 + lane < s1)
         for (int k = 0; k < 9; ++k) sh[k][lane] = v[k];
-      }
+      if (c0 + 64 < s1) fetch(c0 + 64);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -666,8 +683,8 @@ void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int
 }
 
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
-                   ContactParams cp, int mode) {
-  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode);
+                   ContactParams cp, int mode, bool stage) {
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kBlock), 0, st, piles, wl, cp, mode, (int)stage);
 }
 
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt) {

@@ -6,7 +6,10 @@
   (brute-force contacts and the exact direct sum over all sources).
 * The 256 spin-up piles (1.31M spheres) in one engine, FP32-force, with the
   tuning the benchmark's autotuner picks; after one batched step, four piles
-  from the smallest to the largest are checked against the oracle's own step.
+  from the smallest to the largest are checked against the oracle's own step
+  and against their own run alone, bit for bit (the batch is large enough
+  for the member reduction to stage its members through LDS; a pile alone
+  reads them directly).
 
 Needs an MI355X.
 """
@@ -122,5 +125,13 @@ def test_batched_256_piles_sampled(D, piles256):
         assert rel_err(g["sph_force"], o.spheres()["F"]) <= 1e-5, k
         assert rel_err(g["agg_pos"], o.aggregates()["rA"]) <= 1e-12, k
         assert rel_err(g["sph_pos"], o.spheres()["r"]) <= 1e-12, k
+        alone = serve.make_sim(p, D.PREC_FP32_FORCE, tuning=(512, 1.0))
+        alone.step(1)
+        ga = alone.read_state(pairs=True)
+        gb = sims[k].read_state(pairs=True)
+        alone.close()
+        for f in ("agg_pos", "agg_vel", "agg_quat", "agg_spin", "agg_acc", "agg_torque",
+                  "pair_keys", "pair_hist", "sph_force", "sph_torque"):
+            assert np.array_equal(ga[f], gb[f]), (k, f)
     for s in sims:
         s.close()
