@@ -202,6 +202,18 @@ def main():
     torch.cuda.synchronize()
     graph_value = w.n_sph * args.steps / (time.perf_counter() - g0)
 
+    # per-step latency over repeated single steps (outside the timed region)
+    lat = []
+    for _ in range(max(50, args.steps)):
+        s0 = time.perf_counter()
+        sim.step(1)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - s0))
+    lat.sort()
+    step_latency = {"p50_ms": round(lat[len(lat) // 2], 4),
+                    "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+                    "steps": len(lat)}
+
     n = w.n_sph
     grav_ms = prof["gravity"] / prof["_steps"]
     flop = GRAVITY_FLOP_PER_PAIR * n * (n - 1)
@@ -240,6 +252,7 @@ def main():
                                   if args.gravity == "tree" else ""),
                    "n_spheres": w.n_sph, "n_aggregates": w.n_agg, "contacts": state["n_pairs"]},
         "graph_replay_value": round(graph_value, 1),
+        "step_latency": step_latency,
         "kernel_ms_per_step": per_kernel,
         "roofline": roofline,
     }
