@@ -247,6 +247,12 @@ typedef struct {
                                   full scan of the sphere list, as the paper's original
                                   routines did (Sec. 3.1); 0: contiguous member segments
                                   (the paper's improvement).  Same results, different cost. */
+    int32_t member_read;       /* how the member segments are read (member_scan 0):
+                                  0 automatic -- staged through LDS, a wave's run of spheres
+                                  at a time, in launches of at least 131,072 aggregates,
+                                  else each aggregate's members directly; 1 directly;
+                                  2 staged.  Same order and arithmetic, so the same
+                                  results; different cost. */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them

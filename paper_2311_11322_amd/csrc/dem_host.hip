@@ -285,7 +285,7 @@ struct dem_sim {
   dem_engine* engine = nullptr;
   int engine_slot = -1;
   dem_status last_status = DEM_OK;
-  dem_tuning tune{0, 1.0, 0};
+  dem_tuning tune{0, 1.0, 0, 0};
   // per-kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -605,6 +605,7 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.bits = choose_bits(ns);
   h.periodic = s->prm.periodic ? 1 : 0;
   h.member_scan = s->tune.member_scan;
+  h.member_read = s->tune.member_read;
   h.g_tile = (int32_t)s->sz.g_tile;
   h.g_nt = (int32_t)s->sz.g_nt;
   h.n_rblk = (int32_t)s->sz.n_rblk;
@@ -1186,6 +1187,8 @@ dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
     return fail(s, DEM_ERR_INVALID_ARG, "cell_scale must be finite and >= 1");
   if (t->member_scan != 0 && t->member_scan != 1)
     return fail(s, DEM_ERR_INVALID_ARG, "member_scan must be 0 or 1");
+  if (t->member_read < 0 || t->member_read > 2)
+    return fail(s, DEM_ERR_INVALID_ARG, "member_read must be 0, 1 or 2");
   s->tune = *t;
   return DEM_OK;
 }

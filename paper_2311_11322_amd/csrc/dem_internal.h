@@ -76,7 +76,7 @@ struct PileDev {
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
   int32_t n_periodic;        // cells per axis of a periodic pile
   int32_t member_scan;       // 1: reduction finds members by scanning all spheres
-  int32_t pad2;
+  int32_t member_read;       // 0 automatic, 1 direct, 2 staged through LDS
   double box;                // periodic cube side
   double G, soft_frac, spin_dw;
   double cell_min;           // cell side lower bound: largest diameter of the non-big spheres

@@ -515,6 +515,8 @@ __device__ __forceinline__ void add_member(const double R[9], const double f[3],
 //   iterations, so a wave's 64 aggregates -- one contiguous run of
 //   spheres -- pass through the wave's LDS slice 64 spheres at a time (one
 //   coalesced load per array) and each lane adds the members in the slice.
+// The launch chooses (stage: at least kReduceStageMin aggregates) unless the
+// pile's tuning fixes one way.
 __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl,
                                                    ContactParams cp, int mode, int stage) {
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
         const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
         add_member(R, f, bb, tau, FA, NA);
       }
-  } else if (!stage) {
+  } else if (P.member_read == 1 || (P.member_read == 0 && !stage)) {
     if (own)
       for (int i = P.first[A], i1 = i + P.count[A]; i < i1; ++i) {
         const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};

@@ -293,6 +293,10 @@ def test_invalid_input_rejected(D):
     bad = w.pos.copy()
     bad[5, 1] = np.nan
     sim = D.Sim(w.params)
+    for bad_tuning in ((0, 1.0, 2, 0), (0, 1.0, 0, 3), (0, 0.5, 0, 0)):
+        with pytest.raises(D.DemError) as ei:
+            sim.set_tuning(*bad_tuning)
+        assert ei.value.code == D.DEM_ERR_INVALID_ARG
     with pytest.raises(D.DemError) as ei:
         sim.add_aggregates(w.counts, bad, w.radius, w.mass)
     assert ei.value.code == D.DEM_ERR_INVALID_ARG
@@ -316,6 +320,45 @@ def test_spin_up_parity(D):
     sim.step(3)
     o.step(3)
     compare_states(sim, o, tol=1e-10)
+
+
+@pytest.mark.parametrize("case", ["lone+big", "collapse"])
+def test_member_read_paths_bit_identical(D, case):
+    """The member reduction read directly and staged through LDS (forced by
+    the tuning; a launch picks staging only from 131,072 aggregates) gives
+    bit-identical states, and the staged run matches the oracle -- with lone
+    spheres and a 155-sphere aggregate spanning several 64-sphere slices, and
+    with aggregates of 2-8 spheres."""
+    say("member read paths", case)
+    if case == "lone+big":
+        rng = np.random.default_rng(5)
+        big_rel, big_r = W.random_cluster(rng, 155)
+        parts_p, parts_r, counts = [big_rel], [big_r], [155]
+        for k in range(200):
+            parts_p.append(rng.uniform(-30, 30, 3)[None] + 40.0)
+            parts_r.append(rng.uniform(0.8, 1.2, 1))
+            counts.append(1)
+        rad = np.concatenate(parts_r)
+        prm = dict(W.CONTACT_PARAMS, dt=5e-4, G=1.0, soft_frac=0.5, periodic=0, box=(0, 0, 0))
+        w = W.Workload("mixed", np.array(counts, np.int32), np.concatenate(parts_p), rad,
+                       W.sphere_mass(rad), rng.normal(0, 0.1, (len(counts), 3)),
+                       rng.normal(0, 0.2, (len(counts), 3)), prm, 3)
+    else:
+        w = W.collapse_cloud(62, n_agg=500, contact_seeded=True, spin_sigma=0.2)
+    out = []
+    for read in (1, 2):
+        sim = D.Sim(w.params)
+        sim.set_tuning(0, 1.0, 0, read)
+        sim.add_workload(w)
+        sim.step(3)
+        out.append(sim.read_state(pairs=True))
+        if read == 2:
+            o = O.Oracle(w.params).add_workload(w)
+            o.step(3)
+            compare_states(sim, o, tol=1e-10)
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
 
 
 def test_engine_alone_vs_mix_bit_identical(D):
