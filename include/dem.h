@@ -202,6 +202,7 @@ dem_status dem_reserve_contacts(dem_sim* sim, int32_t max_contacts_per_sphere);
  * agg[i] != agg[j] and d^2 < (s_i+s_j)^2, d^2 = (dx*dx + dy*dy) + dz*dz with
  * the minimum-image rule when box != NULL (cube of side box[0]).  Host arrays
  * in; canonical keys out (up to cap); *n_out gets the total count.
+ * n = 0 is an empty search (*n_out = 0, the arrays may be NULL).
  * CAPACITY if more than 64 contacts per sphere are found. */
 dem_status dem_find_contacts(const double* pos, const double* radius, const int32_t* agg,
                              int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,

@@ -1230,8 +1230,13 @@ dem_status dem_sim_status(const dem_sim* s) {
 dem_status dem_find_contacts(const double* pos, const double* radius, const int32_t* agg,
                              int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,
                              int64_t* n_out) {
-  if (!pos || !radius || !agg || n <= 0 || !n_out || (cap > 0 && !pairs_out))
+  if (!n_out || n < 0 || cap < 0 || (cap > 0 && !pairs_out))
     return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  if (n == 0) {                 // no spheres, no contacts
+    *n_out = 0;
+    return DEM_OK;
+  }
+  if (!pos || !radius || !agg) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
   if (n > (int64_t(1) << 28)) return fail(nullptr, DEM_ERR_INVALID_ARG, "too many spheres");
   double smax = 0.0;
   for (int64_t i = 0; i < n; ++i) {

@@ -45,6 +45,31 @@ def test_find_contacts_bit_exact(D, n_agg, periodic):
         assert ref.size > n_agg // 2
 
 
+def test_degenerate_systems(D):
+    """An empty contact search finds nothing; one lone sphere drifts and
+    spins freely (its gravity excludes itself); one spinning 8-sphere
+    aggregate alone feels no net force or torque from its own members'
+    gravity and rotates torque-free -- each against the oracle."""
+    say("degenerate systems")
+    z = np.zeros((0, 3))
+    assert D.find_contacts(z, np.zeros(0), np.zeros(0, np.int32)).size == 0
+    prm = dict(W.CONTACT_PARAMS, dt=5e-4, G=1.0, soft_frac=0.5, periodic=0, box=(0, 0, 0))
+    rng = np.random.default_rng(8)
+    rel, rad = W.random_cluster(rng, 8)
+    for counts, pos, r in (([1], np.array([[0.3, -0.2, 0.1]]), np.array([1.1])),
+                           ([8], rel + 5.0, rad)):
+        w = W.Workload("degenerate", np.array(counts, np.int32), pos, r, W.sphere_mass(r),
+                       np.array([[0.2, -0.1, 0.05]]), np.array([[0.1, 0.4, -0.3]]), prm, 5)
+        sim, o = _pair(D, w)
+        compare_states(sim, o)
+        sim.step(5)
+        o.step(5)
+        compare_states(sim, o, tol=1e-10)
+        a = sim.read_state(["agg_acc", "agg_torque"])
+        scale = float(np.abs(o.spheres()["F"]).max()) if counts[0] > 1 else 1.0
+        assert np.abs(a["agg_acc"]).max() <= 1e-12 * max(scale, 1.0)
+
+
 def test_find_contacts_wrapped_positions(D):
     """Whole aggregates shifted by +-L: binning wraps the centres and both
     sides apply the same minimum-image rule."""
