@@ -470,6 +470,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ p
   const int cap = P.cap_pairs;
   const uint32_t* __restrict__ up_off = P.up_off[nxt];
   double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+  // unrolled so that two contacts' loads are in flight (same order of sums)
+#pragma unroll 2
   for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
     const uint32_t p = P.lo_pair[e];
     for (int k = 0; k < 3; ++k) {
@@ -477,6 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ p
       t[k] += P.pTj[k * cap + p];
     }
   }
+#pragma unroll 2
   for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
     for (int k = 0; k < 3; ++k) {
       f[k] += P.pF[k * cap + p];
