@@ -552,7 +552,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
         add_member(R, f, bb, tau, FA, NA);
       }
   } else if (P.member_read == 1 || (P.member_read == 0 && !stage)) {
+    // unrolled so that two members' loads are in flight (same order of sums)
     if (own)
+#pragma unroll 2
       for (int i = P.first[A], i1 = i + P.count[A]; i < i1; ++i) {
         const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
         const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
