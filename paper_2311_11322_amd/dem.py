@@ -97,6 +97,16 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2311_11322_amd.build_lib` (hipcc, gfx950)")
+        # PyTorch carries its own HIP runtime beside the one the library
+        # links.  With the library's runtime initialised first, PyTorch then
+        # finds no GPU; the other order works.  So PyTorch, when it sees a
+        # GPU, is initialised before the library is loaded.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.dem_create.argtypes = [C.POINTER(dem_params), C.POINTER(dem_allocator), vp, C.POINTER(vp)]
