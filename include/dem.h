@@ -208,6 +208,32 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
                              int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,
                              int64_t* n_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * stateless contact search of dem_find_contacts on arrays already in device
+ * memory, allocating nothing.  Every scratch buffer of the search (cell
+ * table, sorted copies, contact runs, work lists) lives in one static device
+ * array of 40 MiB, which each GPU the library runs on holds until the process
+ * ends; it is found on the current device.
+ *   pos     device [n][3] row-major sphere centres
+ *   radius  device [n] radii (> 0, finite)
+ *   agg     device [n] aggregate ids; pairs with equal ids never count
+ *   box     host pointer to the periodic cube side (box[0]), or NULL (open)
+ *   pairs_out device [cap] canonical keys i << 32 | j, in order; the first
+ *           cap are written
+ *   n_out   host; total number of contacts
+ *   hip_stream  stream the work is issued on (NULL: the null stream); the
+ *           call returns after the work is complete
+ * Limits: n <= 65536 spheres and at most 1,048,576 contacts (CAPACITY
+ * beyond, with *n_out the total found).  INVALID_ARG for larger n, a
+ * non-positive or non-finite radius, a non-finite position or box.
+ * Calls on one GPU share its scratch array: calls that overlap in time on
+ * the same GPU (other threads or streams) race and must not be made. */
+dem_status dem_find_contacts_noalloc(const double* pos, const double* radius,
+                                     const int32_t* agg, int64_t n, const double* box,
+                                     uint64_t* pairs_out, int64_t cap, int64_t* n_out,
+                                     void* hip_stream);
+
 dem_status dem_destroy(dem_sim* sim);
 
 /* Description of the last error on this system (or the last global error if

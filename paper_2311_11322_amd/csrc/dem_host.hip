@@ -705,6 +705,164 @@ dem_status ensure_own_table(dem_sim* s) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// allocation-free contact search: every scratch buffer in one static array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int64_t kNoAllocMaxSpheres = 65536;
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(40) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// Scratch of dem_find_contacts_noalloc: one copy per GPU, held until the
+// process ends.  In host code this name is only a stand-in for the symbol;
+// the device address comes from hipGetSymbolAddress (noalloc_scratch()).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// First bytes of the scratch: the largest radius (bit pattern of a positive
+// double, ordered like an unsigned integer) and a flag for invalid input.
+struct NoAllocHdr {
+  unsigned long long max_r_bits;
+  uint32_t bad;
+  uint32_t pad;
+};
+
+// One thread per sphere: row-major device positions into the search's
+// component-major array; radius and position checks; largest radius.
+__global__ __launch_bounds__(kBlock) void k_noalloc_ingest(const double* __restrict__ pos,
+                                                           const double* __restrict__ rad, int n,
+                                                           double* __restrict__ r,
+                                                           NoAllocHdr* __restrict__ hdr) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double smax = 0.0;
+  bool bad = false;
+  if (i < n) {
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2], s = rad[i];
+    r[i] = x;
+    r[n + i] = y;
+    r[2 * n + i] = z;
+    bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(s) && s > 0.0);
+    smax = bad ? 0.0 : s;
+  }
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
+  const bool any_bad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    if (any_bad) atomicOr(&hdr->bad, 1u);
+    if (smax > 0.0) atomicMax(&hdr->max_r_bits, (unsigned long long)__double_as_longlong(smax));
+  }
+}
+
+// One thread per sphere: its upper run as canonical keys, up to cap in all.
+__global__ __launch_bounds__(kBlock) void k_noalloc_keys(const uint32_t* __restrict__ off,
+                                                         const uint32_t* __restrict__ pj, int n,
+                                                         uint64_t* __restrict__ out, int64_t cap) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t p = off[i], p1 = off[i + 1]; p < p1 && p < cap; ++p)
+    out[p] = (uint64_t(i) << 32) | pj[p];
+}
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up once per device,
+// with that device current).
+hipError_t noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Bump placement inside the scratch (256-byte aligned pieces).
+struct Placer {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += round256(size_t(std::max<int64_t>(count, 1)) * sizeof(T));
+    return p;
+  }
+};
+
+// Places the header, the table entry, the work lists and every buffer the
+// search kernels touch for n spheres; returns the bytes used.
+struct NoAllocPlan {
+  NoAllocHdr* hdr;
+  PileDev* entry;
+  WorkItem* wl;
+  ScanSeg* seg_cells;
+  ScanItem* item_cells;
+  uint32_t* sums_cells;
+  ScanSeg* seg_pairs;
+  ScanItem* item_pairs;
+  uint32_t* sums_pairs;
+  int n_blk, n_item_cells, n_item_pairs, max_items_cells, max_items_pairs;
+  int64_t cells;
+  size_t bytes;
+};
+
+int64_t scan_items(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+
+NoAllocPlan plan_noalloc(char* base, int64_t n, PileDev& h) {
+  Placer L{base};
+  NoAllocPlan q{};
+  q.cells = int64_t(1) << (3 * choose_bits(n));
+  q.n_blk = (int)((n + kBlock - 1) / kBlock);
+  q.n_item_cells = (int)scan_items(q.cells + 1);
+  q.max_items_cells = q.n_item_cells;
+  q.max_items_pairs = (int)scan_items(n);
+  q.n_item_pairs = 2 * q.max_items_pairs;
+  q.hdr = L.take<NoAllocHdr>(1);
+  q.entry = L.take<PileDev>(1);
+  q.wl = L.take<WorkItem>(q.n_blk);
+  q.seg_cells = L.take<ScanSeg>(1);
+  q.item_cells = L.take<ScanItem>(q.n_item_cells);
+  q.sums_cells = L.take<uint32_t>(q.n_item_cells);
+  q.seg_pairs = L.take<ScanSeg>(2);
+  q.item_pairs = L.take<ScanItem>(q.n_item_pairs);
+  q.sums_pairs = L.take<uint32_t>(q.n_item_pairs);
+  h.r = L.take<double>(3 * n);
+  h.key = L.take<uint32_t>(n);
+  h.sidx = L.take<uint32_t>(n);
+  h.sidx_raw = L.take<uint32_t>(n);
+  h.slot = L.take<uint32_t>(n);
+  h.xs = L.take<double>(4 * n);
+  h.xg = L.take<SortedGeom>(n);
+  h.sid = L.take<SortedId>(n);
+  h.bpart = L.take<double>(10 * q.n_blk);
+  h.grid = L.take<Grid>(1);
+  h.cell_cnt = L.take<uint32_t>(q.cells + 1);
+  h.cell_start = L.take<uint32_t>(q.cells + 2);
+  h.run_cache = L.take<uint32_t>(2 * kRunCache * n);
+  h.cnt_up = L.take<uint32_t>(n);
+  h.cnt_lo = L.take<uint32_t>(n);
+  h.up_off[0] = L.take<uint32_t>(n + 1);
+  h.up_off[1] = L.take<uint32_t>(n + 1);
+  h.lo_off = L.take<uint32_t>(n + 1);
+  h.pair_j[0] = L.take<uint32_t>(kNoAllocMaxPairs);
+  h.pair_j[1] = L.take<uint32_t>(kNoAllocMaxPairs);
+  h.pair_i = L.take<uint32_t>(kNoAllocMaxPairs);
+  h.lo_nbr = L.take<uint32_t>(kNoAllocMaxPairs);
+  q.bytes = L.off;
+  return q;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
 
@@ -1311,6 +1469,118 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
   for (int64_t i = 0; i < n; ++i)
     for (uint32_t q = off[i]; q < off[i + 1] && q < cap; ++q)
       pairs_out[q] = (uint64_t(i) << 32) | pj[q];
+  return DEM_OK;
+}
+
+dem_status dem_find_contacts_noalloc(const double* pos, const double* radius,
+                                     const int32_t* agg, int64_t n, const double* box,
+                                     uint64_t* pairs_out, int64_t cap, int64_t* n_out,
+                                     void* hip_stream) {
+  if (!n_out || n < 0 || cap < 0 || (cap > 0 && !pairs_out))
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  if (n > kNoAllocMaxSpheres)
+    return fail(nullptr, DEM_ERR_INVALID_ARG,
+                "more spheres than the static scratch holds (65536)");
+  if (box && !(box[0] > 0 && std::isfinite(box[0])))
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "bad box");
+  *n_out = 0;
+  if (n == 0) return DEM_OK;
+  if (!pos || !radius || !agg) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  HIPCHK(nullptr, hipGetDevice(&dev));
+  void* base = nullptr;
+  HIPCHK(nullptr, noalloc_scratch(dev, &base));
+  PileDev h{};
+  const NoAllocPlan q = plan_noalloc(static_cast<char*>(base), n, h);
+  if (q.bytes > kNoAllocScratchBytes)
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "search does not fit the static scratch");
+  // positions in, radius checks and the largest radius out
+  launch_fill_u32(st, reinterpret_cast<uint32_t*>(q.hdr), 0u, sizeof(NoAllocHdr) / 4);
+  hipLaunchKernelGGL(k_noalloc_ingest, dim3(q.n_blk), dim3(kBlock), 0, st, pos, radius, (int)n,
+                     h.r, q.hdr);
+  NoAllocHdr hdr{};
+  HIPCHK(nullptr, hipMemcpyAsync(&hdr, q.hdr, sizeof hdr, hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  if (hdr.bad) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad radius or position");
+  double smax;
+  std::memcpy(&smax, &hdr.max_r_bits, sizeof smax);
+  // the table entry of a pile of given positions (no aggregates, no gravity)
+  h.na = 0;
+  h.ns = (int32_t)n;
+  h.cap_pairs = (int32_t)kNoAllocMaxPairs;
+  h.bits = choose_bits(n);
+  h.periodic = box ? 1 : 0;
+  h.box = box ? box[0] : 0.0;
+  h.n_rblk = q.n_blk;
+  h.cell_min = 2.0 * smax;
+  h.s_cut = INFINITY;
+  h.s_small = smax;
+  h.n_big = 0;
+  h.fail_step = -1;
+  h.s = const_cast<double*>(radius);
+  h.agg = const_cast<int32_t*>(agg);
+  if (box) h.n_periodic = periodic_cells(box[0], h.cell_min, h.bits);
+  // work lists and scan segments (fixed-size host staging)
+  WorkItem wl[kNoAllocMaxSpheres / kBlock];
+  for (int b = 0; b < q.n_blk; ++b) wl[b] = WorkItem{0, b * kBlock};
+  ScanSeg sc{};
+  sc.in = h.cell_cnt;
+  sc.out_pp[0] = sc.out_pp[1] = h.cell_start;
+  sc.n = (int32_t)(q.cells + 1);
+  sc.n_items = q.n_item_cells;
+  ScanItem ic[(((int64_t(1) << 18) + 1) + kScanChunk - 1) / kScanChunk];
+  static_assert(sizeof(ic) / sizeof(ic[0]) >= (size_t)(((int64_t(1) << 18) + 1 + kScanChunk - 1) /
+                                                        kScanChunk), "cell scan items");
+  for (int c = 0; c < q.n_item_cells; ++c) ic[c] = ScanItem{0, c};
+  ScanSeg sp[2]{};
+  ScanItem ip[2 * ((kNoAllocMaxSpheres + kScanChunk - 1) / kScanChunk)];
+  const uint32_t* ins[2] = {h.cnt_up, h.cnt_lo};
+  uint32_t* outs[2] = {h.up_off[1], h.lo_off};
+  for (int g = 0; g < 2; ++g) {
+    sp[g].in = ins[g];
+    sp[g].out_pp[0] = sp[g].out_pp[1] = outs[g];
+    sp[g].n = (int32_t)n;
+    sp[g].item0 = g * q.max_items_pairs;
+    sp[g].n_items = q.max_items_pairs;
+    for (int c = 0; c < q.max_items_pairs; ++c) ip[g * q.max_items_pairs + c] = ScanItem{g, c};
+  }
+  HIPCHK(nullptr, hipMemcpyAsync(q.entry, &h, sizeof h, hipMemcpyHostToDevice, st));
+  HIPCHK(nullptr, hipMemcpyAsync(q.wl, wl, q.n_blk * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+  HIPCHK(nullptr, hipMemcpyAsync(q.seg_cells, &sc, sizeof sc, hipMemcpyHostToDevice, st));
+  HIPCHK(nullptr, hipMemcpyAsync(q.item_cells, ic, q.n_item_cells * sizeof(ScanItem),
+                                 hipMemcpyHostToDevice, st));
+  HIPCHK(nullptr, hipMemcpyAsync(q.seg_pairs, sp, sizeof sp, hipMemcpyHostToDevice, st));
+  HIPCHK(nullptr, hipMemcpyAsync(q.item_pairs, ip, q.n_item_pairs * sizeof(ScanItem),
+                                 hipMemcpyHostToDevice, st));
+  // the cell counts start at zero (the scatter returns them to zero)
+  launch_fill_u32(st, h.cell_cnt, 0u, q.cells + 1);
+  const PileDev* t = q.entry;
+  launch_reconstruct(st, t, q.wl, q.n_blk);
+  launch_grid(st, t, 1, kModeInit, 1.0);
+  launch_bin(st, t, q.wl, q.n_blk);
+  launch_scan(st, q.seg_cells, 1, q.item_cells, q.n_item_cells, q.sums_cells, q.max_items_cells);
+  launch_scatter(st, t, q.wl, q.n_blk);
+  launch_cell_sort(st, t, q.wl, q.n_blk);
+  launch_search(st, t, q.wl, q.n_blk, 0);
+  launch_scan(st, q.seg_pairs, 2, q.item_pairs, q.n_item_pairs, q.sums_pairs, q.max_items_pairs);
+  launch_search(st, t, q.wl, q.n_blk, 1);
+  HIPCHK(nullptr, hipGetLastError());
+  int32_t status = 0;
+  uint32_t total = 0;
+  HIPCHK(nullptr, hipMemcpyAsync(&status, &q.entry->status, sizeof status, hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipMemcpyAsync(&total, h.up_off[1] + n, sizeof total, hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  *n_out = total;
+  if (status & kStCapacity)
+    return fail(nullptr, DEM_ERR_CAPACITY, "more contacts than the static scratch holds");
+  if (status != 0) return fail(nullptr, DEM_ERR_INVALID_ARG, "non-finite positions");
+  if (cap > 0 && total > 0) {
+    hipLaunchKernelGGL(k_noalloc_keys, dim3(q.n_blk), dim3(kBlock), 0, st, h.up_off[1], h.pair_j[1],
+                       (int)n, pairs_out, cap);
+    HIPCHK(nullptr, hipGetLastError());
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+  }
   return DEM_OK;
 }
 

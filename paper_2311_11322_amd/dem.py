@@ -119,6 +119,8 @@ def lib():
         L.dem_restore_state.argtypes = [vp, C.POINTER(dem_state)]
         L.dem_reserve_contacts.argtypes = [vp, C.c_int32]
         L.dem_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64, _PI64]
+        L.dem_find_contacts_noalloc.argtypes = [vp, vp, vp, C.c_int64, _PD, vp, C.c_int64, _PI64,
+                                                vp]
         L.dem_destroy.argtypes = [vp]
         L.dem_last_error.argtypes = [vp]
         L.dem_last_error.restype = C.c_char_p
@@ -142,7 +144,7 @@ def lib():
                      "dem_engine_create", "dem_engine_attach", "dem_engine_step",
                      "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
                      "dem_set_profiling", "dem_get_profile", "dem_set_tuning",
-                     "dem_get_forcing"):
+                     "dem_get_forcing", "dem_find_contacts_noalloc"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -407,6 +409,26 @@ def find_contacts(pos, radius, agg, box=None) -> np.ndarray:
     _check(lib().dem_find_contacts(_p(pos), _p(radius), _p(agg, _PI32), n, _p(bx),
                                    _p(keys, _PU64), cap, C.byref(nout)))
     return keys[:nout.value].copy()
+
+
+def find_contacts_noalloc(pos, radius, agg, box=None, out=None, stream=None):
+    """The allocation-free device search on device tensors (torch, cuda:0):
+    ``pos`` [n, 3] float64, ``radius`` [n] float64, ``agg`` [n] int32, all
+    contiguous; ``out`` a device uint64/int64 tensor receiving the keys (up
+    to its length).  Returns the total number of contacts.  Argument
+    marshalling only; nothing here allocates device memory."""
+    n = int(radius.shape[0])
+    for t in (pos, radius, agg):
+        if not t.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+    bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    cap = 0 if out is None else int(out.numel())
+    nout = C.c_int64()
+    st = torch_stream() if stream is None else stream
+    _check(lib().dem_find_contacts_noalloc(
+        C.c_void_p(pos.data_ptr()), C.c_void_p(radius.data_ptr()), C.c_void_p(agg.data_ptr()),
+        n, _p(bx), None if out is None else C.c_void_p(out.data_ptr()), cap, C.byref(nout), st))
+    return int(nout.value)
 
 
 def gravity_tiles(precision: int = PREC_FP64):
