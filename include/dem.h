@@ -71,7 +71,7 @@ typedef struct {
     double max_overlap_frac;   /* > 0: overlap above this fraction of the smaller radius is
                                   an instability (DEM_ERR_UNSTABLE); <= 0: no check */
     /* Container and uniform field of the box-filling and shaking workloads
-     * (Sec. 3.2 profiling runs, Sec. 4.3 Brazil-nut runs).  g is added to the
+     * (Sec. 3.3 performance-scaling runs, Sec. 4.3 Brazil-nut runs).  g is added to the
      * acceleration of every body.  Wall w is the plane n.x = d with
      * walls[w] = {n_x, n_y, n_z, d}, n a unit normal pointing into the domain,
      * displaced rigidly by shake_amp[w] * sin(shake_omega * t + shake_phase)
@@ -207,6 +207,34 @@ dem_status dem_reserve_contacts(dem_sim* sim, int32_t max_contacts_per_sphere);
 dem_status dem_find_contacts(const double* pos, const double* radius, const int32_t* agg,
                              int64_t n, const double* box, uint64_t* pairs_out, int64_t cap,
                              int64_t* n_out);
+
+/* Contact forces of given sphere states (test hook, so that a checker can
+ * evaluate the contact model on exactly the same FP64 input): one evaluation
+ * of the contact part of a step -- search skipping pairs of one aggregate,
+ * spring history carried from the given previous contacts, the contact force
+ * of every contact (Sec. 2.1, 2.2.4, 2.2.5; Eqs. 8-9) and the per-sphere sums
+ * in canonical order -- without motion, gravity or the aggregate reduction.
+ * Walls of params are evaluated at t = 0; params->G is ignored.  Host arrays:
+ *   pos, vel  [n][3] sphere centres and velocities (the predicted velocities
+ *             of Eq. 3)
+ *   radius    [n]; agg [n] aggregate of each sphere, 0 .. n_agg-1
+ *   agg_mass  [n_agg] aggregate masses (the reduced mass of a contact is
+ *             formed from them); agg_spin [n_agg][3] space-frame spins
+ *   old_keys  [n_old] canonical sorted keys of the previous contacts (a wall
+ *             w of a sphere i is i << 32 | (n + w)); old_hist [n_old][7]
+ *   force, torque  out [n][3]: contact force on each sphere and contact
+ *             torque about its centre
+ *   keys_out, hist_out  out [cap] and [cap][7]: the new contacts and their
+ *             updated history (the first cap); *n_out gets the count.
+ * Precision and contact capacity (default 16 per sphere) from params.
+ * Errors: INVALID_ARG (sizes, non-finite values, unsorted keys), CAPACITY,
+ * UNSTABLE (non-finite force). */
+dem_status dem_contact_forces(const dem_params* params, int64_t n, const double* pos,
+                              const double* vel, const double* radius, const int32_t* agg,
+                              int64_t n_agg, const double* agg_mass, const double* agg_spin,
+                              int64_t n_old, const uint64_t* old_keys, const double* old_hist,
+                              double* force, double* torque, uint64_t* keys_out,
+                              double* hist_out, int64_t cap, int64_t* n_out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the

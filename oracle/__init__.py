@@ -69,6 +69,12 @@ def lib():
         L.ora_get_perturber.argtypes = [C.c_void_p, _PD, _PD, _PD]
         L.ora_rotate.argtypes = [_PD, _PD, _PD, _PD, C.c_double, _PD]
         L.ora_setup_body.restype = C.c_int
+        L.ora_set_threads.restype = C.c_int32
+        L.ora_contact_forces.restype = C.c_int64
+        L.ora_contact_forces.argtypes = [C.POINTER(Params), C.c_int64, _PD, _PD, _PD, _PI32,
+                                         C.c_int64, _PD, _PD, C.c_int64, _PU64, _PD, _PD, _PD,
+                                         _PU64, _PD, C.c_int64]
+        L.ora_set_threads.argtypes = [C.c_int32]
         L.ora_setup_body.argtypes = [C.c_int64, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
         _LIB = L
     return _LIB
@@ -124,6 +130,10 @@ class Oracle:
         self._h = lib().ora_create(C.byref(self._params))
         if not self._h:
             raise MemoryError("ora_create failed")
+
+    @property
+    def dt(self) -> float:
+        return float(self._params.dt)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -283,3 +293,35 @@ def quat_matrix(q) -> np.ndarray:
         [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
         [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
     ])
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's gravity target loops (OpenMP); the results do
+    not depend on it.  n <= 0 only queries.  Returns the count in effect."""
+    return int(lib().ora_set_threads(int(n)))
+
+
+def contact_forces(params: Dict, pos, vel, radius, agg, agg_mass, agg_spin, old_keys=None,
+                   old_hist=None) -> Dict[str, np.ndarray]:
+    """Contact part of one evaluation on given sphere states: per-sphere
+    contact force and torque, new canonical keys and their history."""
+    prm = make_params(params)
+    pos = _f64(pos)
+    vel = _f64(vel)
+    radius = _f64(radius)
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    agg_mass = _f64(agg_mass)
+    agg_spin = _f64(agg_spin)
+    ok = np.zeros(0, np.uint64) if old_keys is None else np.ascontiguousarray(old_keys, np.uint64)
+    oh = np.zeros((0, 7)) if old_hist is None else _f64(old_hist)
+    n = radius.shape[0]
+    cap = 64 * n
+    F = np.zeros((n, 3))
+    T = np.zeros((n, 3))
+    keys = np.zeros(cap, np.uint64)
+    hist = np.zeros((cap, 7))
+    k = lib().ora_contact_forces(C.byref(prm), n, _p(pos), _p(vel), _p(radius), _p(agg, _PI32),
+                                 agg_mass.shape[0], _p(agg_mass), _p(agg_spin), ok.shape[0],
+                                 _p(ok, _PU64), _p(oh), _p(F), _p(T), _p(keys, _PU64), _p(hist),
+                                 cap)
+    return {"F": F, "tau": T, "keys": keys[:k].copy(), "hist": hist[:k].copy()}

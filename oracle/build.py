@@ -1,5 +1,6 @@
 """Build step of the FP64 oracle (test infrastructure): plain gcc, no FMA
-contraction, no fast-math."""
+contraction, no fast-math; OpenMP shares the independent gravity targets among
+threads (each target's sum keeps its order)."""
 import os
 import subprocess
 import sys
@@ -10,7 +11,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
+           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
            os.path.join(HERE, "oracle.c"), "-o", LIB, "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -21,7 +21,7 @@
  *                   aggregate (members are rigidly bonded, Sec. 2.2).
  *   pair_force      spring-dashpot normal force, tangential spring with
  *                   history and a static-friction cap, rolling and twisting
- *                   friction (Sec. 2.1, 2.2.5); contact point from the lever
+ *                   friction (Sec. 2.1, 2.2.5); contact point (Sec. 2.2.4) from the lever
  *                   arm of Eq. 8; forces applied at that point (Eq. 9).
  *   gravity         direct sum of Eq. 4 with Plummer softening.
  *   reduce          Eqs. 5-7 and 9: aggregate acceleration and torque about
@@ -35,6 +35,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -628,12 +631,16 @@ static void gravity_pair(double G, double soft_frac, const double* ri, const dou
     F[2] += f * d[2];
 }
 
+/* Targets are independent: with OpenMP they are shared among threads, each
+ * target's sum still taken over j in index order, so the result does not
+ * depend on the thread count. */
 void ora_gravity(const double* pos, const double* mass, const double* radius, int64_t n,
                  double G, double soft_frac, const int64_t* idx, int64_t n_idx, double* F)
 {
-    int64_t k, j;
+    int64_t k;
+#pragma omp parallel for schedule(static)
     for (k = 0; k < n_idx; k++) {
-        int64_t i = idx[k];
+        int64_t i = idx[k], j;
         double acc[3] = {0.0, 0.0, 0.0};
         for (j = 0; j < n; j++) {
             if (j == i) continue;
@@ -997,12 +1004,49 @@ static int64_t find_old(const int64_t* opi, const int64_t* opj, int64_t onp, int
     return -1;
 }
 
+/* Contacts at the current positions and velocities: brute-force search,
+ * spring history carried from the previous list (opi, opj, ohist of onp
+ * pairs; none when onp is 0), the force of every contact, and the per-sphere
+ * sums in canonical order (F and tau are overwritten). */
+static void contact_pass(ora_sim* s, const int64_t* opi, const int64_t* opj, const double* ohist,
+                         int64_t onp)
+{
+    int64_t k, i;
+    int c;
+    find_pairs(s);
+    for (i = 0; i < 3 * s->ns; i++) { s->F[i] = 0.0; s->tau[i] = 0.0; }
+    /* pairs in lexicographic order: each sphere accumulates its contacts in
+     * that order */
+    for (k = 0; k < s->np; k++) {
+        double h_old[7] = {0, 0, 0, 0, 0, 0, 0};
+        int64_t ii = s->pi[k], jj = s->pj[k];
+        if (onp > 0) {
+            int64_t o = find_old(opi, opj, onp, ii, jj);
+            if (o >= 0) memcpy(h_old, &ohist[7 * o], 7 * sizeof(double));
+        }
+        pair_force(s, ii, jj, h_old, &s->hist[7 * k], &s->pforce[9 * k], &s->pdiag[8 * k]);
+    }
+    /* per-sphere accumulation in canonical order (pairs sorted by (i, j)) */
+    for (k = 0; k < s->np; k++) {
+        int64_t ii = s->pi[k], jj = s->pj[k];
+        const double* f = &s->pforce[9 * k];
+        for (c = 0; c < 3; c++) {
+            s->F[3 * ii + c] += f[c];
+            s->tau[3 * ii + c] += f[3 + c];
+            if (jj < s->ns) {             /* a wall takes the reaction */
+                s->F[3 * jj + c] -= f[c];
+                s->tau[3 * jj + c] += f[6 + c];
+            }
+        }
+    }
+}
+
 /* Full force evaluation at the current positions and predicted velocities:
  * contacts (with history carried for pairs that persist), gravity, and the
  * reduction onto aggregates (Eqs. 5-7, 9). */
 static void evaluate(ora_sim* s, int carry_history)
 {
-    int64_t k, i, A;
+    int64_t i, A;
     int c;
     /* keep the previous contact list for the history carry */
     int64_t onp = s->np;
@@ -1017,33 +1061,8 @@ static void evaluate(ora_sim* s, int carry_history)
         memcpy(opj, s->pj, onp * sizeof(int64_t));
         memcpy(ohist, s->hist, onp * 7 * sizeof(double));
     }
-    find_pairs(s);
-    for (i = 0; i < 3 * s->ns; i++) { s->F[i] = 0.0; s->tau[i] = 0.0; }
-    /* pairs in lexicographic order: each sphere accumulates its contacts in
-     * that order */
-    for (k = 0; k < s->np; k++) {
-        double h_old[7] = {0, 0, 0, 0, 0, 0, 0};
-        int64_t ii = s->pi[k], jj = s->pj[k];
-        if (ohist) {
-            int64_t o = find_old(opi, opj, onp, ii, jj);
-            if (o >= 0) memcpy(h_old, &ohist[7 * o], 7 * sizeof(double));
-        }
-        pair_force(s, ii, jj, h_old, &s->hist[7 * k], &s->pforce[9 * k], &s->pdiag[8 * k]);
-    }
+    contact_pass(s, opi, opj, ohist, ohist ? onp : 0);
     free(opi); free(opj); free(ohist);
-    /* per-sphere accumulation in canonical order (pairs sorted by (i, j)) */
-    for (k = 0; k < s->np; k++) {
-        int64_t ii = s->pi[k], jj = s->pj[k];
-        const double* f = &s->pforce[9 * k];
-        for (c = 0; c < 3; c++) {
-            s->F[3 * ii + c] += f[c];
-            s->tau[3 * ii + c] += f[3 + c];
-            if (jj < s->ns) {             /* a wall takes the reaction */
-                s->F[3 * jj + c] -= f[c];
-                s->tau[3 * jj + c] += f[6 + c];
-            }
-        }
-    }
     /* self-gravity, Eq. 4, every j != i including members of the same
      * aggregate (their forces cancel in Eqs. 5-6) */
     if (s->p.G != 0.0 && s->p.gravity_tree) {
@@ -1053,9 +1072,13 @@ static void evaluate(ora_sim* s, int carry_history)
         for (i = 0; i < 3 * s->ns; i++) s->F[i] += Fg[i];
         free(Fg);
     } else if (s->p.G != 0.0) {
+        /* one target per iteration (threads share the targets; each sum runs
+         * over j in index order, so the thread count changes nothing) */
+#pragma omp parallel for schedule(static)
         for (i = 0; i < s->ns; i++) {
             double acc[3] = {0.0, 0.0, 0.0};
             int64_t j;
+            int c;
             for (j = 0; j < s->ns; j++) {
                 if (j == i) continue;
                 gravity_pair(s->p.G, s->p.soft_frac, &s->r[3 * i], &s->r[3 * j], s->m[i], s->m[j],
@@ -1348,12 +1371,15 @@ void ora_diagnostics(ora_sim* s, double* out)
     out[15] = Uu;
 }
 
+/* The listed spheres are independent: with OpenMP they are shared among
+ * threads; each one's sums keep their order. */
 void ora_eval_subset(const ora_sim* s, const int64_t* idx, int64_t n_idx, double* F, double* tau)
 {
-    int64_t k, j;
-    int c;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
     for (k = 0; k < n_idx; k++) {
-        int64_t x = idx[k];
+        int64_t x = idx[k], j;
+        int c;
         double f[3] = {0, 0, 0}, t[3] = {0, 0, 0};
         /* contacts in canonical order: pairs (j, x) with j < x, then (x, j) */
         for (j = 0; j < s->ns; j++) {
@@ -1409,5 +1435,70 @@ int64_t ora_find_contacts(const double* pos, const double* radius, const int32_t
             }
         }
     }
+    return np;
+}
+
+/* Threads of the OpenMP target loops (gravity); 1 runs them serially.
+ * Returns the count in effect (1 without OpenMP). */
+int32_t ora_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* Contact part of one evaluation on given sphere states (the same-input
+ * check of the contact model): n spheres at pos with velocities vel (the
+ * predicted velocities of Eq. 3), radii, aggregate ids agg (0..n_agg-1),
+ * aggregate masses and space-frame spins; previous contacts old_keys
+ * (canonical, sorted; a wall w of sphere i is i << 32 | (n + w)) with their
+ * history old_hist[7].  Walls of p are taken at t = 0.  Writes per-sphere
+ * contact force F and torque tau (canonical order of sums), the new keys and
+ * history (up to cap); returns the number of contacts. */
+int64_t ora_contact_forces(const ora_params* p, int64_t n, const double* pos, const double* vel,
+                           const double* radius, const int32_t* agg, int64_t n_agg,
+                           const double* agg_mass, const double* agg_spin, int64_t n_old,
+                           const uint64_t* old_keys, const double* old_hist, double* F,
+                           double* tau, uint64_t* keys, double* hist, int64_t cap)
+{
+    int64_t i, k, np;
+    ora_sim* s = ora_create(p);
+    int64_t* opi = (int64_t*)malloc((n_old > 0 ? n_old : 1) * sizeof(int64_t));
+    int64_t* opj = (int64_t*)malloc((n_old > 0 ? n_old : 1) * sizeof(int64_t));
+    s->na = n_agg;
+    s->ns = n;
+    s->agg = (int64_t*)malloc(n * sizeof(int64_t));
+    s->s = (double*)malloc(n * sizeof(double));
+    s->r = (double*)malloc(3 * n * sizeof(double));
+    s->v = (double*)malloc(3 * n * sizeof(double));
+    s->F = (double*)calloc(3 * n, sizeof(double));
+    s->tau = (double*)calloc(3 * n, sizeof(double));
+    s->M = (double*)malloc(n_agg * sizeof(double));
+    s->wA = (double*)malloc(3 * n_agg * sizeof(double));
+    for (i = 0; i < n; i++) { s->agg[i] = agg[i]; s->s[i] = radius[i]; }
+    memcpy(s->r, pos, 3 * n * sizeof(double));
+    memcpy(s->v, vel, 3 * n * sizeof(double));
+    memcpy(s->M, agg_mass, n_agg * sizeof(double));
+    memcpy(s->wA, agg_spin, 3 * n_agg * sizeof(double));
+    s->t_eval = 0.0;
+    for (k = 0; k < n_old; k++) {
+        opi[k] = (int64_t)(old_keys[k] >> 32);
+        opj[k] = (int64_t)(old_keys[k] & 0xffffffffu);
+    }
+    contact_pass(s, opi, opj, old_hist, n_old);
+    memcpy(F, s->F, 3 * n * sizeof(double));
+    memcpy(tau, s->tau, 3 * n * sizeof(double));
+    np = s->np;
+    for (k = 0; k < np && k < cap; k++) {
+        keys[k] = ((uint64_t)s->pi[k] << 32) | (uint64_t)s->pj[k];
+        memcpy(&hist[7 * k], &s->hist[7 * k], 7 * sizeof(double));
+    }
+    free(opi);
+    free(opj);
+    ora_destroy(s);
     return np;
 }

@@ -134,6 +134,23 @@ void ora_rotate(double* q, double* wb, const double* I, const double* N_space, d
 int ora_setup_body(int64_t n, const double* pos, const double* radius, const double* mass,
                    double* M, double* r, double* I, double* q, double* b);
 
+/* Contact part of one evaluation on given sphere states (same-input check
+ * of the contact model): brute-force search, history carried from the given
+ * previous contacts, every contact's force, per-sphere sums in canonical
+ * order.  pos, vel [n][3]; agg ids in 0..n_agg-1; agg_mass [n_agg],
+ * agg_spin [n_agg][3] space frame; old_keys canonical and sorted (wall w of
+ * sphere i: i << 32 | (n + w)), old_hist [n_old][7]; walls at t = 0.
+ * Outputs F, tau [n][3], keys [cap], hist [cap][7]; returns the count. */
+int64_t ora_contact_forces(const ora_params* p, int64_t n, const double* pos, const double* vel,
+                           const double* radius, const int32_t* agg, int64_t n_agg,
+                           const double* agg_mass, const double* agg_spin, int64_t n_old,
+                           const uint64_t* old_keys, const double* old_hist, double* F,
+                           double* tau, uint64_t* keys, double* hist, int64_t cap);
+
+/* Threads used by the gravity target loops (OpenMP); results do not depend
+ * on it.  n <= 0 only queries.  Returns the count in effect. */
+int32_t ora_set_threads(int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -308,6 +308,21 @@ dem_status fail(dem_sim* s, dem_status code, const std::string& msg) {
   return code;
 }
 
+// The library's HIP runtime must see a device before anything is allocated:
+// a process that also holds PyTorch (which carries its own HIP runtime) has to
+// initialise PyTorch first, or this runtime may come up without a GPU.
+dem_status require_device(dem_sim* s) {
+  int n = 0;
+  const hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0)
+    return fail(s, DEM_ERR_DEVICE,
+                std::string("no HIP device visible to the library's runtime (") +
+                    (e != hipSuccess ? hipGetErrorString(e) : "0 devices") +
+                    "); in a process that uses PyTorch, initialise PyTorch's GPU before "
+                    "loading this library");
+  return DEM_OK;
+}
+
 #define HIPCHK(sim, call)                                                   \
   do {                                                                      \
     hipError_t e_ = (call);                                                 \
@@ -940,6 +955,7 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
     if (agg_vel && !std::isfinite(agg_vel[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite velocity");
     if (agg_spin && !std::isfinite(agg_spin[k])) return fail(s, DEM_ERR_INVALID_ARG, "non-finite spin");
   }
+  if (require_device(s) != DEM_OK) return DEM_ERR_DEVICE;
   double s_cut, s_small;
   int n_big;
   split_big(radius, ns, &s_cut, &s_small, &n_big);
@@ -1185,7 +1201,9 @@ dem_status dem_restore_state(dem_sim* s, const dem_state* in) {
   for (int64_t p = 0; p < np; ++p) {
     const uint64_t key = in->pair_keys[p];
     const int64_t i = int64_t(key >> 32), j = int64_t(key & 0xffffffffu);
-    if (i < 0 || i >= ns || j <= i || j >= ns || (p > 0 && key <= in->pair_keys[p - 1]))
+    // a partner is a sphere j > i or a wall ns + w (sorted after the spheres)
+    if (i < 0 || i >= ns || j <= i || j >= ns + h.n_walls ||
+        (p > 0 && key <= in->pair_keys[p - 1]))
       return fail(s, DEM_ERR_INVALID_ARG, "pair keys must be canonical and sorted");
     off[i + 1]++;
     pj[p] = uint32_t(j);
@@ -1262,12 +1280,15 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
     return DEM_OK;
   }
   if (per_sphere <= s->c_max) return DEM_OK;
-  // checkpoint the state, reallocate with the larger capacity, restore
+  // checkpoint the state on the host, allocate a second set of buffers with
+  // the larger capacity, copy the constants across and restore into it; the
+  // old buffers are released only once that has succeeded, so any failure
+  // leaves the system as it was
   hipStream_t st = s->stream;
   HIPCHK(s, get_entry(s, s->own.d_table, st));
   const int64_t na = s->h.na, ns = s->h.ns, np = s->h.n_pairs;
   std::vector<double> rA(3 * na), vA(3 * na), aA(3 * na), NA(3 * na), q(4 * na), wb(3 * na),
-      b(3 * ns), hist(kHist * std::max<int64_t>(np, 1));
+      hist(kHist * std::max<int64_t>(np, 1));
   std::vector<uint64_t> keys(std::max<int64_t>(np, 1));
   dem_state io{};
   io.agg_pos = rA.data();
@@ -1280,60 +1301,79 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
   io.pair_hist = hist.data();
   dem_status r = dem_read_state(s, &io);
   if (r != DEM_OK) return r;
-  // constants that survive: copy them to host too
-  std::vector<int32_t> first(na), count(na), agg(ns);
-  std::vector<double> M(na), I(3 * na), rad(ns), mass(ns);
   const PileDev old = s->h;
-  HIPCHK(s, hipMemcpyAsync(first.data(), old.first, na * 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(count.data(), old.count, na * 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(agg.data(), old.agg, ns * 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(M.data(), old.M, na * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(I.data(), old.I, 3 * na * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(b.data(), old.b, 3 * ns * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(rad.data(), old.s, ns * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(mass.data(), old.m, ns * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipStreamSynchronize(st));
-  const double cell_min = old.cell_min;
-  const double s_cut = old.s_cut, s_small = old.s_small;
-  const int n_big = old.n_big;
-  const int nbp = old.n_periodic;
-  const int64_t step = old.step;
-  free_meta(s->own);
-  release_pile(s);
+  const Sizes old_sz = s->sz;
+  std::vector<void*> old_bufs;
+  old_bufs.swap(s->bufs);
+  const size_t old_bytes = s->bytes;
+  const int old_c = s->c_max;
+  s->bytes = 0;
+  auto undo = [&](dem_status code) {
+    release_pile(s);                       // the new buffers (if any)
+    s->bufs.swap(old_bufs);
+    s->bytes = old_bytes;
+    s->sz = old_sz;
+    s->h = old;
+    s->c_max = old_c;
+    free_meta(s->own);
+    if (put_entry(s, s->own.d_table, st) == hipSuccess) (void)rebuild(s->own, st, s);
+    (void)hipStreamSynchronize(st);
+    return code;
+  };
   s->c_max = per_sphere;
   r = alloc_pile(s, na, ns);
-  if (r != DEM_OK) return r;
+  if (r != DEM_OK) {
+    const std::string why = s->err;
+    undo(r);
+    return fail(s, r, why);
+  }
   PileDev& h = s->h;
-  h.cell_min = cell_min;
-  h.s_cut = s_cut;
-  h.s_small = s_small;
-  h.n_big = n_big;
-  h.n_periodic = nbp;
-  h.step = step;
+  h.cell_min = old.cell_min;
+  h.s_cut = old.s_cut;
+  h.s_small = old.s_small;
+  h.n_big = old.n_big;
+  h.n_periodic = old.n_periodic;
+  h.step = old.step;
   for (int k = 0; k < 3; ++k) {   // the perturber continues where it was
     h.pert_r[0][k] = old.pert_r[old.parity][k];
     h.pert_v[0][k] = old.pert_v[old.parity][k];
     h.pert_a[0][k] = old.pert_a[old.parity][k];
   }
-  HIPCHK(s, hipMemcpyAsync(h.first, first.data(), na * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.count, count.data(), na * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.agg, agg.data(), ns * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.M, M.data(), na * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.I, I.data(), 3 * na * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.b, b.data(), 3 * ns * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.s, rad.data(), ns * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync(h.m, mass.data(), ns * 8, hipMemcpyHostToDevice, st));
+  // constants that survive, device to device
+  hipError_t e = hipSuccess;
+  auto copy = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+  };
+  copy(h.first, old.first, na * 4);
+  copy(h.count, old.count, na * 4);
+  copy(h.agg, old.agg, ns * 4);
+  copy(h.M, old.M, na * 8);
+  copy(h.I, old.I, 3 * na * 8);
+  copy(h.b, old.b, 3 * ns * 8);
+  copy(h.s, old.s, ns * 8);
+  copy(h.m, old.m, ns * 8);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(s, undo(DEM_ERR_DEVICE), hip_msg(e, "reserve copy"));
   launch_fill_u32(st, h.up_off[0], 0u, ns + 1);
   launch_fill_u32(st, h.up_off[1], 0u, ns + 1);
   launch_fill_u32(st, h.lo_off, 0u, ns + 1);
-  r = ensure_own_table(s);
-  if (r != DEM_OK) return r;
-  HIPCHK(s, put_entry(s, s->own.d_table, st));
+  free_meta(s->own);
+  e = put_entry(s, s->own.d_table, st);
+  if (e != hipSuccess) return fail(s, undo(DEM_ERR_DEVICE), hip_msg(e, "reserve table"));
   r = rebuild(s->own, st, s);
-  if (r != DEM_OK) return r;
-  io.n_pairs = np;
-  io.step = step;
-  return dem_restore_state(s, &io);
+  if (r == DEM_OK) {
+    io.n_pairs = np;
+    io.step = old.step;
+    r = dem_restore_state(s, &io);
+  }
+  if (r != DEM_OK) {
+    const std::string why = s->err;
+    undo(r);
+    return fail(s, r, why);
+  }
+  // the new buffers hold the state: release the old ones
+  for (void* p : old_bufs) s->alloc.release(p);
+  return DEM_OK;
 }
 
 dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
@@ -1396,6 +1436,7 @@ dem_status dem_find_contacts(const double* pos, const double* radius, const int3
   }
   if (!pos || !radius || !agg) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
   if (n > (int64_t(1) << 28)) return fail(nullptr, DEM_ERR_INVALID_ARG, "too many spheres");
+  if (require_device(nullptr) != DEM_OK) return DEM_ERR_DEVICE;
   double smax = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     if (!(radius[i] > 0) || !std::isfinite(radius[i])) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad radius");
@@ -1486,6 +1527,7 @@ dem_status dem_find_contacts_noalloc(const double* pos, const double* radius,
   *n_out = 0;
   if (n == 0) return DEM_OK;
   if (!pos || !radius || !agg) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  if (require_device(nullptr) != DEM_OK) return DEM_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int dev = 0;
   HIPCHK(nullptr, hipGetDevice(&dev));
@@ -1580,6 +1622,147 @@ dem_status dem_find_contacts_noalloc(const double* pos, const double* radius,
                        (int)n, pairs_out, cap);
     HIPCHK(nullptr, hipGetLastError());
     HIPCHK(nullptr, hipStreamSynchronize(st));
+  }
+  return DEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// contact forces of given sphere states (same-input test hook)
+// ---------------------------------------------------------------------------
+
+dem_status dem_contact_forces(const dem_params* params, int64_t n, const double* pos,
+                              const double* vel, const double* radius, const int32_t* agg,
+                              int64_t n_agg, const double* agg_mass, const double* agg_spin,
+                              int64_t n_old, const uint64_t* old_keys, const double* old_hist,
+                              double* force, double* torque, uint64_t* keys_out,
+                              double* hist_out, int64_t cap, int64_t* n_out) {
+  std::string why;
+  if (valid_params(params, &why) != DEM_OK) return fail(nullptr, DEM_ERR_INVALID_ARG, why);
+  if (!n_out || n <= 0 || n_agg <= 0 || cap < 0 || n_old < 0 || !pos || !vel || !radius ||
+      !agg || !agg_mass || !agg_spin || !force || !torque || (cap > 0 && (!keys_out || !hist_out)) ||
+      (n_old > 0 && (!old_keys || !old_hist)))
+    return fail(nullptr, DEM_ERR_INVALID_ARG, "bad argument");
+  if (n > (int64_t(1) << 28) || n_agg > n) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad size");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(radius[i] > 0) || !std::isfinite(radius[i]) || agg[i] < 0 || agg[i] >= n_agg)
+      return fail(nullptr, DEM_ERR_INVALID_ARG, "bad radius or aggregate id");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(pos[3 * i + k]) || !std::isfinite(vel[3 * i + k]))
+        return fail(nullptr, DEM_ERR_INVALID_ARG, "non-finite position or velocity");
+  }
+  for (int64_t a = 0; a < n_agg; ++a) {
+    if (!(agg_mass[a] > 0) || !std::isfinite(agg_mass[a]))
+      return fail(nullptr, DEM_ERR_INVALID_ARG, "aggregate mass must be finite and > 0");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(agg_spin[3 * a + k])) return fail(nullptr, DEM_ERR_INVALID_ARG, "bad spin");
+  }
+  for (int64_t p = 0; p < n_old; ++p) {
+    const uint64_t key = old_keys[p];
+    const int64_t i = int64_t(key >> 32), j = int64_t(key & 0xffffffffu);
+    if (i >= n || j <= i || j >= n + params->n_walls || (p > 0 && key <= old_keys[p - 1]))
+      return fail(nullptr, DEM_ERR_INVALID_ARG, "old keys must be canonical and sorted");
+  }
+  if (require_device(nullptr) != DEM_OK) return DEM_ERR_DEVICE;
+  dem_params p = *params;
+  p.G = 0.0;                       // contacts only
+  if (p.max_contacts_per_sphere <= 0) p.max_contacts_per_sphere = 16;
+  dem_sim* s = nullptr;
+  dem_status r = dem_create(&p, nullptr, nullptr, &s);
+  if (r != DEM_OK) return r;
+  struct Guard {
+    dem_sim* s;
+    ~Guard() { dem_destroy(s); }
+  } guard{s};
+  if (n_old > int64_t(s->c_max) * n) return fail(nullptr, DEM_ERR_CAPACITY, "too many old contacts");
+  double s_cut, s_small;
+  int n_big;
+  split_big(radius, n, &s_cut, &s_small, &n_big);
+  r = alloc_pile(s, n_agg, n);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  PileDev& h = s->h;
+  h.given = 1;
+  h.cell_min = 2.0 * s_small;
+  h.s_cut = s_cut;
+  h.s_small = s_small;
+  h.n_big = n_big;
+  if (p.periodic) h.n_periodic = periodic_cells(p.box[0], h.cell_min, h.bits);
+  hipStream_t st = nullptr;
+  auto put_cols = [&](double* d, const double* host, int k, int64_t m) -> hipError_t {
+    std::vector<double> col(size_t(k) * m);
+    for (int64_t i = 0; i < m; ++i)
+      for (int c = 0; c < k; ++c) col[size_t(c) * m + i] = host[i * k + c];
+    hipError_t e = hipMemcpyAsync(d, col.data(), col.size() * 8, hipMemcpyHostToDevice, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+  };
+  HIPCHK(s, put_cols(h.r, pos, 3, n));
+  HIPCHK(s, put_cols(h.v, vel, 3, n));
+  HIPCHK(s, put_cols(h.wA, agg_spin, 3, n_agg));
+  HIPCHK(s, hipMemcpy(h.s, radius, n * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemcpy(h.agg, agg, n * 4, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemcpy(h.M, agg_mass, n_agg * 8, hipMemcpyHostToDevice));
+  // the previous contact list (parity 0) with its spring history
+  std::vector<uint32_t> off(n + 1, 0), pj(std::max<int64_t>(n_old, 1));
+  for (int64_t q = 0; q < n_old; ++q) {
+    off[(old_keys[q] >> 32) + 1]++;
+    pj[q] = uint32_t(old_keys[q] & 0xffffffffu);
+  }
+  for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+  HIPCHK(s, hipMemcpy(h.up_off[0], off.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+  if (n_old) {
+    HIPCHK(s, hipMemcpy(h.pair_j[0], pj.data(), n_old * 4, hipMemcpyHostToDevice));
+    std::vector<double> col(n_old);
+    for (int c = 0; c < kHist; ++c) {
+      for (int64_t q = 0; q < n_old; ++q) col[q] = old_hist[q * kHist + c];
+      HIPCHK(s, hipMemcpy(h.hist[0] + size_t(c) * h.cap_pairs, col.data(), n_old * 8,
+                          hipMemcpyHostToDevice));
+    }
+  }
+  launch_fill_u32(st, h.cell_cnt, 0u, s->sz.cells + 1);
+  r = ensure_own_table(s);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  HIPCHK(s, put_entry(s, s->own.d_table, st));
+  r = rebuild(s->own, st, s);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  // one evaluation pass without motion, gravity or the aggregate reduction
+  Batch& b = s->own;
+  launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_grid(st, b.d_table, 1, kModeInit, p.dt);
+  launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
+              b.max_items_cells);
+  launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
+  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 0);
+  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
+              b.max_items_pairs);
+  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
+  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 1);
+  launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
+  launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  HIPCHK(s, hipGetLastError());
+  PileDev tmp;
+  HIPCHK(s, hipMemcpyAsync(&tmp, b.d_table, sizeof(PileDev), hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> off1(n + 1);
+  HIPCHK(s, hipMemcpyAsync(off1.data(), h.up_off[1], (n + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  const int64_t total = off1[n];
+  *n_out = total;
+  if (tmp.status & kStCapacity) return fail(nullptr, DEM_ERR_CAPACITY, "contact capacity exceeded");
+  if (tmp.status != 0) return fail(nullptr, DEM_ERR_UNSTABLE, "non-finite force or bad positions");
+  r = fetch_rows(s, h.F, 3, n, force, st);
+  if (r == DEM_OK) r = fetch_rows(s, h.tau, 3, n, torque, st);
+  if (r != DEM_OK) return fail(nullptr, r, s->err);
+  if (cap > 0 && total > 0) {
+    std::vector<uint32_t> pj1(total);
+    HIPCHK(s, hipMemcpy(pj1.data(), h.pair_j[1], total * 4, hipMemcpyDeviceToHost));
+    std::vector<double> hh(size_t(kHist) * h.cap_pairs);
+    HIPCHK(s, hipMemcpy(hh.data(), h.hist[1], hh.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i)
+      for (uint32_t q = off1[i]; q < off1[i + 1] && q < cap; ++q) {
+        keys_out[q] = (uint64_t(i) << 32) | pj1[q];
+        for (int c = 0; c < kHist; ++c) hist_out[q * kHist + c] = hh[size_t(c) * h.cap_pairs + q];
+      }
   }
   return DEM_OK;
 }

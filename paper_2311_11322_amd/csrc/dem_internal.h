@@ -85,7 +85,8 @@ struct PileDev {
   // each; s_small is the largest radius of the others
   double s_cut, s_small;
   int32_t n_big;
-  int32_t pad4;
+  int32_t given;             // 1: sphere positions and velocities are given (no rigid bodies
+                             // to reconstruct them from; stateless test hooks)
   // uniform field and container walls (host-set)
   int32_t n_walls;
   int32_t pad3;

@@ -278,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(PileDev* __restrict__ pile
 // ---------------------------------------------------------------------------
 
 // One thread per sphere: r_i = r_A + R b_i and v_i = vpred_A + w_A x (R b_i)
-// (a pile without aggregates keeps the positions it was given).  Each block
+// (a pile without aggregates, or with given sphere states, keeps the
+// positions and velocities it was given).  Each block
 // also writes the bounding box and mass moments of its spheres
 // for the per-pile cell grid.
 __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restrict__ piles,
@@ -290,8 +291,8 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
   const int ns = P.ns, na = P.na, nxt = P.parity ^ 1;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double mom[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < ns && na == 0) {
-    // positions given directly (stateless contact search): bbox only
+  if (i < ns && (na == 0 || P.given)) {
+    // positions given directly (stateless hooks): bbox only
     for (int k = 0; k < 3; ++k) {
       const double x = P.r[k * ns + i];
       lo[k] = x;

@@ -1,6 +1,6 @@
 // kernels_contact.hip -- cell-list binning, contact search that skips pairs
 // inside one aggregate, and the per-contact soft-sphere force with spring
-// history (Sec. 2.1 and 2.2.5 of the paper; lever arm Eq. 8, contact-point
+// history (Sec. 2.1, 2.2.4 and 2.2.5 of the paper; lever arm Eq. 8, contact-point
 // torque Eq. 9).
 //
 // Binning is a counting sort on Morton cell codes: integer atomics build the

@@ -1,7 +1,7 @@
 // kernels_force.hip -- soft-sphere contact force of every contact, with the
 // spring history carried from the previous step (Sec. 2.1: spring-dashpot
 // normal and tangential forces, static friction, rolling and twisting
-// friction, history kept while the contact lasts; Sec. 2.2.5: forces act at
+// friction, history kept while the contact lasts; Sec. 2.2.4: forces act at
 // the contact point, lever arm of Eq. 8, torque of Eq. 9).
 //
 // One thread per contact (i, j) of the canonical upper list (j > i, runs
@@ -134,7 +134,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PileDev* __restrict__ piles,
         if (dz > hL) dz -= L;
         else if (dz < -hL) dz += L;
       }
-      const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+      // |d| from d^2 = (dx*dx + dy*dy) + dz*dz rounded step by step, as the
+      // contact search forms it (no fused multiply-add)
+      const double dist = sqrt(
+          __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
       const double sj = P.s[j];
       delta_d = (si + sj) - dist;
       li_d = (si * si - sj * sj + dist * dist) / (2.0 * dist);

@@ -121,6 +121,9 @@ def lib():
         L.dem_find_contacts.argtypes = [_PD, _PD, _PI32, C.c_int64, _PD, _PU64, C.c_int64, _PI64]
         L.dem_find_contacts_noalloc.argtypes = [vp, vp, vp, C.c_int64, _PD, vp, C.c_int64, _PI64,
                                                 vp]
+        L.dem_contact_forces.argtypes = [C.POINTER(dem_params), C.c_int64, _PD, _PD, _PD, _PI32,
+                                         C.c_int64, _PD, _PD, C.c_int64, _PU64, _PD, _PD, _PD,
+                                         _PU64, _PD, C.c_int64, _PI64]
         L.dem_destroy.argtypes = [vp]
         L.dem_last_error.argtypes = [vp]
         L.dem_last_error.restype = C.c_char_p
@@ -144,7 +147,7 @@ def lib():
                      "dem_engine_create", "dem_engine_attach", "dem_engine_step",
                      "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
                      "dem_set_profiling", "dem_get_profile", "dem_set_tuning",
-                     "dem_get_forcing", "dem_find_contacts_noalloc"):
+                     "dem_get_forcing", "dem_find_contacts_noalloc", "dem_contact_forces"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -409,6 +412,34 @@ def find_contacts(pos, radius, agg, box=None) -> np.ndarray:
     _check(lib().dem_find_contacts(_p(pos), _p(radius), _p(agg, _PI32), n, _p(bx),
                                    _p(keys, _PU64), cap, C.byref(nout)))
     return keys[:nout.value].copy()
+
+
+def contact_forces(params: Dict, pos, vel, radius, agg, agg_mass, agg_spin, old_keys=None,
+                   old_hist=None, precision: int = PREC_FP64) -> Dict:
+    """Contact forces of given sphere states on the device (same-input hook):
+    per-sphere force and torque, the new contact keys and their history."""
+    prm = make_params(params, precision)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    agg = np.ascontiguousarray(agg, dtype=np.int32)
+    agg_mass = np.ascontiguousarray(agg_mass, dtype=np.float64)
+    agg_spin = np.ascontiguousarray(agg_spin, dtype=np.float64)
+    ok = np.zeros(0, np.uint64) if old_keys is None else np.ascontiguousarray(old_keys, np.uint64)
+    oh = np.zeros((0, 7)) if old_hist is None else np.ascontiguousarray(old_hist, np.float64)
+    n = radius.shape[0]
+    cap = 16 * n
+    F = np.zeros((n, 3))
+    T = np.zeros((n, 3))
+    keys = np.zeros(cap, np.uint64)
+    hist = np.zeros((cap, 7))
+    nout = C.c_int64()
+    _check(lib().dem_contact_forces(C.byref(prm), n, _p(pos), _p(vel), _p(radius), _p(agg, _PI32),
+                                    agg_mass.shape[0], _p(agg_mass), _p(agg_spin), ok.shape[0],
+                                    _p(ok, _PU64), _p(oh), _p(F), _p(T), _p(keys, _PU64),
+                                    _p(hist), cap, C.byref(nout)))
+    k = nout.value
+    return {"F": F, "tau": T, "keys": keys[:k].copy(), "hist": hist[:k].copy()}
 
 
 def find_contacts_noalloc(pos, radius, agg, box=None, out=None, stream=None):

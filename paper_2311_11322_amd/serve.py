@@ -261,9 +261,11 @@ class Server:
 
 def request_stream(seed: int, n_requests: int, rate_per_s: float, nmin: int = 1000,
                    nmax: int = 50000, smin: int = 100, smax: int = 5000,
-                   kinds=("collapse", "spinup", "flyby"), workers: int = 0) -> List[Request]:
+                   kinds=("collapse", "spinup", "flyby"), workers: int = 0,
+                   executor=None) -> List[Request]:
     """Poisson arrivals at ``rate_per_s``; sphere counts and step counts
-    log-uniform; kind uniform.  Inputs are generated up front."""
+    log-uniform; kind uniform.  Inputs are generated up front (in ``workers``
+    processes, or on an existing process pool ``executor``)."""
     from . import workloads as W
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_per_s, n_requests)
@@ -274,7 +276,9 @@ def request_stream(seed: int, n_requests: int, rate_per_s: float, nmin: int = 10
     seeds = rng.integers(2 ** 31, size=n_requests)
     jobs = [(k, int(seeds[k]), max(1, int(round(n_sph[k] / 4.5))), 1, 8, 0.15, 5e-4, int(steps[k]),
              1.0, 0.5, 1e-6 if kind[k] == "spinup" else 0.0) for k in range(n_requests)]
-    if workers and workers > 1:
+    if executor is not None:
+        wl = list(executor.map(W._one_pile, jobs, chunksize=1))
+    elif workers and workers > 1:
         from concurrent.futures import ProcessPoolExecutor
         with ProcessPoolExecutor(max_workers=workers) as ex:
             wl = list(ex.map(W._one_pile, jobs, chunksize=1))

@@ -532,13 +532,15 @@ def _one_pile(args):
 def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 20000,
                cmin: int = 1, cmax: int = 8, phi0: float = 0.15, dt: float = 5e-4,
                n_steps: int = 800, spin_rate_per_step2: float = 1e-6,
-               G: float = 1.0, soft_frac: float = 0.5, workers: int = 0) -> List[Workload]:
+               G: float = 1.0, soft_frac: float = 0.5, workers: int = 0,
+               executor=None) -> List[Workload]:
     """Independent piles with log-uniform sphere counts in [nmin, nmax].
 
     Each pile is a cloud of aggregates packed at phi0 about the origin; the
     spin-up forcing (constant spin increment per step) is recorded in the
     params of every pile.  ``workers`` > 1 generates piles in parallel
-    processes (same result: every pile has its own seed).
+    processes, or ``executor`` (an existing process pool) does (same result:
+    every pile has its own seed).
     """
     rng = np.random.default_rng(seed)
     targets = np.floor(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_piles))).astype(int)
@@ -548,6 +550,8 @@ def pile_batch(seed: int = 3, n_piles: int = 256, nmin: int = 500, nmax: int = 2
         n_agg = max(1, int(round(nt / (0.5 * (cmin + cmax)))))
         jobs.append((k, prng_seed, n_agg, cmin, cmax, phi0, dt, n_steps, G, soft_frac,
                      spin_rate_per_step2))
+    if executor is not None:
+        return list(executor.map(_one_pile, jobs, chunksize=1))
     if workers and workers > 1:
         from concurrent.futures import ProcessPoolExecutor
         with ProcessPoolExecutor(max_workers=workers) as ex:
@@ -673,7 +677,7 @@ def fixture_system(shapes, centres, s=1.0, vel=None, spin=None, rot=None,
 
 
 # --------------------------------------------------------------------------
-# walled workloads: box filling (Sec. 3.2) and the Brazil-nut effect (Sec. 4.3)
+# walled workloads: box filling (Sec. 3.3) and the Brazil-nut effect (Sec. 4.3)
 # --------------------------------------------------------------------------
 
 MIXED_SHAPES = ("dumbbell", "diamond", "tetrahedron", "rod", "cube")

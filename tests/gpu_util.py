@@ -116,21 +116,38 @@ def compare_states(sim, o: O.Oracle, box=None, tol=1e-12, with_pairs=True):
         # the contact forces inherit the overlap's conditioning: each contact
         # force carries an error of k_n times a few ulp of |r| (the spring
         # history's bound), a sphere sums up to z of them, and the largest
-        # force is at least k_n max(delta); carried into torques,
-        # accelerations and the velocities and spins they change (the
-        # spheres' predicted velocities are built from both)
+        # force is at least k_n max(delta); so forces, torques, accelerations
+        # and aggregate torques carry `cond` relative to their scales
         ns = s["r"].shape[0]
         z = np.bincount(np.concatenate([op["i"], op["j"][op["j"] < ns]]), minlength=ns)
         cond = hist_tolerance(s["r"], op["diag"][:, 4]) * max(1.0, float(z.max()))
-        for k in ("sph_force", "sph_torque", "agg_acc", "agg_torque", "agg_vel", "agg_spin",
-                  "sph_vel"):
+        for k in ("sph_force", "sph_torque", "agg_acc", "agg_torque"):
             tols[k] = max(tol, cond)
+        # a step changes a velocity by h a and a spin by h N / I, so those
+        # carry the same relative error times the size of that change over
+        # the size of the velocity (spin) itself; a sphere's predicted
+        # velocity adds the spin's error times its lever |R b|
+        # (a system at rest is compared relative to the change itself)
+        h = o.dt
+        dv = h * mx(AF)
+        dw = h * mx(AT / a["I"].min(axis=1))
+        dvi = dv + dw * mx(np.linalg.norm(s["b"], axis=1))
+        w_ora = space_spin(a["q"], a["wb"])
+        for k, d, ora, gpu in (("agg_vel", dv, a["vA"], g["agg_vel"]),
+                               ("agg_spin", dw, w_ora, g["agg_spin"]),
+                               ("sph_vel", dvi, s["v"], g["sph_vel"])):
+            scale = max(mx(np.abs(ora)), d)
+            if scale > 0.0:
+                errs[k] = rel_err(gpu, ora, scale=scale)
+                tols[k] = max(tol, cond * d / scale)
     if with_pairs:
         keys = oracle_keys(o)
         assert np.array_equal(g["pair_keys"], keys), "contact lists differ"
         if keys.size:
             errs["pair_hist"] = rel_err(g["pair_hist"], op["hist"])
             tols["pair_hist"] = max(tol, hist_tolerance(s["r"], op["diag"][:, 4]))
+    print("parity (error / bound):",
+          ", ".join(f"{k} {v:.2e}/{tols[k]:.1e}" for k, v in errs.items()), flush=True)
     bad = {k: (v, tols[k]) for k, v in errs.items() if not v <= tols[k]}
-    assert not bad, f"parity above {tol}: {bad}"
+    assert not bad, f"parity above its bound: {bad}"
     return errs

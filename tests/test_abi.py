@@ -66,3 +66,22 @@ def test_parameter_validation_on_host():
     f2 = dem.footprint_bytes(good, 2000, 9000)
     assert 0 < f1 < f2
     assert f1 > 4500 * 500
+
+
+@pytest.mark.skipif(not os.path.exists(LIB) or os.path.exists("/dev/kfd"),
+                    reason="needs the built library on a machine without a GPU")
+def test_no_device_fails_loudly():
+    """Without a device the first call that needs one reports DEVICE with a
+    message (not an allocation failure)."""
+    import numpy as np
+    from paper_2311_11322_amd import dem
+    from paper_2311_11322_amd import workloads as W
+    w = W.periodic_box(3, n_agg=5)
+    sim = dem.Sim(w.params)
+    with pytest.raises(dem.DemError) as ei:
+        sim.add_workload(w)
+    assert ei.value.code == dem.DEM_ERR_DEVICE
+    assert "device" in str(ei.value)
+    with pytest.raises(dem.DemError) as ei:
+        dem.find_contacts(w.pos, w.radius, np.zeros(w.n_sph, np.int32))
+    assert ei.value.code == dem.DEM_ERR_DEVICE

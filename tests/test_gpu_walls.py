@@ -190,3 +190,82 @@ def test_brazil_nut_full_size_parity(D):
     sim.step(30)
     o.step(30)
     compare_states(sim, o, tol=1e-10)
+
+
+def test_walled_checkpoint_restore_bit_identical(D):
+    """A box fill with floor and wall contacts checkpointed after 3 steps
+    and restored into a fresh system (wall partners n_sph + w in the keys)
+    continues bit for bit like the uninterrupted run."""
+    say("walled checkpoint/restore")
+    w = _small_box(seed=4)
+    a = D.Sim(w.params)
+    a.add_workload(w)
+    a.step(3)
+    ck = a.checkpoint()
+    assert (ck["pair_keys"] & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)).any()
+    a.step(5)
+    ref = a.read_state(pairs=True)
+    b = D.Sim(w.params)
+    b.add_workload(w)
+    b.restore(ck)
+    b.step(5)
+    got = b.read_state(pairs=True)
+    for k in ("agg_pos", "agg_vel", "agg_acc", "agg_torque", "agg_quat", "pair_keys", "pair_hist",
+              "sph_force"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def _walled_lattice():
+    """Lone unit spheres stacked 6 x 6 x 8 in a box whose side walls and
+    floor they touch, falling onto each other: the contacts grow from about
+    1.1 to 2.8 per sphere within a few steps."""
+    B = 11.998
+    g = np.arange(6) * 2.0 + 0.999
+    z = np.arange(8) * 2.01 + 0.999
+    pos = np.stack(np.meshgrid(g, g, z, indexing="ij"), -1).reshape(-1, 3)
+    n = len(pos)
+    prm = dict(W.CONTACT_PARAMS, dt=5e-4, G=0.0, soft_frac=0.5, periodic=0, box=(0, 0, 0),
+               g=(0.0, 0.0, -2.0), walls=W.open_box_walls(B, B))
+    vel = np.zeros((n, 3))
+    vel[:, 2] = -1.0
+    one = np.ones(n)
+    return W.Workload("walled lattice", np.ones(n, np.int32), pos, one, W.sphere_mass(one), vel,
+                      np.zeros((n, 3)), prm, 1)
+
+
+def test_walled_capacity_overflow_then_reserve(D):
+    """A walled system with room for two contacts per sphere overflows
+    (CAPACITY, state rolled back to the failing step's start); growing the
+    capacity keeps every contact's spring history, wall contacts included,
+    and the run then continues bit for bit like a roomy one."""
+    say("walled capacity overflow + reserve")
+    w = _walled_lattice()
+    small = D.Sim(w.params, max_contacts=2)
+    small.add_workload(w)
+    code = None
+    for _ in range(40):
+        try:
+            small.step(1)
+        except D.DemError as e:
+            code = e.code
+            break
+    assert code == D.DEM_ERR_CAPACITY
+    st = small.read_state(["agg_pos"], pairs=True)
+    k = st["step"]
+    assert k >= 1 and (st["pair_keys"] & np.uint64(0xFFFFFFFF) >= np.uint64(w.n_sph)).any()
+    ref = D.Sim(w.params, max_contacts=16)
+    ref.add_workload(w)
+    ref.step(k)
+    rs = ref.read_state(["agg_pos"], pairs=True)
+    for f in ("agg_pos", "pair_keys", "pair_hist"):
+        assert np.array_equal(st[f], rs[f]), f
+    small.reserve_contacts(16)
+    got = small.read_state(["agg_pos"], pairs=True)
+    for f in ("agg_pos", "pair_keys", "pair_hist"):
+        assert np.array_equal(got[f], rs[f]), f
+    small.step(10)
+    ref.step(10)
+    a, b = small.read_state(pairs=True), ref.read_state(pairs=True)
+    assert a["n_pairs"] > 2 * w.n_sph
+    for f in ("agg_pos", "agg_vel", "pair_keys", "pair_hist", "sph_force"):
+        assert np.array_equal(a[f], b[f]), f

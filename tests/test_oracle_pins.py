@@ -298,6 +298,59 @@ def test_torque_free_asymmetric_conserves_L_and_energy():
     assert abs(0.5 * np.dot(wb, I * wb) - E0) < 1e-10
 
 
+def _euler_closed_form(I, w0, t):
+    """Torque-free body-frame spin of an asymmetric body, I1 < I2 < I3, with
+    L^2 > 2 E I2 (the spin circulates about the axis of largest moment):
+    w1 = A1 cn(u), w2 = A2 sn(u), w3 = A3 dn(u), u = lam t + u0, the
+    textbook solution of Euler's equations by Jacobi elliptic functions.
+    Amplitudes and rate from the two invariants 2E = sum I w^2 and
+    L^2 = sum I^2 w^2; u0 from the initial phase by the incomplete integral
+    of the first kind."""
+    from scipy.special import ellipj, ellipkinc
+    I1, I2, I3 = I
+    E2 = float(np.dot(I, w0 * w0))
+    L2 = float(np.dot(I * I, w0 * w0))
+    assert I1 < I2 < I3 and L2 > E2 * I2
+    A1 = math.sqrt((E2 * I3 - L2) / (I1 * (I3 - I1)))
+    A3 = math.copysign(math.sqrt((L2 - E2 * I1) / (I3 * (I3 - I1))), w0[2])
+    lam = math.sqrt((I3 - I2) * (L2 - E2 * I1) / (I1 * I2 * I3))
+    A2 = (I3 - I1) * A3 * A1 / (I2 * lam)
+    m = (I2 - I1) * (E2 * I3 - L2) / ((I3 - I2) * (L2 - E2 * I1))
+    phi0 = math.atan2(w0[1] / A2, w0[0] / A1)
+    u0 = ellipkinc(phi0, m)
+    sn, cn, dn, _ = ellipj(lam * np.asarray(t) + u0, m)
+    return np.stack([A1 * cn, A2 * sn, A3 * dn], -1)
+
+
+def test_torque_free_asymmetric_matches_jacobi_elliptic_solution():
+    """V7 for a body with three different moments: the RK5 spin follows the
+    Jacobi-elliptic closed form over several tumbling periods, and the
+    orientation carries the body-frame angular momentum I w_b(t) of that
+    closed form onto the fixed space-frame L (so the quaternion kinematics
+    are pinned too, not only Euler's equations)."""
+    I = np.array([1.0, 2.0, 3.5])
+    w0 = np.array([0.3, 1.7, -0.4])
+    q = np.array([0.9, 0.1, -0.3, 0.2])
+    q /= np.linalg.norm(q)
+    L0 = O.quat_matrix(q) @ (I * w0)
+    h, n_out, every = 1e-3, 20, 500            # 10 time units, ~3 tumbling periods
+    ts, got, Rs = [], [], []
+    wb = w0.copy()
+    for k in range(1, n_out + 1):
+        for _ in range(every):
+            q, wb, _ = O.rotate(q, wb, I, np.zeros(3), h)
+        ts.append(k * every * h)
+        got.append(wb.copy())
+        Rs.append(O.quat_matrix(q))
+    exact = _euler_closed_form(I, w0, np.array(ts))
+    assert np.abs(np.array(got) - exact).max() < 1e-9
+    # the spin really tumbles: w2 changes sign along the run
+    assert exact[:, 1].min() < -1.0 and exact[:, 1].max() > 1.0
+    for R, we in zip(Rs, exact):
+        # R(q(t)) I w_b(t) with the closed-form w_b is the fixed L
+        assert np.abs(R @ (I * we) - L0).max() < 1e-9
+
+
 def test_constant_torque_spin_up_about_principal_axis():
     """Constant space-frame torque along a principal axis of a body at rest:
     w(t) = N t / I exactly (linear), so RK5 is exact up to rounding."""

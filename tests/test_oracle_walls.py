@@ -1,6 +1,6 @@
 """Pins of the oracle's planar walls, uniform field and wall shaking.
 
-The box-filling and Brazil-nut workloads of the paper (Sec. 3.2 profiling,
+The box-filling and Brazil-nut workloads of the paper (Sec. 3.3 performance scaling,
 Sec. 4.3) put the spheres under a uniform gravitational field inside a
 container whose walls may oscillate sinusoidally.  The paper gives no wall
 model of its own; the oracle treats each wall as a contact partner of
