@@ -72,35 +72,133 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_sample, seconds_cap):
-    """FP64 oracle on the host: force evaluation (brute-force contacts and
-    direct-sum gravity at full N) of a sample of spheres, scaled to
-    sphere-steps/s (one step evaluates every sphere at the same cost)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                        "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(inp, n_sample, seconds_cap):
+    """The FP64 oracle on the host, as it stands: its gravity and sampled
+    evaluation loops are shared among threads with OpenMP (each target's sum
+    keeps its order, so the thread count changes no result).
+
+    * headline (collapse): the t0 force evaluation (brute-force contacts and
+      direct-sum gravity at full N) of a sample of spheres, on all allowed
+      cores and on one core, scaled by N to a whole step;
+    * cfg0 (the contact-only periodic box) run in full, 200 steps (no
+      gravity: the step is single-threaded);
+    * 8 of the spin-up piles, one step each, all cores."""
     import numpy as np
     import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    w = inp["collapse"]
     o = O.Oracle(w.params).add_workload(w, evaluate=False)
     rng = np.random.default_rng(0)
     idx = np.sort(rng.choice(w.n_sph, n_sample, replace=False))
-    done, t_used = 0, 0.0
-    chunk = 64
-    while done < n_sample and t_used < seconds_cap:
-        sl = idx[done:done + chunk]
+
+    def sampled(threads, cap_s):
+        used = O.set_threads(threads)
+        done, t_used, chunk = 0, 0.0, max(64, 16 * used)
+        while done < n_sample and t_used < cap_s:
+            sl = idx[done:done + chunk]
+            t0 = time.perf_counter()
+            o.eval_subset(sl)
+            t_used += time.perf_counter() - t0
+            done += len(sl)
+        return used, done, t_used
+
+    used_n, done_n, t_n = sampled(cores, seconds_cap / 2)
+    _, done_1, t_1 = sampled(1, seconds_cap / 2)
+    log(f"cpu baseline: {done_n} spheres on {used_n} threads in {t_n:.1f} s, "
+        f"{done_1} on 1 in {t_1:.1f} s")
+    out = {"value": round(done_n / t_n, 1), "unit": "sphere-steps/s", "cores": used_n,
+           "kind": "oracle",
+           "sample": f"t0 force evaluation of {done_n} of {w.n_sph} spheres of the collapse at "
+                     f"full N (brute-force contacts + direct-sum gravity, {used_n} OpenMP "
+                     f"threads, {t_n:.1f} s), scaled by N to a whole step",
+           "one_core": {"value": round(done_1 / t_1, 1), "cores": 1,
+                        "sample": f"{done_1} spheres, {t_1:.1f} s"},
+           "host_cores_allowed": cores, "cpu_model": _cpu_model()}
+    # cfg0 in full
+    w0 = inp.get("cfg0")
+    if w0 is not None:
+        O.set_threads(1)
         t0 = time.perf_counter()
-        o.eval_subset(sl)
-        t_used += time.perf_counter() - t0
-        done += len(sl)
-    per_sphere = t_used / done
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": 1.0 / per_sphere, "unit": "sphere-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"t0 force evaluation of {done} of {w.n_sph} spheres at full N "
-                      f"(brute-force contacts + direct-sum gravity, single thread, "
-                      f"{t_used:.1f} s), scaled by N to a whole step",
-            "host_cores_allowed": len(os.sched_getaffinity(0)), "cpu_model": model}
+        o0 = O.Oracle(w0.params).add_workload(w0)
+        o0.step(w0.n_steps)
+        t = time.perf_counter() - t0
+        out["cfg0"] = {"value": round(w0.n_sph * w0.n_steps / t, 1), "unit": "sphere-steps/s",
+                       "cores": 1, "steps": w0.n_steps, "seconds": round(t, 2),
+                       "contacts_at_end": o0.counts()[2],
+                       "sample": f"the whole run: {w0.n_steps} steps of {w0.n_sph} spheres "
+                                 "(set-up and t0 evaluation included)"}
+    # 8 of the spin-up piles, one step each
+    piles = inp.get("piles")
+    if piles:
+        used = O.set_threads(cores)
+        pick = np.sort(np.random.default_rng(8).choice(len(piles), min(8, len(piles)),
+                                                       replace=False))
+        t_sum, ss = 0.0, 0
+        for k in pick:
+            p = piles[int(k)]
+            op = O.Oracle(p.params).add_workload(p)
+            t0 = time.perf_counter()
+            op.step(1)
+            t_sum += time.perf_counter() - t0
+            ss += p.n_sph
+        out["cfg3_subset"] = {"value": round(ss / t_sum, 1), "unit": "sphere-steps/s",
+                              "cores": used, "piles": [int(k) for k in pick],
+                              "spheres": ss, "seconds": round(t_sum, 2),
+                              "sample": "one step of each of 8 spin-up piles (FP64 oracle, "
+                                        "brute-force contacts single-threaded, gravity on "
+                                        f"{used} threads)"}
+    O.set_threads(cores)
+    return out
+
+
+def prepare_inputs(args, workers, sections):
+    """Every CPU-side input, generated before anything touches the GPU, on
+    one process pool (its workers are forked from a process that has not
+    initialised a device)."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2311_11322_amd import serve
+    from paper_2311_11322_amd import workloads as W
+    t = time.time()
+    inp, fut = {}, {}
+    with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
+        if "big" in sections and args.big_agg > 0:
+            fut["big"] = ex.submit(W.collapse_cloud, 2, n_agg=args.big_agg)
+        if "headline" in sections:
+            fut["collapse"] = ex.submit(W.collapse_cloud, 1, n_agg=args.n_agg)
+            fut["cfg0"] = ex.submit(W.periodic_box, 0)
+        if "ablation" in sections:
+            fut["ablation"] = ex.submit(W.collapse_cloud, seed=5, n_agg=4444, cmin=1, cmax=8)
+        if "contact_path" in sections:
+            fut["lattices"] = [ex.submit(W.dense_lattice, n_side=n) for n in args.lattice_sides]
+        if "walled" in sections:
+            fut["fills"] = {sh: ex.submit(W.box_fill, seed=8, shape=sh)
+                            for sh in ("sphere", "dumbbell", "cube", "mixed")}
+            fut["boxes"] = [ex.submit(W.box_fill, seed=100 + k, shape="mixed")
+                            for k in range(args.box_batch)]
+            fut["brazil"] = ex.submit(W.brazil_nut)
+        if "batched" in sections:
+            inp["piles"] = W.pile_batch(seed=3, n_piles=args.piles, executor=ex)
+        if "served" in sections and args.requests > 0:
+            inp["requests"] = serve.request_stream(seed=4, n_requests=args.requests,
+                                                   rate_per_s=20.0, executor=ex)
+        for k, f in fut.items():
+            if isinstance(f, dict):
+                inp[k] = {a: b.result() for a, b in f.items()}
+            elif isinstance(f, list):
+                inp[k] = [b.result() for b in f]
+            else:
+                inp[k] = f.result()
+    log(f"inputs generated in {time.time() - t:.1f} s on {workers} workers")
+    return inp
 
 
 def main():
@@ -115,12 +213,19 @@ def main():
     ap.add_argument("--n-agg", type=int, default=25000)
     ap.add_argument("--gravity-tile", type=int, default=0, help="0: library default")
     ap.add_argument("--cell-scale", type=float, default=1.0)
+    ap.add_argument("--full-run-steps", type=int, default=2000,
+                    help="steps of the whole-run leg of the headline workload (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline workload (skip FP32-force, batched and served)")
     ap.add_argument("--piles", type=int, default=256)
+    ap.add_argument("--settle-steps", type=int, default=5600,
+                    help="steps that collapse and settle each spin-up pile first "
+                         "(5600 x 5e-4 = 2 free-fall times of the packing-0.15 cloud)")
+    ap.add_argument("--campaign-steps", type=int, default=4000,
+                    help="step limit of the spin-up campaign to failure")
     ap.add_argument("--big-agg", type=int, default=100000,
                     help="aggregates of the FP32-force 500k-sphere gravity run (0: skip)")
     ap.add_argument("--requests", type=int, default=200)
@@ -151,28 +256,35 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": args.calibrate_copy, "copies": 3}))
         return
-    from paper_2311_11322_amd import dem
-    from paper_2311_11322_amd import workloads as W
+    workers = min(16, len(os.sched_getaffinity(0)))
     if args.only:
-        dem.lib()
+        sections = {args.only}
+    else:
+        sections = {"headline"}
+        if not args.no_extra:
+            sections |= {"big", "ablation", "contact_path", "walled", "batched", "served"}
+        if not args.no_cpu_baseline:
+            sections |= {"batched"}
+    inp = prepare_inputs(args, workers, sections)
+    from paper_2311_11322_amd import dem
+    torch.cuda.init()
+    dem.lib()
+    if args.only:
         part = {}
-        workers = min(16, len(os.sched_getaffinity(0)))
         if args.only == "contact_path":
-            contact_path_run(args, part)
+            contact_path_run(args, inp, part)
         elif args.only == "batched":
-            batched_run(args, part, workers, plain=False)
+            batched_run(args, inp, part, plain=False)
         else:
-            walled_runs(args, part, workers)
+            walled_runs(args, inp, part)
         print(json.dumps(part), flush=True)
         return
 
-    t = time.time()
-    w = W.collapse_cloud(1, n_agg=args.n_agg)
-    log(f"workload: {w.n_agg} aggregates, {w.n_sph} spheres ({time.time() - t:.1f} s to place)")
+    w = inp["collapse"]
+    log(f"workload: {w.n_agg} aggregates, {w.n_sph} spheres")
     prec = dem.PREC_FP32_FORCE if args.precision == "fp32" else dem.PREC_FP64
     if args.gravity == "tree":
         w.params.update(gravity_tree=1, theta=0.5, tree_leaf=32, tree_order=4)
-    torch.cuda.init()
     alloc = dem.TorchAllocator(0)
     sim = dem.Sim(w.params, precision=prec, allocator=alloc, stream=dem.torch_stream())
     sim.set_tuning(args.gravity_tile, args.cell_scale)
@@ -257,12 +369,58 @@ def main():
         "roofline": roofline,
     }
     sim.close()
+    if not args.no_extra and args.full_run_steps > 0:
+        full_run(w, prec, args.full_run_steps, out)
+    cfg0_run(inp["cfg0"], out)
     if not args.no_extra:
-        extra_runs(args, w, out, prec)
+        extra_runs(args, inp, out, prec)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_sample, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def full_run(w, prec, steps, out):
+    """The whole run the collapse configuration names (2,000 steps from
+    rest), one graph replay per step, timed in ten chunks: sphere-steps/s
+    over the run, and the step time and contact count as the cloud falls in."""
+    from paper_2311_11322_amd import dem
+    sf = dem.Sim(w.params, precision=prec)
+    sf.add_workload(w)
+    chunk = max(1, steps // 10)
+    done, wall, trace = 0, 0.0, []
+    while done < steps:
+        k = min(chunk, steps - done)
+        t = timed_steps(sf, k)
+        wall += t
+        done += k
+        trace.append({"step": done, "ms_per_step": round(1e3 * t / k, 4),
+                      "contacts": sf.counts()[2]})
+    sf.close()
+    out["full_run"] = {"workload": f"the collapse above, all {steps} steps from rest, "
+                                   "graph replay",
+                       "value": round(w.n_sph * steps / wall, 1), "unit": "sphere-steps/s",
+                       "seconds": round(wall, 2), "trace": trace}
+    log(f"full run: {out['full_run']['value']:.4g} sphere-steps/s over {steps} steps")
+
+
+def cfg0_run(w0, out):
+    """The contact-only periodic box (500 aggregates of 1-8 spheres, packing
+    0.2, velocities N(0, 0.05), dt 1e-4), plain FP64, its whole 200-step run
+    replayed as graphs after a t0 evaluation."""
+    from paper_2311_11322_amd import dem
+    s0 = dem.Sim(w0.params)
+    s0.add_workload(w0)
+    c0 = s0.counts()[2]
+    wall = timed_steps(s0, w0.n_steps)
+    out["cfg0"] = {"workload": f"periodic box, {w0.n_agg} aggregates of 1-8 spheres "
+                               f"({w0.n_sph} spheres), packing 0.2, v ~ N(0, 0.05), dt=1e-4, "
+                               f"{w0.n_steps} steps, plain FP64",
+                   "value": round(w0.n_sph * w0.n_steps / wall, 1), "unit": "sphere-steps/s",
+                   "ms_per_step": round(1e3 * wall / w0.n_steps, 4),
+                   "contacts_at_t0": c0, "contacts_at_end": s0.counts()[2]}
+    s0.close()
+    log(f"cfg0: {out['cfg0']}")
 
 
 def timed_steps(sim, steps):
@@ -274,21 +432,14 @@ def timed_steps(sim, steps):
     return time.perf_counter() - t0
 
 
-def _box(seed_shape):
-    from paper_2311_11322_amd import workloads as W
-    seed, shape = seed_shape
-    return W.box_fill(seed=seed, shape=shape)
-
-
-def contact_path_run(args, out):
+def contact_path_run(args, inp, out):
     """The contact path alone on contact-dense periodic lattices (no
     gravity): every non-gravity kernel of the step, against the HBM roofline,
     at 125k spheres (launch-latency bound) and at 1M spheres."""
     from paper_2311_11322_amd import dem
     from paper_2311_11322_amd import workloads as W
     res = []
-    for n_side in args.lattice_sides:
-        wl = W.dense_lattice(n_side=n_side)
+    for wl in inp["lattices"]:
         sl = dem.Sim(wl.params)
         sl.add_workload(wl)
         sl.step(2)
@@ -318,19 +469,16 @@ def contact_path_run(args, out):
     out["contact_path"] = res[0] if len(res) == 1 else res
 
 
-def walled_runs(args, out, workers):
+def walled_runs(args, inp, out):
     """The box-filling profiling workload (6,400 unit spheres in a 40 x 40 x
     240 open-topped box under a uniform field; the first 10^4 steps of the
     fill, as profiled in the paper) for each aggregate shape, the member
     search ablation on it, many box fills batched in one engine, and the
     Brazil-nut set-up with shaken walls."""
-    from concurrent.futures import ProcessPoolExecutor
     from paper_2311_11322_amd import dem, serve
-    from paper_2311_11322_amd import workloads as W
     n_fill = args.fill_steps
     shapes = ("sphere", "dumbbell", "cube", "mixed")
-    with ProcessPoolExecutor(max_workers=max(1, min(workers, 8))) as ex:
-        fills = dict(zip(shapes, ex.map(_box, [(8, s) for s in shapes])))
+    fills = inp["fills"]
     per_shape = {}
     prof = None
     for shape in shapes:
@@ -368,8 +516,7 @@ def walled_runs(args, out, workers):
     # many box fills in one engine (seeds differ, mixed shapes)
     nb = args.box_batch
     if nb > 0:
-        with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
-            boxes = list(ex.map(_box, [(100 + k, "mixed") for k in range(nb)]))
+        boxes = inp["boxes"]
         steps_b = max(50, n_fill // 20)
         rb = serve.run_batch(boxes, steps_b, dem.PREC_FP64, warmup=2)
         for s in rb["sims"]:
@@ -380,7 +527,7 @@ def walled_runs(args, out, workers):
             "ms_per_step": round(rb["ms_per_step"], 4)}
         log(f"box fill batched: {out['box_fill']['batched']}")
     # Brazil-nut set-up, walls shaken at Froude number 3
-    wn = W.brazil_nut()
+    wn = inp["brazil"]
     sn = dem.Sim(wn.params)
     sn.add_workload(wn)
     sn.step(2)
@@ -398,11 +545,6 @@ def walled_runs(args, out, workers):
                                if not k.startswith("_")}}
     sn.close()
     log(f"brazil nut: {out['brazil_nut']}")
-
-
-def _big_collapse(n_agg):
-    from paper_2311_11322_amd import workloads as W
-    return W.collapse_cloud(2, n_agg=n_agg)
 
 
 def tree_run(w, steps, theta=0.5, leaf=32, order=4):
@@ -450,17 +592,44 @@ def big_run(args, out, wbig):
     log(f"tree 500k: {out['tree_500k']}")
 
 
-def batched_run(args, out, workers, plain=True):
-    """The spin-up piles in one engine, FP32-force, with the tuning the
-    autotuner picks (or, for a profiler run of this section alone, the
-    --gravity-tile / --cell-scale given); with ``plain``, also the same piles
-    in plain FP64 one at a time.  Returns the tuning."""
+def _one_at_a_time(piles, steps, precision, cache):
+    """Sphere-steps/s of the piles run one system at a time (each after a
+    warm-up step), summed over the piles' timed steps; each pile with the
+    tuning the autotuner picks for its size (one measurement per shape
+    bucket, cached)."""
     from paper_2311_11322_amd import dem, serve
-    from paper_2311_11322_amd import workloads as W
-    t = time.time()
-    piles = W.pile_batch(seed=3, n_piles=args.piles, workers=workers)
-    n_tot = sum(p.n_sph for p in piles)
-    log(f"{len(piles)} piles, {n_tot} spheres ({time.time() - t:.1f} s to place)")
+    t_sum = 0.0
+    for p in piles:
+        tune = serve.autotune([p], precision, steps=2, cell_scales=(1.0, 1.5), cache=cache)
+        sp = dem.Sim(p.params, precision=precision)
+        sp.set_tuning(tune["gravity_tile"], tune["cell_scale"])
+        sp.set_forcing(p.params["spin_dw"])
+        sp.add_workload(p)
+        sp.step(1)
+        t_sum += timed_steps(sp, steps)
+        sp.close()
+    return sum(p.n_sph for p in piles) * steps / t_sum
+
+
+def batched_run(args, inp, out, plain=True):
+    """The spin-up piles (Sec. 4.1 shape): each cloud first collapsed and
+    settled on the GPU (all piles in one engine, FP32-force, no forcing),
+    then spun up from its settled state.  Timed in one engine in the
+    FP32-force form with the tuning the autotuner picks (or, for a profiler
+    run of this section alone, the --gravity-tile / --cell-scale given);
+    per-kernel times of the batched step give the contact path's HBM
+    fraction.  With ``plain``, also the same piles batched in FP64 and one
+    at a time in both forms (the gain of batching apart from that of the
+    precision), and the whole spin-up campaign to each pile's failure (its
+    bulk radius grown by 5 %, the device's stop rule).  Returns the tuning."""
+    from paper_2311_11322_amd import dem, serve
+    clouds = inp["piles"]
+    n_tot = sum(p.n_sph for p in clouds)
+    t = time.perf_counter()
+    piles = serve.settle(clouds, args.settle_steps, dem.PREC_FP32_FORCE)
+    t_settle = time.perf_counter() - t
+    log(f"{len(piles)} piles, {n_tot} spheres, settled over {args.settle_steps} steps "
+        f"in {t_settle:.1f} s")
     if not plain and args.gravity_tile:
         tune = {"gravity_tile": args.gravity_tile, "cell_scale": args.cell_scale}
     else:
@@ -468,46 +637,82 @@ def batched_run(args, out, workers, plain=True):
     log(f"tuning: tile {tune['gravity_tile']}, cell scale {tune['cell_scale']}")
     bsteps = max(5, args.steps // 2)
     batch = serve.run_batch(piles, bsteps, dem.PREC_FP32_FORCE,
-                            tuning=(tune["gravity_tile"], tune["cell_scale"]), warmup=2)
+                            tuning=(tune["gravity_tile"], tune["cell_scale"]), warmup=2,
+                            profile=True)
     for s in batch["sims"]:
         s.close()
+    prof = batch["profile"]
+    kms = {k: v / prof["_steps"] for k, v in prof.items() if not k.startswith("_")}
+    contact_ms = sum(v for k, v in kms.items() if k != "gravity")
+    zbar = 2.0 * batch["contacts"] / n_tot
+    gbs = (CONTACT_BYTES_FIXED + CONTACT_BYTES_PER_CONTACT * zbar) * n_tot / (contact_ms * 1e-3) / 1e9
     out["batched"] = {
         "workload": f"{len(piles)} independent spin-up piles, 500-20000 spheres each "
-                    f"(log-uniform), {n_tot} spheres, FP32-force, one engine",
+                    f"(log-uniform), {n_tot} spheres, each a cloud at packing 0.15 collapsed and "
+                    f"settled on the GPU for {args.settle_steps} steps, spin ramp 1e-6 rad/step^2, "
+                    "FP32-force, one engine",
         "value": round(batch["sphere_steps_per_s"], 1), "unit": "sphere-steps/s",
         "ms_per_step": round(batch["ms_per_step"], 4),
         "gravity_pairs_per_step": batch["sum_n2"],
-        "tuning": {"gravity_tile": tune["gravity_tile"], "cell_scale": tune["cell_scale"]}}
+        "contacts": batch["contacts"],
+        "settle_seconds": round(t_settle, 1),
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in kms.items()},
+        "contact_path_roofline": {
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "algorithmic": f"{CONTACT_BYTES_FIXED} B + {CONTACT_BYTES_PER_CONTACT} B x z per "
+                           f"sphere-step (z = {zbar:.2f}) over the summed non-gravity kernel times"},
+        "tuning": {"gravity_tile": tune["gravity_tile"], "cell_scale": tune["cell_scale"],
+                   "candidates": len(tune.get("candidates", []))}}
     if plain:
-        # the same piles, FP64, one at a time
-        plain_time = 0.0
-        for p in piles:
-            sp = dem.Sim(p.params)
-            sp.add_workload(p)
-            sp.set_forcing(p.params["spin_dw"])
-            sp.step(1)
-            plain_time += timed_steps(sp, bsteps)
-            sp.close()
-        plain_value = n_tot * bsteps / plain_time
+        b64 = serve.run_batch(piles, bsteps, dem.PREC_FP64, warmup=2)
+        for s in b64["sims"]:
+            s.close()
+        cache = {}
+        one64 = _one_at_a_time(piles, bsteps, dem.PREC_FP64, cache)
+        one32 = _one_at_a_time(piles, bsteps, dem.PREC_FP32_FORCE, cache)
+        v32 = batch["sphere_steps_per_s"]
+        v64 = b64["sphere_steps_per_s"]
         out["batched"].update(
-            plain_fp64_one_pile_at_a_time=round(plain_value, 1),
-            speedup_vs_plain=round(batch["sphere_steps_per_s"] / plain_value, 2))
+            batched_fp64=round(v64, 1),
+            plain_fp64_one_pile_at_a_time=round(one64, 1),
+            fp32_force_one_pile_at_a_time=round(one32, 1),
+            speedup_vs_plain=round(v32 / one64, 2),
+            gain_of_batching={"fp64": round(v64 / one64, 2), "fp32_force": round(v32 / one32, 2)},
+            gain_of_precision={"batched": round(v32 / v64, 2),
+                               "one_at_a_time": round(one32 / one64, 2)})
+        camp = serve.spin_campaign(piles, dem.PREC_FP32_FORCE,
+                                   (tune["gravity_tile"], tune["cell_scale"]), stop_growth=1.05,
+                                   max_steps=args.campaign_steps)
+        import numpy as np
+        crit = []
+        for p, wf in zip(piles, camp["spin_at_failure"]):
+            if wf is None:
+                continue
+            m = p.mass
+            com = (m[:, None] * p.pos).sum(0) / m.sum()
+            R = math.sqrt(5.0 / 3.0 * float((m * ((p.pos - com) ** 2).sum(1)).sum() / m.sum()))
+            rho = float(m.sum()) / (4.0 / 3.0 * math.pi * R ** 3)
+            crit.append(wf / math.sqrt(4.0 * math.pi * p.params["G"] * rho / 3.0))
+        stf = [d for d in camp["steps_to_failure"] if d is not None]
+        out["batched"]["spin_campaign"] = {
+            "piles": camp["piles"], "stopped": camp["stopped"], "steps": camp["steps"],
+            "seconds": round(camp["seconds"], 2),
+            "sphere_steps_per_s": round(camp["sphere_steps_per_s"], 1),
+            "steps_to_failure_p50": float(np.percentile(stf, 50)) if stf else None,
+            "steps_to_failure_max": max(stf) if stf else None,
+            "spin_at_failure_over_nominal_critical_p50":
+                round(float(np.percentile(crit, 50)), 3) if crit else None}
     log(f"batched: {out['batched']}")
     return tune
 
 
-def extra_runs(args, w, out, prec):
+def extra_runs(args, inp, out, prec):
     """The FP32-force form on the same collapse, the batched spin-up piles
     (plain FP64 one pile at a time vs FP32-force batched in one engine) and
     a served request stream."""
-    import numpy as np
-    import torch
     from paper_2311_11322_amd import dem, serve
-    from paper_2311_11322_amd import workloads as W
-    workers = min(16, len(os.sched_getaffinity(0)))
-    from concurrent.futures import ProcessPoolExecutor
-    big_pool = ProcessPoolExecutor(max_workers=1) if args.big_agg > 0 else None
-    big_fut = big_pool.submit(_big_collapse, args.big_agg) if big_pool else None
+    w = inp["collapse"]
     # -- FP32-force form at 125k spheres
     if prec == dem.PREC_FP64:
         s32 = dem.Sim(w.params, precision=dem.PREC_FP32_FORCE)
@@ -529,10 +734,10 @@ def extra_runs(args, w, out, prec):
                            workload=f"collapse, {w.n_sph} spheres, tree gravity (multipoles to "
                                     "hexadecapole order), FP64")
         log(f"tree: {out['tree']}")
-    contact_path_run(args, out)
+    contact_path_run(args, inp, out)
     # -- the paper's efficiency experiment: original (full-scan) vs improved
     #    (contiguous) member search, on its collapse shape (2e4 spheres)
-    wa = W.collapse_cloud(seed=5, n_agg=4444, cmin=1, cmax=8)
+    wa = inp["ablation"]
     abl = {}
     for scan in (0, 1):
         sa = dem.Sim(wa.params)
@@ -550,14 +755,11 @@ def extra_runs(args, w, out, prec):
         "improved_reduce_ms": round(abl[0][1], 4), "original_reduce_ms": round(abl[1][1], 4),
         "speedup": round(abl[1][0] / abl[0][0], 3)}
     log(f"member search ablation: {out['member_search_ablation']}")
-    walled_runs(args, out, workers)
-    tune = batched_run(args, out, workers)
+    walled_runs(args, inp, out)
+    tune = batched_run(args, inp, out)
     # -- served stream
     if args.requests > 0:
-        t = time.time()
-        reqs = serve.request_stream(seed=4, n_requests=args.requests, rate_per_s=20.0,
-                                    workers=workers)
-        log(f"{len(reqs)} requests generated ({time.time() - t:.1f} s)")
+        reqs = inp["requests"]
         srv = serve.Server(64 << 30, precision=dem.PREC_FP32_FORCE, chunk_steps=50,
                            tuning=(tune["gravity_tile"], tune["cell_scale"]))
         st = srv.run(reqs)
@@ -610,13 +812,9 @@ def extra_runs(args, w, out, prec):
                 "makespan_s": round(st2["makespan_s"], 2), "completed": st2["completed"],
                 "failed": st2["failed"]}
             log(f"served at a sustainable rate: {out['served_sustainable']}")
-    # -- FP32-force gravity at 500k spheres, placed in the background meanwhile
-    if big_fut is not None:
-        t = time.time()
-        wbig = big_fut.result()
-        big_pool.shutdown()
-        log(f"big collapse: {wbig.n_sph} spheres (waited {time.time() - t:.1f} s)")
-        big_run(args, out, wbig)
+    # -- FP32-force gravity at 500k spheres
+    if "big" in inp:
+        big_run(args, out, inp["big"])
 
 
 if __name__ == "__main__":

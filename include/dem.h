@@ -44,7 +44,9 @@ typedef enum {
     DEM_ERR_CAPACITY = -3,     /* contact capacity exceeded; state rolled back to the failing step's start */
     DEM_ERR_UNSTABLE = -4,     /* non-finite force or overlap > max_overlap_frac*radius; rolled back */
     DEM_ERR_DEVICE = -5,       /* a HIP call failed */
-    DEM_ERR_STATE = -6         /* call out of order (e.g. adding aggregates after stepping) */
+    DEM_ERR_STATE = -6,        /* call out of order (e.g. adding aggregates after stepping) */
+    DEM_STOPPED = 1            /* not an error: the system's stop rule fired (dem_forcing);
+                                  its state is that at the start of the stopping step */
 } dem_status;
 
 typedef enum {
@@ -117,6 +119,15 @@ typedef struct {
     double pert_mass;          /* perturber mass; 0: no perturber */
     double pert_pos[3];        /* perturber position */
     double pert_vel[3];        /* perturber velocity */
+    double stop_growth;        /* > 0: stop rule of a spin-up run (Sec. 4.1: the pile has
+                                  failed once its bulk radius has grown by 5 %, i.e. 1.05):
+                                  the first evaluation after dem_set_forcing records the bulk
+                                  radius R0 = sqrt(5/3 <|r_i - r_com|^2>_m) of the sphere
+                                  centres; the first step whose evaluation finds
+                                  R >= stop_growth * R0 is not committed and the system stops
+                                  (dem_step / dem_sim_status report DEM_STOPPED, the step
+                                  index in dem_state.step).  Setting the forcing again
+                                  re-arms the rule and lets a stopped system go on. */
 } dem_forcing;
 
 /* State read-out / restore.  Caller-owned host buffers sized by
@@ -169,8 +180,9 @@ dem_status dem_add_aggregates(dem_sim* sim, int64_t n_agg, const int32_t* sphere
                               const double* agg_spin, int64_t* first_agg_id);
 
 /* Advance n_steps fixed steps (replays of one captured HIP graph).  Returns
- * after the work is complete.  On CAPACITY / UNSTABLE the state is that at
- * the start of the failing step and dem_state.step tells which step it is.
+ * after the work is complete.  On CAPACITY / UNSTABLE (and on DEM_STOPPED,
+ * the stop rule of dem_forcing) the state is that at the start of the
+ * failing step and dem_state.step tells which step it is.
  * STATE if the system is attached to an engine or has no aggregates. */
 dem_status dem_step(dem_sim* sim, int64_t n_steps);
 
@@ -279,13 +291,22 @@ dem_status dem_engine_create(size_t hbm_budget_bytes, void* hip_stream, dem_engi
  * budget; INVALID_ARG if its contact parameters or time step differ from
  * those already attached. */
 dem_status dem_engine_attach(dem_engine* eng, dem_sim* sim);
-/* Advance every attached system by n_steps.  A system that fails stops
- * (rolled back to its failing step) while the others continue; the return
- * value is the first failure code, and dem_sim_status tells which. */
+/* Advance every attached system by n_steps.  A system that fails (or whose
+ * stop rule fires) stops, rolled back to that step's start, while the others
+ * continue; the return value is the first failure code (a stopped system is
+ * not a failure), and dem_sim_status tells which. */
 dem_status dem_engine_step(dem_engine* eng, int64_t n_steps);
 dem_status dem_engine_detach(dem_engine* eng, dem_sim* sim);
 dem_status dem_engine_destroy(dem_engine* eng);
-/* Status of one system after an engine step (DEM_OK or the failure code). */
+/* Per-kernel timing of an engine's steps, as dem_set_profiling /
+ * dem_get_profile for one system (eager launches with a HIP event between
+ * consecutive kernels while enabled; totals in milliseconds in the order of
+ * dem_profile_names). */
+dem_status dem_engine_set_profiling(dem_engine* eng, int32_t enabled);
+dem_status dem_engine_get_profile(const dem_engine* eng, double* kernel_ms, int32_t n_max,
+                                  int64_t* n_steps);
+/* Status of one system after an engine step (DEM_OK, DEM_STOPPED or the
+ * failure code). */
 dem_status dem_sim_status(const dem_sim* sim);
 
 /* Launch-shape tuning of one system, set before dem_add_aggregates (the

@@ -192,7 +192,7 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
       L.add(reinterpret_cast<double**>(&h.gpart), z.precision == 1 ? (part_vals + 1) / 2 : part_vals);
     }
   }
-  L.add(&h.bpart, 10 * z.n_rblk);
+  L.add(&h.bpart, kBbox * z.n_rblk);
   L.add(&h.ppart, 3 * z.n_rblk);
   L.add(&h.grid, 1);
   L.add(&h.cell_cnt, z.cells + 1);          // + the cell of the big spheres
@@ -261,6 +261,10 @@ struct Batch {
   int n_seg_pairs = 0, n_item_pairs = 0, max_items_pairs = 0;
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
+  // gravity runs on a second stream beside the contact search and forces
+  // (fork after the cell sort, join before the per-sphere gather)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool dirty = true;
   ContactParams cp{};
   int precision = 0;
@@ -298,6 +302,11 @@ struct dem_engine {
   hipStream_t stream = nullptr;
   Batch batch;
   std::string err = "no error";
+  // per-kernel timing, as for a standalone system
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  std::vector<double> prof_ms;
+  int64_t prof_steps = 0;
 };
 
 namespace {
@@ -452,66 +461,107 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
 
 // Kernel families of one step, in launch order (profiling names).
 constexpr int kNumStages = 15;
+constexpr int kStageGravity = 11;
 const char* const kStageNames =
     "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;search_count;"
     "scan_pairs;search_write;pairs;gravity;gather;reduce;finish";
 
-// Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
-// mark(k) is called before stage k and mark(kNumStages) after the last.
-template <typename Mark>
-void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark) {
-  const int np = (int)b.members.size();
-  mark(0);
-  launch_integrate(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
-  mark(1);
-  launch_reconstruct(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(2);
-  launch_grid(st, b.d_table, np, mode, b.cp.dt);
-  mark(3);
-  launch_bin(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(4);
-  launch_scan(st, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
-              b.max_items_cells);
-  mark(5);
-  launch_scatter(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(6);
-  launch_cell_sort(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(7);
-  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 0);
-  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 0);
-  mark(8);
-  launch_scan(st, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
-              b.max_items_pairs);
-  mark(9);
-  launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
-  if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 1);
-  mark(10);
-  launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
-  mark(11);
-  if (b.any_grav) {
-    launch_gravity_records(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
-    for (int g = 0; g < b.n_grav_groups; ++g)
-      launch_gravity_tiles(st, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
-                           b.grav_tile[g]);
-    if (b.any_direct) launch_gravity_combine(st, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
-    if (b.any_tree) launch_tree(st, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
-                               b.n_sph_blk, b.tree_order);
-  }
-  mark(12);
-  launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
-  mark(13);
-  launch_reduce(st, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode, b.reduce_stage);
-  mark(14);
-  launch_finish(st, b.d_table, np, mode, b.cp.dt);
-  mark(15);
+// Second stream and fork/join events of a batch (default priority).
+hipError_t ensure_side(Batch& b) {
+  hipError_t e = hipSuccess;
+  if (!b.side) e = hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking);
+  if (e == hipSuccess && !b.fork_ev) e = hipEventCreateWithFlags(&b.fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess && !b.join_ev) e = hipEventCreateWithFlags(&b.join_ev, hipEventDisableTiming);
+  return e;
 }
 
-void enqueue_pass(Batch& b, hipStream_t st, int mode) {
-  enqueue_pass_marked(b, st, mode, [](int) {});
+void release_side(Batch& b) {
+  if (b.side) (void)hipStreamDestroy(b.side);
+  if (b.fork_ev) (void)hipEventDestroy(b.fork_ev);
+  if (b.join_ev) (void)hipEventDestroy(b.join_ev);
+  b.side = nullptr;
+  b.fork_ev = b.join_ev = nullptr;
+}
+
+// Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
+// mark(k, stream, begin) is called before (begin) and after each stage k on
+// the stream that runs it.  Gravity depends only on the sorted copies of the
+// cell sort and is read only by the gather, so with `overlap` it runs on the
+// batch's second stream beside the search, scan and force kernels (the
+// captured step); without, every stage runs in order on one stream (the
+// t0 evaluation, the stateless hooks, and the profiled passes, whose event
+// spans then time each stage alone).
+template <typename Mark>
+void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark, bool overlap) {
+  const int np = (int)b.members.size();
+  auto stage = [&](int k, hipStream_t s, auto&& launch) {
+    mark(k, s, true);
+    launch(s);
+    mark(k, s, false);
+  };
+  stage(0, st, [&](hipStream_t s) { launch_integrate(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode); });
+  stage(1, st, [&](hipStream_t s) { launch_reconstruct(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(2, st, [&](hipStream_t s) { launch_grid(s, b.d_table, np, mode, b.cp.dt); });
+  stage(3, st, [&](hipStream_t s) { launch_bin(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(4, st, [&](hipStream_t s) {
+    launch_scan(s, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
+                b.max_items_cells);
+  });
+  stage(5, st, [&](hipStream_t s) { launch_scatter(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(6, st, [&](hipStream_t s) { launch_cell_sort(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  const bool fork = overlap && b.any_grav && b.side;
+  auto gravity = [&](hipStream_t s) {
+    launch_gravity_records(s, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    for (int g = 0; g < b.n_grav_groups; ++g)
+      launch_gravity_tiles(s, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
+                           b.grav_tile[g]);
+    if (b.any_direct) launch_gravity_combine(s, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    if (b.any_tree) launch_tree(s, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
+                               b.n_sph_blk, b.tree_order);
+  };
+  if (fork) {
+    (void)hipEventRecord(b.fork_ev, st);
+    (void)hipStreamWaitEvent(b.side, b.fork_ev, 0);
+    stage(kStageGravity, b.side, gravity);
+    (void)hipEventRecord(b.join_ev, b.side);
+  }
+  stage(7, st, [&](hipStream_t s) {
+    launch_search(s, b.d_table, b.wl_sph, b.n_sph_blk, 0);
+    if (b.n_big_blk) launch_search_big(s, b.d_table, b.wl_big, b.n_big_blk, 0);
+  });
+  stage(8, st, [&](hipStream_t s) {
+    launch_scan(s, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
+                b.max_items_pairs);
+  });
+  stage(9, st, [&](hipStream_t s) {
+    launch_search(s, b.d_table, b.wl_sph, b.n_sph_blk, 1);
+    if (b.n_big_blk) launch_search_big(s, b.d_table, b.wl_big, b.n_big_blk, 1);
+  });
+  stage(10, st, [&](hipStream_t s) {
+    launch_pairs(s, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
+  });
+  if (fork) {
+    (void)hipStreamWaitEvent(st, b.join_ev, 0);
+  } else if (b.any_grav) {
+    stage(kStageGravity, st, gravity);
+  } else {
+    mark(kStageGravity, st, true);
+    mark(kStageGravity, st, false);
+  }
+  stage(12, st, [&](hipStream_t s) { launch_gather(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(13, st, [&](hipStream_t s) {
+    launch_reduce(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode, b.reduce_stage);
+  });
+  stage(14, st, [&](hipStream_t s) { launch_finish(s, b.d_table, np, mode, b.cp.dt); });
+}
+
+void enqueue_pass(Batch& b, hipStream_t st, int mode, bool overlap = false) {
+  enqueue_pass_marked(b, st, mode, [](int, hipStream_t, bool) {}, overlap);
 }
 
 dem_status ensure_graph(Batch& b, hipStream_t st, dem_sim* errsim) {
   if (b.graph) return DEM_OK;
+  HIPCHK(errsim, ensure_side(b));
   hipStream_t cap = st;
   bool own_stream = false;
   if (cap == nullptr) {
@@ -520,13 +570,47 @@ dem_status ensure_graph(Batch& b, hipStream_t st, dem_sim* errsim) {
     own_stream = true;
   }
   HIPCHK(errsim, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  enqueue_pass(b, cap, kModeStep);
+  enqueue_pass(b, cap, kModeStep, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(cap, &g);
   if (own_stream) (void)hipStreamDestroy(cap);
   if (e != hipSuccess) return fail(errsim, DEM_ERR_DEVICE, hip_msg(e, "graph capture"));
   b.graph_def = g;
   HIPCHK(errsim, hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0));
+  return DEM_OK;
+}
+
+// Eager launches of n_steps passes with a HIP event between consecutive
+// kernels on the stream; accumulates each kernel family's milliseconds.
+dem_status profiled_passes(Batch& b, hipStream_t st, int64_t n_steps,
+                           std::vector<hipEvent_t>& events, std::vector<double>& prof_ms,
+                           int64_t& prof_steps, dem_sim* errsim) {
+  const size_t per_step = size_t(2) * kNumStages;
+  const size_t need = size_t(n_steps) * per_step;
+  while (events.size() < need) {
+    hipEvent_t ev;
+    HIPCHK(errsim, hipEventCreate(&ev));
+    events.push_back(ev);
+  }
+  hipError_t rec = hipSuccess;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    hipEvent_t* ev = &events[size_t(k) * per_step];
+    enqueue_pass_marked(b, st, kModeStep, [&](int m, hipStream_t s, bool begin) {
+      if (rec == hipSuccess) rec = hipEventRecord(ev[2 * m + (begin ? 0 : 1)], s);
+    }, false);
+  }
+  HIPCHK(errsim, rec);
+  HIPCHK(errsim, hipStreamSynchronize(st));
+  prof_ms.resize(kNumStages, 0.0);
+  for (int64_t k = 0; k < n_steps; ++k) {
+    hipEvent_t* ev = &events[size_t(k) * per_step];
+    for (int m = 0; m < kNumStages; ++m) {
+      float ms = 0.f;
+      HIPCHK(errsim, hipEventElapsedTime(&ms, ev[2 * m], ev[2 * m + 1]));
+      prof_ms[m] += ms;
+    }
+  }
+  prof_steps += n_steps;
   return DEM_OK;
 }
 
@@ -628,6 +712,8 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.G = s->prm.G;
   h.soft_frac = s->prm.softening_frac;
   h.spin_dw = s->forcing.spin_dw;
+  h.stop_growth = s->forcing.stop_growth;
+  h.R0 = 0.0;
   h.tree = s->sz.tree ? 1 : 0;
   h.tree_leaf = s->prm.tree_leaf;
   h.theta = s->prm.tree_theta;
@@ -673,6 +759,7 @@ void copy_device_fields(PileDev& dst, const PileDev& src) {
   dst.step = src.step;
   dst.fail_step = src.fail_step;
   dst.n_pairs = src.n_pairs;
+  dst.R0 = src.R0;
   for (int q = 0; q < 2; ++q)
     for (int k = 0; k < 3; ++k) {
       dst.pert_r[q][k] = src.pert_r[q][k];
@@ -702,6 +789,7 @@ hipStream_t stream_of(const dem_sim* s) { return s->engine ? s->engine->stream :
 dem_status status_code(int st) {
   if (st & kStCapacity) return DEM_ERR_CAPACITY;
   if (st & kStUnstable) return DEM_ERR_UNSTABLE;
+  if (st & kStStopped) return DEM_STOPPED;
   return DEM_OK;
 }
 
@@ -857,7 +945,7 @@ NoAllocPlan plan_noalloc(char* base, int64_t n, PileDev& h) {
   h.xs = L.take<double>(4 * n);
   h.xg = L.take<SortedGeom>(n);
   h.sid = L.take<SortedId>(n);
-  h.bpart = L.take<double>(10 * q.n_blk);
+  h.bpart = L.take<double>(kBbox * q.n_blk);
   h.grid = L.take<Grid>(1);
   h.cell_cnt = L.take<uint32_t>(q.cells + 1);
   h.cell_start = L.take<uint32_t>(q.cells + 2);
@@ -923,6 +1011,7 @@ dem_status dem_destroy(dem_sim* s) {
   (void)hipStreamSynchronize(s->stream);
   for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
   free_meta(s->own);
+  release_side(s->own);
   if (s->own.d_table) (void)hipFree(s->own.d_table);
   release_pile(s);
   delete s;
@@ -1031,36 +1120,17 @@ dem_status dem_step(dem_sim* s, int64_t n_steps) {
   if (s->engine) return fail(s, DEM_ERR_STATE, "system is attached to an engine");
   if (!s->has_aggs) return fail(s, DEM_ERR_STATE, "no aggregates");
   if (n_steps < 0) return fail(s, DEM_ERR_INVALID_ARG, "negative step count");
-  if (s->h.status != 0) return fail(s, status_code(s->h.status), "system has failed; restore it");
+  if (s->h.status != 0) {
+    const dem_status code = status_code(s->h.status);
+    if (code == DEM_STOPPED) return DEM_STOPPED;   // reset the forcing to go on
+    return fail(s, code, "system has failed; restore it");
+  }
   s->stepped = true;
   if (n_steps == 0) return DEM_OK;
   if (s->profiling) {
-    // eager launches with an event between consecutive kernels
-    const size_t need = size_t(n_steps) * (kNumStages + 1);
-    while (s->events.size() < need) {
-      hipEvent_t ev;
-      HIPCHK(s, hipEventCreate(&ev));
-      s->events.push_back(ev);
-    }
-    hipError_t rec = hipSuccess;
-    for (int64_t k = 0; k < n_steps; ++k) {
-      hipEvent_t* ev = &s->events[size_t(k) * (kNumStages + 1)];
-      enqueue_pass_marked(s->own, s->stream, kModeStep, [&](int m) {
-        if (rec == hipSuccess) rec = hipEventRecord(ev[m], s->stream);
-      });
-    }
-    HIPCHK(s, rec);
-    HIPCHK(s, hipStreamSynchronize(s->stream));
-    s->prof_ms.resize(kNumStages, 0.0);
-    for (int64_t k = 0; k < n_steps; ++k) {
-      hipEvent_t* ev = &s->events[size_t(k) * (kNumStages + 1)];
-      for (int m = 0; m < kNumStages; ++m) {
-        float ms = 0.f;
-        HIPCHK(s, hipEventElapsedTime(&ms, ev[m], ev[m + 1]));
-        s->prof_ms[m] += ms;
-      }
-    }
-    s->prof_steps += n_steps;
+    dem_status st = profiled_passes(s->own, s->stream, n_steps, s->events, s->prof_ms,
+                                    s->prof_steps, s);
+    if (st != DEM_OK) return st;
   } else {
     dem_status st = ensure_graph(s->own, s->stream, s);
     if (st != DEM_OK) return st;
@@ -1069,10 +1139,16 @@ dem_status dem_step(dem_sim* s, int64_t n_steps) {
   HIPCHK(s, get_entry(s, s->own.d_table, s->stream));
   if (s->h.status != 0) {
     dem_status code = status_code(s->h.status);
-    char buf[160];
+    char buf[200];
     snprintf(buf, sizeof buf, "%s at step %lld; state is that at the start of that step",
-             code == DEM_ERR_CAPACITY ? "contact capacity exceeded" : "unstable contact",
+             code == DEM_ERR_CAPACITY  ? "contact capacity exceeded"
+             : code == DEM_STOPPED     ? "stop rule reached (bulk radius grown)"
+                                       : "unstable contact",
              (long long)s->h.fail_step);
+    if (code == DEM_STOPPED) {
+      s->err = buf;
+      return DEM_STOPPED;
+    }
     return fail(s, code, buf);
   }
   return DEM_OK;
@@ -1232,7 +1308,8 @@ dem_status dem_restore_state(dem_sim* s, const dem_state* in) {
 
 dem_status dem_set_forcing(dem_sim* s, const dem_forcing* f) {
   if (!s || !f) return fail(s, DEM_ERR_INVALID_ARG, "NULL argument");
-  bool ok = std::isfinite(f->spin_dw) && std::isfinite(f->pert_mass) && f->pert_mass >= 0.0;
+  bool ok = std::isfinite(f->spin_dw) && std::isfinite(f->pert_mass) && f->pert_mass >= 0.0 &&
+            std::isfinite(f->stop_growth) && f->stop_growth >= 0.0;
   for (int k = 0; k < 3; ++k) ok = ok && std::isfinite(f->pert_pos[k]) && std::isfinite(f->pert_vel[k]);
   if (!ok) return fail(s, DEM_ERR_INVALID_ARG, "non-finite or negative forcing");
   if (f->pert_mass > 0.0 && !(s->prm.G > 0.0))
@@ -1243,6 +1320,10 @@ dem_status dem_set_forcing(dem_sim* s, const dem_forcing* f) {
   HIPCHK(s, get_entry(s, entry_of(s), st));
   PileDev& h = s->h;
   h.spin_dw = f->spin_dw;
+  h.stop_growth = f->stop_growth;
+  h.R0 = 0.0;                        // the next evaluation sets the reference radius
+  h.status &= ~kStStopped;           // a stopped system may go on under the new rule
+  if (h.status == 0) h.fail_step = -1;
   h.pert_on = f->pert_mass > 0.0 ? 1 : 0;
   h.pert_M = f->pert_mass;
   for (int k = 0; k < 3; ++k) {
@@ -1264,6 +1345,7 @@ dem_status dem_get_forcing(dem_sim* s, dem_forcing* out) {
   HIPCHK(s, hipMemcpyAsync(&cur, entry_of(s), sizeof(PileDev), hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipStreamSynchronize(st));
   out->spin_dw = cur.spin_dw;
+  out->stop_growth = cur.stop_growth;
   out->pert_mass = cur.pert_on ? cur.pert_M : 0.0;
   for (int k = 0; k < 3; ++k) {
     out->pert_pos[k] = cur.pert_r[cur.parity][k];
@@ -1872,11 +1954,18 @@ dem_status dem_engine_step(dem_engine* e, int64_t n_steps) {
     dem_status r = rebuild(b, e->stream, b.members[0]);
     if (r != DEM_OK) return r;
   }
-  dem_status r = ensure_graph(b, e->stream, b.members[0]);
-  if (r != DEM_OK) return r;
-  for (int64_t k = 0; k < n_steps; ++k) {
-    hipError_t he = hipGraphLaunch(b.graph, e->stream);
-    if (he != hipSuccess) return fail(b.members[0], DEM_ERR_DEVICE, hip_msg(he, "hipGraphLaunch"));
+  if (e->profiling) {
+    dem_status r = profiled_passes(b, e->stream, n_steps, e->events, e->prof_ms, e->prof_steps,
+                                   b.members[0]);
+    if (r != DEM_OK) return r;
+  } else {
+    dem_status r = ensure_graph(b, e->stream, b.members[0]);
+    if (r != DEM_OK) return r;
+    for (int64_t k = 0; k < n_steps; ++k) {
+      hipError_t he = hipGraphLaunch(b.graph, e->stream);
+      if (he != hipSuccess)
+        return fail(b.members[0], DEM_ERR_DEVICE, hip_msg(he, "hipGraphLaunch"));
+    }
   }
   // one read-back of every entry's bookkeeping
   std::vector<PileDev> tab(b.members.size());
@@ -1890,15 +1979,34 @@ dem_status dem_engine_step(dem_engine* e, int64_t n_steps) {
     copy_device_fields(s->h, tab[k]);
     s->stepped = true;
     const dem_status c = status_code(s->h.status);
-    if (c != DEM_OK && first == DEM_OK) first = c;
+    if (c < 0 && first == DEM_OK) first = c;     // a stopped system is not a failure
   }
   return first;
 }
 
+dem_status dem_engine_set_profiling(dem_engine* e, int32_t enabled) {
+  if (!e) return fail(nullptr, DEM_ERR_INVALID_ARG, "engine is NULL");
+  e->profiling = enabled != 0;
+  e->prof_ms.assign(kNumStages, 0.0);
+  e->prof_steps = 0;
+  return DEM_OK;
+}
+
+dem_status dem_engine_get_profile(const dem_engine* e, double* kernel_ms, int32_t n_max,
+                                  int64_t* n_steps) {
+  if (!e) return fail(nullptr, DEM_ERR_INVALID_ARG, "engine is NULL");
+  for (int k = 0; k < n_max && k < kNumStages; ++k)
+    kernel_ms[k] = k < (int)e->prof_ms.size() ? e->prof_ms[k] : 0.0;
+  if (n_steps) *n_steps = e->prof_steps;
+  return DEM_OK;
+}
+
 dem_status dem_engine_destroy(dem_engine* e) {
   if (!e) return DEM_OK;
+  for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);
   while (!e->batch.members.empty()) dem_engine_detach(e, e->batch.members.back());
   free_meta(e->batch);
+  release_side(e->batch);
   if (e->batch.d_table) (void)hipFree(e->batch.d_table);
   delete e;
   return DEM_OK;

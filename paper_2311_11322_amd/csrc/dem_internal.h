@@ -28,6 +28,12 @@ constexpr int kRaw = 32;           // per tree node: raw M2[6], M3[10], M4[15], 
 // status bits of a pile (device-written)
 constexpr int kStCapacity = 1;
 constexpr int kStUnstable = 2;
+constexpr int kStStopped = 4;      // the stop rule fired (bulk radius grown by stop_growth)
+
+// per-block partials of the sphere set for the cell grid: bbox min[3],
+// max[3], mass moments sum m, sum m r[3], and sum m |r - c|^2 about a
+// reference point c (aggregate 0's centre) for the bulk radius
+constexpr int kBbox = 11;
 
 // modes of one pass through the step graph
 constexpr int kModeStep = 0;       // kick, drift, rotate, evaluate, kick
@@ -51,6 +57,7 @@ struct Grid {
   int32_t nc[3];             // cells per axis
   int32_t nbits[3];          // key bits per axis (sum 3 * bits)
   double t;                  // time of this evaluation
+  double R_bulk;             // bulk radius sqrt(5/3 <|r - com|^2>_m) of this evaluation
   double wall_d[6];          // plane offset of each wall at time t
   double wall_v[6][3];       // velocity of each wall at time t
 };
@@ -79,6 +86,9 @@ struct PileDev {
   int32_t member_read;       // 0 automatic, 1 direct, 2 staged through LDS
   double box;                // periodic cube side
   double G, soft_frac, spin_dw;
+  double stop_growth;        // > 0: stop (kStStopped) once R_bulk >= stop_growth * R0
+  double R0;                 // bulk radius the stop rule compares with (device-set at the
+                             // first evaluation with the rule on)
   double cell_min;           // cell side lower bound: largest diameter of the non-big spheres
   // spheres with radius > s_cut ("big", at most kMaxBig) are not binned: they
   // sit in one extra cell after the Morton cells and are searched by a block
@@ -156,7 +166,7 @@ struct PileDev {
   double* ganchor;           // [g_nt][4] FP64 anchor of each tile (relative coordinates)
   void* gpart;               // [g_nt][3][ns] per-tile partial sums (sorted slots)
   double* gacc;              // [3][ns] gravity force G m_i sum_j (by sphere id)
-  double* bpart;             // [n_rblk][10] bbox min/max + mass moments
+  double* bpart;             // [n_rblk][kBbox] bbox min/max + mass moments
   Grid* grid;
   uint32_t* cell_cnt;        // [cells]
   uint32_t* cell_start;      // [cells + 1]

@@ -290,7 +290,11 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
   const int i = w.base + threadIdx.x;
   const int ns = P.ns, na = P.na, nxt = P.parity ^ 1;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double mom[4] = {0.0, 0.0, 0.0, 0.0};
+  double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // reference point of the second moment: aggregate 0's new centre
+  double cref[3] = {0.0, 0.0, 0.0};
+  if (na > 0 && !P.given)
+    for (int k = 0; k < 3; ++k) cref[k] = P.rA[nxt][k * na];
   if (i < ns && (na == 0 || P.given)) {
     // positions given directly (stateless hooks): bbox only
     for (int k = 0; k < 3; ++k) {
@@ -311,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
     const double wa[3] = {P.wA[A], P.wA[na + A], P.wA[2 * na + A]};
     cross3(wa, d, wxd);
     const double mi = P.m[i];
+    double d2 = 0.0;
     for (int k = 0; k < 3; ++k) {
       const double x = P.rA[nxt][k * na + A] + d[k];
       P.r[k * ns + i] = x;
@@ -318,24 +323,27 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
       lo[k] = x;
       hi[k] = x;
       mom[k + 1] = mi * x;
+      d2 += (x - cref[k]) * (x - cref[k]);
     }
     mom[0] = mi;
+    mom[4] = mi * d2;
   }
   // block reduction (wave shuffles, then across the 4 waves through LDS)
-  __shared__ double red[4][10];
-  double vals[10] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], mom[0], mom[1], mom[2], mom[3]};
+  __shared__ double red[4][kBbox];
+  double vals[kBbox] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
+                        mom[0], mom[1], mom[2], mom[3], mom[4]};
   for (int off = 32; off > 0; off >>= 1) {
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], __shfl_xor(vals[k], off));
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
-    for (int k = 6; k < 10; ++k) vals[k] += __shfl_xor(vals[k], off);
+    for (int k = 6; k < kBbox; ++k) vals[k] += __shfl_xor(vals[k], off);
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
-    for (int k = 0; k < 10; ++k) red[wave][k] = vals[k];
+    for (int k = 0; k < kBbox; ++k) red[wave][k] = vals[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* out = P.bpart + (size_t)(w.base / kBlock) * 10;
-    for (int k = 0; k < 10; ++k) {
+    double* out = P.bpart + (size_t)(w.base / kBlock) * kBbox;
+    for (int k = 0; k < kBbox; ++k) {
       double x = red[0][k];
       for (int j = 1; j < 4; ++j) {
         const double y = red[j][k];
@@ -353,26 +361,26 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
                                                  double dt) {
   PileDev& P = piles[blockIdx.x];
   if (P.status != 0) return;
-  double vals[10] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
-                     0.0, 0.0, 0.0, 0.0};
+  double vals[kBbox] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
+                        0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < P.n_rblk; b += kBlock) {
-    const double* p = P.bpart + (size_t)b * 10;
+    const double* p = P.bpart + (size_t)b * kBbox;
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], p[k]);
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], p[k]);
-    for (int k = 6; k < 10; ++k) vals[k] += p[k];
+    for (int k = 6; k < kBbox; ++k) vals[k] += p[k];
   }
   for (int off = 32; off > 0; off >>= 1) {
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], __shfl_xor(vals[k], off));
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
-    for (int k = 6; k < 10; ++k) vals[k] += __shfl_xor(vals[k], off);
+    for (int k = 6; k < kBbox; ++k) vals[k] += __shfl_xor(vals[k], off);
   }
-  __shared__ double red[4][10];
+  __shared__ double red[4][kBbox];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
-    for (int k = 0; k < 10; ++k) red[wave][k] = vals[k];
+    for (int k = 0; k < kBbox; ++k) red[wave][k] = vals[k];
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int k = 0; k < 10; ++k) {
+  for (int k = 0; k < kBbox; ++k) {
     double x = red[0][k];
     for (int j = 1; j < 4; ++j) {
       const double y = red[j][k];
@@ -382,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
   }
   Grid g;
   bool finite = true;
-  for (int k = 0; k < 10; ++k) finite = finite && isfinite(vals[k]);
+  for (int k = 0; k < kBbox; ++k) finite = finite && isfinite(vals[k]);
   if (!finite) {
     atomicOr(&P.status, kStUnstable);
     return;
@@ -430,6 +438,27 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
   }
   g.inv_cell = 1.0 / g.cell;
   for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
+  // bulk radius from the second moment about aggregate 0's centre c:
+  // <|r - com|^2>_m = <|r - c|^2>_m - |com - c|^2
+  {
+    double c[3] = {0.0, 0.0, 0.0};
+    const int na = P.na, nxt = P.parity ^ 1;
+    if (na > 0 && !P.given)
+      for (int k = 0; k < 3; ++k) c[k] = P.rA[nxt][k * na];
+    double s2 = vals[10] / vals[6];
+    for (int k = 0; k < 3; ++k) s2 -= (g.com[k] - c[k]) * (g.com[k] - c[k]);
+    g.R_bulk = sqrt(fmax(s2, 0.0) * (5.0 / 3.0));
+  }
+  if (P.stop_growth > 0.0) {
+    // the stop rule: the first evaluation sets the reference radius; an
+    // evaluation at or beyond stop_growth times it stops the pile (its step
+    // is not committed, like a failure)
+    if (!(P.R0 > 0.0)) {
+      P.R0 = g.R_bulk;
+    } else if (g.R_bulk >= P.stop_growth * P.R0) {
+      atomicOr(&P.status, kStStopped);
+    }
+  }
   // time of this evaluation: the end of the step being taken, or the
   // current time for an evaluation in place; walls displaced rigidly by
   // A sin(omega t + phase), moving at A omega cos(omega t + phase)

@@ -23,8 +23,9 @@ DEM_ERR_CAPACITY = -3
 DEM_ERR_UNSTABLE = -4
 DEM_ERR_DEVICE = -5
 DEM_ERR_STATE = -6
+DEM_STOPPED = 1
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "CAPACITY", -4: "UNSTABLE",
-                -5: "DEVICE", -6: "STATE"}
+                -5: "DEVICE", -6: "STATE", 1: "STOPPED"}
 
 PREC_FP64 = 0
 PREC_FP32_FORCE = 1
@@ -73,7 +74,8 @@ class dem_tuning(C.Structure):
 
 class dem_forcing(C.Structure):
     _fields_ = [("spin_dw", C.c_double), ("pert_mass", C.c_double),
-                ("pert_pos", C.c_double * 3), ("pert_vel", C.c_double * 3)]
+                ("pert_pos", C.c_double * 3), ("pert_vel", C.c_double * 3),
+                ("stop_growth", C.c_double)]
 
 
 class dem_state(C.Structure):
@@ -133,6 +135,8 @@ def lib():
         L.dem_engine_detach.argtypes = [vp, vp]
         L.dem_engine_destroy.argtypes = [vp]
         L.dem_sim_status.argtypes = [vp]
+        L.dem_engine_set_profiling.argtypes = [vp, C.c_int32]
+        L.dem_engine_get_profile.argtypes = [vp, _PD, C.c_int32, _PI64]
         L.dem_set_tuning.argtypes = [vp, C.POINTER(dem_tuning)]
         L.dem_gravity_tiles.argtypes = [C.c_int32, _PI32, C.c_int32]
         L.dem_gravity_tiles.restype = C.c_int32
@@ -147,7 +151,8 @@ def lib():
                      "dem_engine_create", "dem_engine_attach", "dem_engine_step",
                      "dem_engine_detach", "dem_engine_destroy", "dem_sim_status",
                      "dem_set_profiling", "dem_get_profile", "dem_set_tuning",
-                     "dem_get_forcing", "dem_find_contacts_noalloc", "dem_contact_forces"):
+                     "dem_get_forcing", "dem_find_contacts_noalloc", "dem_contact_forces",
+                     "dem_engine_set_profiling", "dem_engine_get_profile"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -274,8 +279,15 @@ class Sim:
     def add_workload(self, w):
         return self.add_aggregates(w.counts, w.pos, w.radius, w.mass, w.agg_vel, w.agg_spin)
 
-    def step(self, n: int = 1):
-        _check(lib().dem_step(self.h, int(n)), self.h)
+    def step(self, n: int = 1) -> int:
+        """Advance n steps; returns DEM_OK, or DEM_STOPPED when the stop rule
+        of the forcing fired (the state is then that at the start of the
+        stopping step).  Failures raise DemError."""
+        code = lib().dem_step(self.h, int(n))
+        if code == DEM_STOPPED:
+            return code
+        _check(code, self.h)
+        return code
 
     def counts(self):
         a, s, p = C.c_int64(), C.c_int64(), C.c_int64()
@@ -328,16 +340,17 @@ class Sim:
         _check(lib().dem_restore_state(self.h, C.byref(st)), self.h)
 
     def set_forcing(self, spin_dw: float = 0.0, pert_mass: float = 0.0, pert_pos=(0, 0, 0),
-                    pert_vel=(0, 0, 0)):
+                    pert_vel=(0, 0, 0), stop_growth: float = 0.0):
         f = dem_forcing(float(spin_dw), float(pert_mass), (C.c_double * 3)(*map(float, pert_pos)),
-                        (C.c_double * 3)(*map(float, pert_vel)))
+                        (C.c_double * 3)(*map(float, pert_vel)), float(stop_growth))
         _check(lib().dem_set_forcing(self.h, C.byref(f)), self.h)
 
     def get_forcing(self) -> Dict:
         f = dem_forcing()
         _check(lib().dem_get_forcing(self.h, C.byref(f)), self.h)
         return {"spin_dw": f.spin_dw, "pert_mass": f.pert_mass,
-                "pert_pos": np.array(f.pert_pos[:]), "pert_vel": np.array(f.pert_vel[:])}
+                "pert_pos": np.array(f.pert_pos[:]), "pert_vel": np.array(f.pert_vel[:]),
+                "stop_growth": f.stop_growth}
 
     def reserve_contacts(self, per_sphere: int):
         _check(lib().dem_reserve_contacts(self.h, int(per_sphere)), self.h)
@@ -385,6 +398,19 @@ class Engine:
         """Advance every attached system; returns the first failure code
         (failed systems stop, the rest continue)."""
         return int(lib().dem_engine_step(self.h, int(n)))
+
+    def set_profiling(self, on: bool):
+        _check(lib().dem_engine_set_profiling(self.h, int(bool(on))))
+
+    def profile(self) -> Dict[str, float]:
+        """Accumulated per-kernel milliseconds of the engine's steps."""
+        names = lib().dem_profile_names().decode().split(";")
+        ms = np.zeros(len(names))
+        n = C.c_int64()
+        _check(lib().dem_engine_get_profile(self.h, _p(ms), len(names), C.byref(n)))
+        out = dict(zip(names, ms.tolist()))
+        out["_steps"] = int(n.value)
+        return out
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

@@ -50,13 +50,93 @@ def make_sim(w, precision: int, tuning=None, allocator=None, stream=None) -> dem
     if tuning:
         sim.set_tuning(*tuning)
     pert = w.params.get("perturber")
-    if w.params.get("spin_dw", 0.0) or pert:
+    stop = float(w.params.get("stop_growth", 0.0))
+    if w.params.get("spin_dw", 0.0) or pert or stop:
         if pert:
-            sim.set_forcing(w.params.get("spin_dw", 0.0), pert[0], pert[1], pert[2])
+            sim.set_forcing(w.params.get("spin_dw", 0.0), pert[0], pert[1], pert[2],
+                            stop_growth=stop)
         else:
-            sim.set_forcing(w.params["spin_dw"])
+            sim.set_forcing(w.params.get("spin_dw", 0.0), stop_growth=stop)
     sim.add_workload(w)
     return sim
+
+
+def settle(workloads: Sequence, steps: int, precision: int = dem.PREC_FP32_FORCE,
+           tuning=None) -> List:
+    """Self-gravitating clouds collapsed and settled together in one engine
+    (no forcing), then each made into a new workload from its settled state:
+    sphere centres, centre-of-mass velocities and space-frame spins, the
+    forcing of the original kept.  Deterministic: the engine's result for a
+    pile does not depend on the rest of the batch."""
+    import copy
+    quiet = []
+    for w in workloads:
+        q = copy.copy(w)
+        q.params = {k: v for k, v in w.params.items()
+                    if k not in ("spin_dw", "stop_growth", "perturber")}
+        quiet.append(q)
+    eng = dem.Engine(1 << 40)
+    sims = [make_sim(q, precision, tuning) for q in quiet]
+    for sm in sims:
+        eng.attach(sm)
+    code = eng.step(steps)
+    if code != dem.DEM_OK:
+        raise dem.DemError(code, "settling failed")
+    out = []
+    for w, sm in zip(workloads, sims):
+        eng.detach(sm)
+        st = sm.read_state(["sph_pos", "agg_vel", "agg_spin"])
+        sm.close()
+        n = copy.copy(w)
+        n.pos, n.agg_vel, n.agg_spin = st["sph_pos"], st["agg_vel"], st["agg_spin"]
+        n.params = dict(w.params)
+        n.notes = (w.notes + f"; settled {steps} steps").lstrip("; ")
+        out.append(n)
+    eng.close()
+    return out
+
+
+def spin_campaign(workloads: Sequence, precision: int = dem.PREC_FP32_FORCE, tuning=None,
+                  stop_growth: float = 1.05, max_steps: int = 20000, chunk: int = 100) -> Dict:
+    """Spin-up of every pile in one engine until each one's stop rule fires
+    (its bulk radius grown by ``stop_growth``; Sec. 4.1): the steps to
+    failure and spin at failure of each pile, and the throughput of the
+    campaign in sphere-steps of running piles per second."""
+    import copy
+    ws = []
+    for w in workloads:
+        c = copy.copy(w)
+        c.params = dict(w.params, stop_growth=stop_growth)
+        ws.append(c)
+    eng = dem.Engine(1 << 40)
+    sims = [make_sim(w, precision, tuning) for w in ws]
+    for sm in sims:
+        eng.attach(sm)
+    done = [None] * len(sims)
+    steps, t_run = 0, 0.0
+    while steps < max_steps and any(d is None for d in done):
+        t0 = time.perf_counter()
+        code = eng.step(chunk)
+        t_run += time.perf_counter() - t0
+        if code != dem.DEM_OK:
+            raise dem.DemError(code, "spin-up failed")
+        steps += chunk
+        for k, sm in enumerate(sims):
+            if done[k] is None and sm.status() == dem.DEM_STOPPED:
+                # steps committed before the stopping step, plus that step
+                done[k] = sm.read_state(["agg_mass"])["step"] + 1
+    # sphere-steps evaluated: each pile up to and including its stopping step
+    sphere_steps = sum(w.n_sph * (steps if d is None else d) for w, d in zip(ws, done))
+    for sm in sims:
+        eng.detach(sm)
+        sm.close()
+    eng.close()
+    fail = [d for d in done if d is not None]
+    return {"piles": len(ws), "stopped": len(fail), "steps": steps, "seconds": t_run,
+            "steps_to_failure": done,
+            "spin_at_failure": [None if d is None else d * w.params["spin_dw"]
+                                for d, w in zip(done, ws)],
+            "sphere_steps_per_s": sphere_steps / t_run if t_run > 0 else 0.0}
 
 
 def add_flyby(w, mass_ratio: float = 1000.0, periapsis_radii: float = 3.0,
@@ -105,6 +185,13 @@ def run_batch(workloads: Sequence, steps: int, precision: int = dem.PREC_FP32_FO
     out = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "spheres": n_sph,
            "sphere_steps_per_s": n_sph * steps / wall, "status": code,
            "sum_n2": float(sum(float(w.n_sph) ** 2 for w in workloads))}
+    if profile:
+        # per-kernel times over further steps (an event between kernels)
+        eng.set_profiling(True)
+        eng.step(steps)
+        out["profile"] = eng.profile()
+        eng.set_profiling(False)
+        out["contacts"] = sum(s.counts()[2] for s in sims)
     for s in sims:
         eng.detach(s)
     out["sims"] = sims
@@ -112,10 +199,30 @@ def run_batch(workloads: Sequence, steps: int, precision: int = dem.PREC_FP32_FO
     return out
 
 
+_TUNE_CACHE: Dict = {}
+
+
+def shape_bucket(workloads: Sequence, precision: int):
+    """What the tuning of a batch depends on: precision, gravity kind, the
+    number of piles and the total and largest sphere counts, each rounded to
+    a power of two."""
+    n = [w.n_sph for w in workloads]
+    grav = "tree" if any(w.params.get("gravity_tree") for w in workloads) else (
+        "direct" if any(w.params.get("G", 0.0) != 0.0 for w in workloads) else "none")
+    b = lambda x: int(round(math.log2(max(1, x))))
+    return (int(precision), grav, b(len(n)), b(sum(n)), b(max(n)))
+
+
 def autotune(workloads: Sequence, precision: int, steps: int = 3,
-             cell_scales=(1.0, 1.5), tiles=None) -> Dict:
+             cell_scales=(1.0, 1.25, 1.5, 2.0), tiles=None, cache: Optional[Dict] = None) -> Dict:
     """Pick the gravity tile and cell scale that minimise the measured step
-    time of this batch (a few steps per candidate)."""
+    time of this batch (a few steps per candidate).  The choice is cached
+    per shape bucket (``shape_bucket``): a later batch of the same shape
+    reuses it without measuring."""
+    cache = _TUNE_CACHE if cache is None else cache
+    key = shape_bucket(workloads, precision)
+    if key in cache:
+        return dict(cache[key], cached=True)
     tiles = list(tiles) if tiles else dem.gravity_tiles(precision)
     has_grav = any(w.params.get("G", 0.0) != 0.0 for w in workloads)
     if not has_grav:
@@ -128,8 +235,10 @@ def autotune(workloads: Sequence, precision: int, steps: int = 3,
                 s.close()
             timings.append({"gravity_tile": tile, "cell_scale": cs, "ms_per_step": r["ms_per_step"]})
     best = min(timings, key=lambda t: t["ms_per_step"])
-    return {"gravity_tile": best["gravity_tile"], "cell_scale": best["cell_scale"],
-            "candidates": timings}
+    out = {"gravity_tile": best["gravity_tile"], "cell_scale": best["cell_scale"],
+           "candidates": timings, "bucket": list(key)}
+    cache[key] = out
+    return dict(out, cached=False)
 
 
 class Server:
@@ -236,7 +345,8 @@ class Server:
                 st = sim.status()
                 sphere_steps += req.workload.n_sph * n
                 if st != dem.DEM_OK:
-                    self._finish(rid, now, st)
+                    # a stop rule that fired ends the run normally
+                    self._finish(rid, now, 0 if st == dem.DEM_STOPPED else st)
                     continue
                 self.active[rid][2] = rem - n
                 if self.active[rid][2] <= 0:

@@ -1,13 +1,17 @@
-"""Bulk observables of the FP32-force form against the plain FP64 form.
+"""Bulk observables of both forms against the FP64 oracle.
 
-Runs long enough to settle a self-gravitating pile and to spin it up to
-mass shedding are far beyond what the CPU oracle can finish, so the reference
-here is the plain FP64 GPU path (itself held to the oracle step by step in
-test_gpu_parity.py).  Both forms start from the same state with the same
-seeds; the final packing fraction of a collapse and the spin at which a
-spun-up pile's bulk radius has grown by 5 % must agree within 1 %.
+The oracle's values come from tests/golden/make_observables.py (it runs only
+the oracle): the final packing fraction of a reduced self-gravitating
+collapse (Sec. 3.3 collapse runs; 1,100 aggregates, 8 free-fall times) and
+the spin at which a pile made from the oracle's settled collapse fails under
+spin-up (Sec. 4.1: bulk radius grown by 5 %), checked every step.  The plain
+FP64 form and the FP32-force form must each reproduce both within 1 %; the
+runs are long enough for the two sides' states to differ chaotically, so the
+agreement is that of bulk quantities.
 """
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -16,6 +20,8 @@ import pytest
 from paper_2311_11322_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -30,62 +36,117 @@ def D():
     return dem
 
 
+@pytest.fixture(scope="module")
+def gold():
+    with open(os.path.join(GOLDEN, "observables.json")) as f:
+        g = json.load(f)
+    wk = g["workload"]
+    w = W.collapse_cloud(seed=wk["seed"], n_agg=wk["n_agg"], cmin=wk["cmin"], cmax=wk["cmax"],
+                         phi0=wk["phi0"])
+    assert w.n_sph == wk["n_sph"]
+    pile = np.load(os.path.join(GOLDEN, "observables_pile.npz"))
+    return g, w, pile
+
+
 def bulk(sim, radius):
-    st = sim.read_state(["sph_pos"])
-    r = st["sph_pos"]
-    m = radius ** 3
+    """Bulk radius sqrt(5/3 <|r - r_com|^2>_m) and packing sum s^3 / R^3."""
+    r = sim.read_state(["sph_pos"])["sph_pos"]
+    m = W.sphere_mass(radius)
     com = (m[:, None] * r).sum(0) / m.sum()
     R = math.sqrt(5.0 / 3.0 * float((m * ((r - com) ** 2).sum(1)).sum() / m.sum()))
-    phi = float((radius ** 3).sum()) / R ** 3
-    return R, phi
+    return R, float((radius ** 3).sum()) / R ** 3
 
 
-def collapse(D, w, precision, steps):
+@pytest.mark.parametrize("prec", ["fp64", "fp32_force"])
+def test_collapse_packing_matches_oracle(D, gold, prec):
+    g, w, _ = gold
+    precision = D.PREC_FP64 if prec == "fp64" else D.PREC_FP32_FORCE
+    steps = g["collapse"]["steps"]
+    say("collapse", prec, w.n_sph, "spheres,", steps, "steps")
     sim = D.Sim(w.params, precision=precision)
     sim.add_workload(w)
     sim.step(steps)
-    return sim
+    R, phi = bulk(sim, w.radius)
+    ref = g["collapse"]["packing"]
+    print(f"packing {prec} {phi:.5f} oracle {ref:.5f} ({(phi / ref - 1) * 100:+.3f} %); "
+          f"R {R:.4f} oracle {g['collapse']['R_bulk']:.4f}", flush=True)
+    assert abs(phi - ref) <= 0.01 * ref
 
 
-def restart(D, sim, w, precision, spin_dw):
-    """A new system from another's current positions and velocities."""
-    st = sim.read_state(["sph_pos", "agg_vel", "agg_spin"])
-    s2 = D.Sim(w.params, precision=precision)
-    s2.set_forcing(spin_dw)
-    s2.add_aggregates(w.counts, st["sph_pos"], w.radius, w.mass, st["agg_vel"], st["agg_spin"])
-    return s2
-
-
-def spin_to_failure(sim, radius, dw, every=20, max_steps=6000):
-    R0, _ = bulk(sim, radius)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_force"])
+def test_spin_at_failure_matches_oracle(D, gold, prec):
+    g, w, pile = gold
+    precision = D.PREC_FP64 if prec == "fp64" else D.PREC_FP32_FORCE
+    sp = g["spin_up"]
+    dw = sp["spin_dw"]
+    say("spin-up", prec, "from the oracle's settled pile")
+    sim = D.Sim(w.params, precision=precision)
+    sim.set_forcing(dw)
+    sim.add_aggregates(w.counts, pile["sph_pos"], w.radius, w.mass, pile["agg_vel"],
+                       pile["agg_spin"])
+    R0, _ = bulk(sim, w.radius)
+    assert abs(R0 / sp["R0"] - 1.0) < 1e-12
     n = 0
-    while n < max_steps:
-        sim.step(every)
-        n += every
-        R, _ = bulk(sim, radius)
-        if R >= 1.05 * R0:
-            return n * dw
-    return None
+    while n < 3 * sp["steps_to_failure"]:
+        sim.step(1)
+        n += 1
+        R, _ = bulk(sim, w.radius)
+        if R >= sp["fail_growth"] * R0:
+            break
+    spin = n * dw
+    ref = sp["spin_at_failure"]
+    # the device's own stop rule (bulk radius from its evaluation) stops the
+    # same run at the same step, with the state of that step's start
+    say("spin-up with the device stop rule", prec)
+    dev = D.Sim(w.params, precision=precision)
+    dev.set_forcing(dw, stop_growth=sp["fail_growth"])
+    dev.add_aggregates(w.counts, pile["sph_pos"], w.radius, w.mass, pile["agg_vel"],
+                       pile["agg_spin"])
+    code = D.DEM_OK
+    while code == D.DEM_OK and dev.read_state(["agg_mass"])["step"] < 3 * sp["steps_to_failure"]:
+        code = dev.step(50)
+    assert code == D.DEM_STOPPED
+    stopped_at = dev.read_state(["agg_mass"])["step"] + 1
+    assert stopped_at == n, (stopped_at, n)
+    rho = float(w.mass.sum()) / (4.0 / 3.0 * math.pi * R0 ** 3)
+    w_crit = math.sqrt(4.0 * math.pi * w.params["G"] * rho / 3.0)
+    print(f"spin at failure {prec} {spin:.4f} ({n} steps) oracle {ref:.4f} "
+          f"({sp['steps_to_failure']} steps); nominal critical {w_crit:.4f}", flush=True)
+    assert abs(spin - ref) <= 0.01 * ref
 
 
-def test_collapse_packing_and_spin_at_failure_fp32_vs_fp64(D):
-    w = W.collapse_cloud(seed=21, n_agg=1100, cmin=1, cmax=8, phi0=0.15)
-    t_ff = math.sqrt(3 * math.pi / (32 * 1.0 * 0.15))
-    steps = int(8 * t_ff / w.params["dt"])
-    say("collapse", w.n_sph, "spheres,", steps, "steps")
-    s64 = collapse(D, w, D.PREC_FP64, steps)
-    s32 = collapse(D, w, D.PREC_FP32_FORCE, steps)
-    R64, phi64 = bulk(s64, w.radius)
-    R32, phi32 = bulk(s32, w.radius)
-    print(f"packing fp64 {phi64:.5f} fp32 {phi32:.5f}  R {R64:.4f} {R32:.4f}")
-    assert abs(phi32 - phi64) <= 0.01 * phi64
-    # spin-up of the settled FP64 pile in both forms
-    dw = 1e-6 / w.params["dt"]
-    say("spin-up")
-    w64 = spin_to_failure(restart(D, s64, w, D.PREC_FP64, dw), w.radius, dw)
-    w32 = spin_to_failure(restart(D, s64, w, D.PREC_FP32_FORCE, dw), w.radius, dw)
-    rho = float(W.sphere_mass(w.radius).sum()) / (4 / 3 * math.pi * R64 ** 3)
-    w_crit = math.sqrt(4 * math.pi * 1.0 * rho / 3)
-    print(f"spin at failure fp64 {w64} fp32 {w32}  nominal critical {w_crit:.4f}")
-    assert w64 is not None and w32 is not None
-    assert abs(w32 - w64) <= 0.01 * w64
+def test_stop_rule_alone_and_in_engine_bit_identical(D, gold):
+    """The stop rule of one pile inside an engine with other systems fires at
+    the same step as alone, and leaves the same state bit for bit."""
+    g, w, pile = gold
+    sp = g["spin_up"]
+    say("stop rule alone vs engine")
+    from paper_2311_11322_amd import serve
+    alone = D.Sim(w.params, precision=D.PREC_FP32_FORCE)
+    alone.set_forcing(sp["spin_dw"], stop_growth=sp["fail_growth"])
+    alone.add_aggregates(w.counts, pile["sph_pos"], w.radius, w.mass, pile["agg_vel"],
+                         pile["agg_spin"])
+    while alone.step(100) == D.DEM_OK:
+        pass
+    ref = alone.read_state(pairs=True)
+    eng = D.Engine(1 << 36)
+    other = serve.make_sim(W.box_fill(seed=3, n_sph=640, base=16.0, height=60.0),
+                           D.PREC_FP32_FORCE)
+    mine = D.Sim(w.params, precision=D.PREC_FP32_FORCE)
+    mine.set_forcing(sp["spin_dw"], stop_growth=sp["fail_growth"])
+    mine.add_aggregates(w.counts, pile["sph_pos"], w.radius, w.mass, pile["agg_vel"],
+                        pile["agg_spin"])
+    eng.attach(other)
+    eng.attach(mine)
+    while mine.status() == D.DEM_OK:
+        assert eng.step(100) == D.DEM_OK
+    assert mine.status() == D.DEM_STOPPED and other.status() == D.DEM_OK
+    eng.detach(mine)
+    got = mine.read_state(pairs=True)
+    assert got["step"] == ref["step"]
+    for k in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "pair_hist", "sph_force"):
+        assert np.array_equal(got[k], ref[k]), k
+    # re-arming without a stop lets the run go on
+    mine.set_forcing(sp["spin_dw"])
+    assert mine.step(3) == D.DEM_OK
+    assert mine.read_state(["agg_mass"])["step"] == ref["step"] + 3

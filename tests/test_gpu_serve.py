@@ -68,7 +68,15 @@ def test_autotune_picks_a_measured_candidate(D):
     from paper_2311_11322_amd import serve
     say("autotune")
     piles = W.pile_batch(seed=5, n_piles=4, nmin=500, nmax=3000)
-    res = serve.autotune(piles, D.PREC_FP32_FORCE, steps=2)
+    cache = {}
+    res = serve.autotune(piles, D.PREC_FP32_FORCE, steps=2, cache=cache)
+    assert not res["cached"]
     assert (res["gravity_tile"], res["cell_scale"]) in [
         (c["gravity_tile"], c["cell_scale"]) for c in res["candidates"]]
-    assert len(res["candidates"]) == len(D.gravity_tiles(D.PREC_FP32_FORCE)) * 2
+    assert len(res["candidates"]) == len(D.gravity_tiles(D.PREC_FP32_FORCE)) * 4
+    # a batch of the same shape bucket reuses the choice without measuring
+    again = serve.autotune(W.pile_batch(seed=6, n_piles=4, nmin=500, nmax=3000)[:4],
+                           D.PREC_FP32_FORCE, steps=2, cache=cache)
+    if serve.shape_bucket(piles, D.PREC_FP32_FORCE) == serve.shape_bucket(
+            W.pile_batch(seed=6, n_piles=4, nmin=500, nmax=3000), D.PREC_FP32_FORCE):
+        assert again["cached"] and again["gravity_tile"] == res["gravity_tile"]

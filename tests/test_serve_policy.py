@@ -37,3 +37,14 @@ def test_srpt_always_steps_at_least_one_run():
 def test_unknown_policy_is_refused():
     with pytest.raises(ValueError):
         serve.Server(1 << 30, policy="lifo")
+
+
+def test_shape_bucket_groups_batches_by_size_and_kind():
+    mk = lambda n, G=1.0, tree=0: types.SimpleNamespace(
+        n_sph=n, params={"G": G, "gravity_tree": tree})
+    a = serve.shape_bucket([mk(1000), mk(3000)], 1)
+    assert a == serve.shape_bucket([mk(1100), mk(2900)], 1)       # same powers of two
+    assert a != serve.shape_bucket([mk(1000), mk(3000)], 0)       # precision
+    assert a != serve.shape_bucket([mk(1000, G=0.0), mk(3000, G=0.0)], 1)
+    assert a != serve.shape_bucket([mk(1000, tree=1), mk(3000, tree=1)], 1)
+    assert a != serve.shape_bucket([mk(1000), mk(3000), mk(2000), mk(2000)], 1)
