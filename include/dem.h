@@ -329,6 +329,13 @@ typedef struct {
                                   else each aggregate's members directly; 1 directly;
                                   2 staged.  Same order and arithmetic, so the same
                                   results; different cost. */
+    int32_t fused;             /* 0 automatic -- the whole step of the system in one
+                                  workgroup (one launch per step for a batch of such systems;
+                                  with gravity, two launches around the batched gravity
+                                  kernels) when it has at most 256 spheres; 1 always; 2 never
+                                  (one launch per stage).  Never with tree gravity.  The same
+                                  arithmetic per element; the centre of mass and bulk radius
+                                  are summed in another order (spin-up, stop rule). */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them

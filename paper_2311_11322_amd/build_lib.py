@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdem.so")
 
 SOURCES = ["dem_host.hip", "kernels_body.hip", "kernels_contact.hip", "kernels_force.hip",
-           "kernels_gravity.hip", "kernels_tree.hip", "kernels_scan.hip"]
+           "kernels_gravity.hip", "kernels_tree.hip", "kernels_scan.hip", "kernels_fused.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -250,6 +250,17 @@ struct Batch {
   bool any_grav = false;
   bool any_direct = false;                   // some pile with the exact sum
   bool reduce_stage = false;                 // member reduction through LDS
+  // piles whose whole step runs in one workgroup (k_fused): with gravity
+  // (parts 1 and 2 around the gravity kernels) and without (part 3)
+  int32_t* pl_fused_g = nullptr;
+  int n_fused_g = 0;
+  int32_t* pl_fused_ng = nullptr;
+  int n_fused_ng = 0;
+  int n_staged = 0;                          // piles stepped by the staged kernels
+  WorkItem* wl_grav = nullptr;               // spheres of every pile with gravity
+  int n_grav_blk = 0;
+  WorkItem* wl_agg_all = nullptr;            // aggregates of every pile (set-up)
+  int n_agg_all_blk = 0;
   bool all_soft = true;
   ScanSeg* seg_cells = nullptr;
   ScanItem* item_cells = nullptr;
@@ -289,7 +300,7 @@ struct dem_sim {
   dem_engine* engine = nullptr;
   int engine_slot = -1;
   dem_status last_status = DEM_OK;
-  dem_tuning tune{0, 1.0, 0, 0};
+  dem_tuning tune{0, 1.0, 0, 0, 0};
   // per-kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -363,7 +374,8 @@ hipError_t upload(Batch& b, T** dst, const std::vector<T>& src, hipStream_t st) 
 // device table entries must already be in place at slots 0..n-1.
 dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
-  std::vector<WorkItem> wa, wsph, wbig, wtree[11];
+  std::vector<WorkItem> wa, wsph, wbig, wtree[11], wgrav, wall;
+  std::vector<int32_t> pfg, pfng;
   std::vector<GravItem> glg[3];
   int tiles[3] = {0, 0, 0};
   int n_groups = 0;
@@ -376,13 +388,22 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   b.tree_leaf_levels = 0;
   b.all_soft = true;
   int64_t tot_na = 0;
+  b.n_staged = 0;
   for (int p = 0; p < (int)b.members.size(); ++p) {
     const dem_sim* s = b.members[p];
     const PileDev& h = s->h;
-    for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
-    tot_na += h.na;
-    for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
-    for (int k = 0; k < h.n_big; ++k) wbig.push_back({p, k});
+    if (h.G != 0.0)
+      for (int i = 0; i < h.ns; i += kBlock) wgrav.push_back({p, i});
+    for (int a = 0; a < h.na; a += kBlock) wall.push_back({p, a});
+    if (h.fused) {
+      (h.G != 0.0 ? pfg : pfng).push_back(p);
+    } else {
+      b.n_staged++;
+      for (int a = 0; a < h.na; a += kBlock) wa.push_back({p, a});
+      tot_na += h.na;
+      for (int i = 0; i < h.ns; i += kBlock) wsph.push_back({p, i});
+      for (int k = 0; k < h.n_big; ++k) wbig.push_back({p, k});
+    }
     if (h.G != 0.0 && h.tree) {
       b.any_grav = true;
       b.any_tree = true;
@@ -418,12 +439,21 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       for (int c = 0; c < g.n_items; ++c) items.push_back({(int32_t)segs.size(), c});
       segs.push_back(g);
     };
+    if (h.fused) continue;
     PileDev* dentry = b.d_table + p;
     add_seg(sc, ic, h.cell_cnt, h.cell_start, h.cell_start, nullptr, s->sz.cells + 1);
     add_seg(sp, ip, h.cnt_up, h.up_off[0], h.up_off[1], &dentry->parity, h.ns);
     add_seg(sp, ip, h.cnt_lo, h.lo_off, h.lo_off, nullptr, h.ns);
   }
   HIPCHK(errsim, upload(b, &b.wl_agg, wa, st));
+  HIPCHK(errsim, upload(b, &b.wl_grav, wgrav, st));
+  HIPCHK(errsim, upload(b, &b.wl_agg_all, wall, st));
+  b.n_agg_all_blk = (int)wall.size();
+  b.n_grav_blk = (int)wgrav.size();
+  HIPCHK(errsim, upload(b, &b.pl_fused_g, pfg, st));
+  b.n_fused_g = (int)pfg.size();
+  HIPCHK(errsim, upload(b, &b.pl_fused_ng, pfng, st));
+  b.n_fused_ng = (int)pfng.size();
   HIPCHK(errsim, upload(b, &b.wl_sph, wsph, st));
   b.n_big_blk = (int)wbig.size();
   if (!wbig.empty()) HIPCHK(errsim, upload(b, &b.wl_big, wbig, st));
@@ -460,11 +490,13 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
 }
 
 // Kernel families of one step, in launch order (profiling names).
-constexpr int kNumStages = 15;
+constexpr int kNumStages = 17;
 constexpr int kStageGravity = 11;
+constexpr int kStageFusedA = 15;           // k_fused parts 1 and 3
+constexpr int kStageFusedB = 16;           // k_fused part 2
 const char* const kStageNames =
     "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;search_count;"
-    "scan_pairs;search_write;pairs;gravity;gather;reduce;finish";
+    "scan_pairs;search_write;pairs;gravity;gather;reduce;finish;fused_a;fused_b";
 
 // Second stream and fork/join events of a batch (default priority).
 hipError_t ensure_side(Batch& b) {
@@ -494,65 +526,76 @@ void release_side(Batch& b) {
 template <typename Mark>
 void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark, bool overlap) {
   const int np = (int)b.members.size();
-  auto stage = [&](int k, hipStream_t s, auto&& launch) {
+  const bool staged = b.n_staged > 0;
+  auto stage = [&](int k, hipStream_t s, bool run, auto&& launch) {
     mark(k, s, true);
-    launch(s);
+    if (run) launch(s);
     mark(k, s, false);
   };
-  stage(0, st, [&](hipStream_t s) { launch_integrate(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode); });
-  stage(1, st, [&](hipStream_t s) { launch_reconstruct(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  stage(2, st, [&](hipStream_t s) { launch_grid(s, b.d_table, np, mode, b.cp.dt); });
-  stage(3, st, [&](hipStream_t s) { launch_bin(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  stage(4, st, [&](hipStream_t s) {
+  // small piles: their whole step (part 3), or the stages before gravity (part 1)
+  stage(kStageFusedA, st, b.n_fused_ng + b.n_fused_g > 0, [&](hipStream_t s) {
+    launch_fused(s, b.d_table, b.pl_fused_ng, b.n_fused_ng, b.cp, mode, 3, b.precision);
+    launch_fused(s, b.d_table, b.pl_fused_g, b.n_fused_g, b.cp, mode, 1, b.precision);
+  });
+  stage(0, st, staged, [&](hipStream_t s) {
+    launch_integrate(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode);
+  });
+  stage(1, st, staged, [&](hipStream_t s) {
+    launch_reconstruct(s, b.d_table, b.wl_sph, b.n_sph_blk);
+  });
+  stage(2, st, staged, [&](hipStream_t s) { launch_grid(s, b.d_table, np, mode, b.cp.dt); });
+  stage(3, st, staged, [&](hipStream_t s) { launch_bin(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(4, st, staged, [&](hipStream_t s) {
     launch_scan(s, b.seg_cells, b.n_seg_cells, b.item_cells, b.n_item_cells, b.sums_cells,
                 b.max_items_cells);
   });
-  stage(5, st, [&](hipStream_t s) { launch_scatter(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  stage(6, st, [&](hipStream_t s) { launch_cell_sort(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  const bool fork = overlap && b.any_grav && b.side;
+  stage(5, st, staged, [&](hipStream_t s) {
+    launch_scatter(s, b.d_table, b.wl_sph, b.n_sph_blk);
+  });
+  stage(6, st, staged, [&](hipStream_t s) {
+    launch_cell_sort(s, b.d_table, b.wl_sph, b.n_sph_blk);
+  });
+  const bool fork = overlap && b.any_grav && b.side && staged;
   auto gravity = [&](hipStream_t s) {
-    launch_gravity_records(s, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    launch_gravity_records(s, b.d_table, b.wl_grav, b.n_grav_blk, b.precision);
     for (int g = 0; g < b.n_grav_groups; ++g)
       launch_gravity_tiles(s, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
-    if (b.any_direct) launch_gravity_combine(s, b.d_table, b.wl_sph, b.n_sph_blk, b.precision);
+    if (b.any_direct) launch_gravity_combine(s, b.d_table, b.wl_grav, b.n_grav_blk, b.precision);
     if (b.any_tree) launch_tree(s, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
                                b.n_sph_blk, b.tree_order);
   };
   if (fork) {
     (void)hipEventRecord(b.fork_ev, st);
     (void)hipStreamWaitEvent(b.side, b.fork_ev, 0);
-    stage(kStageGravity, b.side, gravity);
+    stage(kStageGravity, b.side, true, gravity);
     (void)hipEventRecord(b.join_ev, b.side);
   }
-  stage(7, st, [&](hipStream_t s) {
+  stage(7, st, staged, [&](hipStream_t s) {
     launch_search(s, b.d_table, b.wl_sph, b.n_sph_blk, 0);
     if (b.n_big_blk) launch_search_big(s, b.d_table, b.wl_big, b.n_big_blk, 0);
   });
-  stage(8, st, [&](hipStream_t s) {
+  stage(8, st, staged, [&](hipStream_t s) {
     launch_scan(s, b.seg_pairs, b.n_seg_pairs, b.item_pairs, b.n_item_pairs, b.sums_pairs,
                 b.max_items_pairs);
   });
-  stage(9, st, [&](hipStream_t s) {
+  stage(9, st, staged, [&](hipStream_t s) {
     launch_search(s, b.d_table, b.wl_sph, b.n_sph_blk, 1);
     if (b.n_big_blk) launch_search_big(s, b.d_table, b.wl_big, b.n_big_blk, 1);
   });
-  stage(10, st, [&](hipStream_t s) {
+  stage(10, st, staged, [&](hipStream_t s) {
     launch_pairs(s, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   });
-  if (fork) {
-    (void)hipStreamWaitEvent(st, b.join_ev, 0);
-  } else if (b.any_grav) {
-    stage(kStageGravity, st, gravity);
-  } else {
-    mark(kStageGravity, st, true);
-    mark(kStageGravity, st, false);
-  }
-  stage(12, st, [&](hipStream_t s) { launch_gather(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  stage(13, st, [&](hipStream_t s) {
+  if (fork) (void)hipStreamWaitEvent(st, b.join_ev, 0);
+  else stage(kStageGravity, st, b.any_grav, gravity);
+  stage(kStageFusedB, st, b.n_fused_g > 0, [&](hipStream_t s) {
+    launch_fused(s, b.d_table, b.pl_fused_g, b.n_fused_g, b.cp, mode, 2, b.precision);
+  });
+  stage(12, st, staged, [&](hipStream_t s) { launch_gather(s, b.d_table, b.wl_sph, b.n_sph_blk); });
+  stage(13, st, staged, [&](hipStream_t s) {
     launch_reduce(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode, b.reduce_stage);
   });
-  stage(14, st, [&](hipStream_t s) { launch_finish(s, b.d_table, np, mode, b.cp.dt); });
+  stage(14, st, staged, [&](hipStream_t s) { launch_finish(s, b.d_table, np, mode, b.cp.dt); });
 }
 
 void enqueue_pass(Batch& b, hipStream_t st, int mode, bool overlap = false) {
@@ -791,6 +834,14 @@ dem_status status_code(int st) {
   if (st & kStUnstable) return DEM_ERR_UNSTABLE;
   if (st & kStStopped) return DEM_STOPPED;
   return DEM_OK;
+}
+
+// Whether a system runs its whole step in one workgroup (k_fused): never
+// with tree gravity; else as tuned, or automatically for small systems.
+int fused_choice(const dem_sim* s, int64_t ns) {
+  if ((s->prm.gravity_tree && s->prm.G != 0.0) || s->tune.fused == 2) return 0;
+  if (s->tune.fused == 1) return 1;
+  return ns <= kFusedAutoMax ? 1 : 0;
 }
 
 dem_status ensure_own_table(dem_sim* s) {
@@ -1056,6 +1107,7 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
   const double cell_min = s->tune.cell_scale * 2.0 * s_small;
   dem_status st = alloc_pile(s, n_agg, ns);
   if (st != DEM_OK) return st;
+  s->h.fused = fused_choice(s, ns);
   s->h.cell_min = cell_min;
   s->h.s_cut = s_cut;
   s->h.s_small = s_small;
@@ -1097,7 +1149,8 @@ dem_status dem_add_aggregates(dem_sim* s, int64_t n_agg, const int32_t* spa, con
   HIPCHK(s, put_entry(s, s->own.d_table, str));
   st = rebuild(s->own, str, s);
   if (st != DEM_OK) return st;
-  launch_setup(str, s->own.d_table, s->own.wl_agg, s->own.n_agg_blk, d_pos, d_vel, d_spin);
+  launch_setup(str, s->own.d_table, s->own.wl_agg_all, s->own.n_agg_all_blk, d_pos, d_vel,
+               d_spin);
   // initial evaluation at t0 (forces, torques and accelerations)
   enqueue_pass(s->own, str, kModeInit);
   HIPCHK(s, hipGetLastError());
@@ -1410,6 +1463,7 @@ dem_status dem_reserve_contacts(dem_sim* s, int32_t per_sphere) {
     return fail(s, r, why);
   }
   PileDev& h = s->h;
+  h.fused = old.fused;
   h.cell_min = old.cell_min;
   h.s_cut = old.s_cut;
   h.s_small = old.s_small;
@@ -1469,6 +1523,7 @@ dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
     return fail(s, DEM_ERR_INVALID_ARG, "member_scan must be 0 or 1");
   if (t->member_read < 0 || t->member_read > 2)
     return fail(s, DEM_ERR_INVALID_ARG, "member_read must be 0, 1 or 2");
+  if (t->fused < 0 || t->fused > 2) return fail(s, DEM_ERR_INVALID_ARG, "fused must be 0, 1 or 2");
   s->tune = *t;
   return DEM_OK;
 }

@@ -7,7 +7,7 @@
 // for centres of mass and a fifth-order Runge-Kutta step for orientation and
 // spin (Sec. 2.1-2.2); predicted member velocity (Eq. 3); aggregate
 // acceleration and torque (Eqs. 5-7, 9).
-#include "dem_internal.h"
+#include "step_body.h"
 
 namespace dem {
 
@@ -156,59 +156,6 @@ __global__ __launch_bounds__(kBlock) void k_setup(const PileDev* __restrict__ pi
   for (int k = 0; k < 4; ++k) P.q[cur][k * P.na + A] = q[k];
 }
 
-// ---------------------------------------------------------------------------
-// rotation: Euler's equations with quaternion kinematics, Cash-Karp RK5
-// ---------------------------------------------------------------------------
-
-// y = (q0..q3, w1..w3); body-frame principal moments I; torque N fixed in
-// the space frame.  dq/dt = q (x) (0, w) / 2; I dw/dt = R^T N - w x (I w).
-__device__ __forceinline__ void euler_deriv(const double y[7], const double I[3],
-                                            const double N[3], double f[7]) {
-  double R[9], Nb[3];
-  quat_rot(y, R);
-  rot_apply_T(R, N, Nb);
-  const double w = y[0], x = y[1], yy = y[2], z = y[3];
-  const double o1 = y[4], o2 = y[5], o3 = y[6];
-  f[0] = 0.5 * (-x * o1 - yy * o2 - z * o3);
-  f[1] = 0.5 * (w * o1 + yy * o3 - z * o2);
-  f[2] = 0.5 * (w * o2 + z * o1 - x * o3);
-  f[3] = 0.5 * (w * o3 + x * o2 - yy * o1);
-  f[4] = (Nb[0] - (I[2] - I[1]) * o2 * o3) / I[0];
-  f[5] = (Nb[1] - (I[0] - I[2]) * o3 * o1) / I[1];
-  f[6] = (Nb[2] - (I[1] - I[0]) * o1 * o2) / I[2];
-}
-
-// Cash & Karp (1990) fifth-order weights and stage matrix.
-__constant__ double ck_a[6][5] = {
-    {0.0, 0.0, 0.0, 0.0, 0.0},
-    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
-    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
-    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
-    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
-    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
-__constant__ double ck_b[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0,
-                               512.0 / 1771.0};
-
-__device__ void rk5_rotate(double y[7], const double I[3], const double N[3], double h) {
-  double k[6][7];
-  for (int st = 0; st < 6; ++st) {
-    double ys[7];
-    for (int c = 0; c < 7; ++c) {
-      double acc = 0.0;
-      for (int j = 0; j < st; ++j) acc += ck_a[st][j] * k[j][c];
-      ys[c] = y[c] + h * acc;
-    }
-    euler_deriv(ys, I, N, k[st]);
-  }
-  for (int c = 0; c < 7; ++c) {
-    double acc = 0.0;
-    for (int st = 0; st < 6; ++st) acc += ck_b[st] * k[st][c];
-    y[c] = y[c] + h * acc;
-  }
-  const double inv = 1.0 / sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
-  for (int c = 0; c < 4; ++c) y[c] *= inv;
-}
-
 // One thread per aggregate.  Step mode: v_A += h/2 a_A, r_A += h v_A (wrapped
 // in a periodic cube), one RK5 step of (q, w_b) with the last torque.  Writes
 // the next state, the space-frame spin w_A = R w_b and the predicted
@@ -221,56 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(PileDev* __restrict__ pile
   PileDev& P = piles[w.pile];
   const int A = w.base + threadIdx.x;
   if (A >= P.na || P.status != 0) return;
-  const int na = P.na, cur = P.parity, nxt = cur ^ 1;
-  const double h = cp.dt;
-  double v[3], r[3], a[3], y[7];
-  for (int k = 0; k < 3; ++k) {
-    v[k] = P.vA[cur][k * na + A];
-    r[k] = P.rA[cur][k * na + A];
-    a[k] = P.aA[cur][k * na + A];
-  }
-  for (int k = 0; k < 4; ++k) y[k] = P.q[cur][k * na + A];
-  for (int k = 0; k < 3; ++k) y[4 + k] = P.wb[cur][k * na + A];
-  if (mode == kModeStep) {
-    for (int k = 0; k < 3; ++k) {
-      v[k] += 0.5 * h * a[k];
-      r[k] += h * v[k];
-    }
-    if (P.periodic) {
-      const double L = P.box;
-      for (int k = 0; k < 3; ++k) {
-        if (r[k] >= L) r[k] -= L;
-        if (r[k] < 0.0) r[k] += L;
-      }
-    }
-    const double I[3] = {P.I[A], P.I[na + A], P.I[2 * na + A]};
-    const double N[3] = {P.NA[cur][A], P.NA[cur][na + A], P.NA[cur][2 * na + A]};
-    rk5_rotate(y, I, N, h);
-  }
-  double R[9], ws[3];
-  quat_rot(y, R);
-  rot_apply(R, &y[4], ws);
-  const double hh = (mode == kModeStep) ? 0.5 * h : 0.0;
-  for (int k = 0; k < 3; ++k) {
-    P.vA[nxt][k * na + A] = v[k];
-    P.rA[nxt][k * na + A] = r[k];
-    P.wA[k * na + A] = ws[k];
-    P.vpred[k * na + A] = v[k] + hh * a[k];
-    P.wb[nxt][k * na + A] = y[4 + k];
-  }
-  for (int k = 0; k < 4; ++k) P.q[nxt][k * na + A] = y[k];
-  if (A == 0 && P.pert_on) {
-    // the perturber is one more body of the same leapfrog
-    for (int k = 0; k < 3; ++k) {
-      double pv = P.pert_v[cur][k], pr = P.pert_r[cur][k];
-      if (mode == kModeStep) {
-        pv += 0.5 * h * P.pert_a[cur][k];
-        pr += h * pv;
-      }
-      P.pert_v[nxt][k] = pv;
-      P.pert_r[nxt][k] = pr;
-    }
-  }
+  integrate_one(P, A, cp, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -288,50 +186,13 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
   const PileDev& P = piles[w.pile];
   if (P.status != 0) return;
   const int i = w.base + threadIdx.x;
-  const int ns = P.ns, na = P.na, nxt = P.parity ^ 1;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  // reference point of the second moment: aggregate 0's new centre
-  double cref[3] = {0.0, 0.0, 0.0};
-  if (na > 0 && !P.given)
-    for (int k = 0; k < 3; ++k) cref[k] = P.rA[nxt][k * na];
-  if (i < ns && (na == 0 || P.given)) {
-    // positions given directly (stateless hooks): bbox only
-    for (int k = 0; k < 3; ++k) {
-      const double x = P.r[k * ns + i];
-      lo[k] = x;
-      hi[k] = x;
-      mom[k + 1] = x;
-    }
-    mom[0] = 1.0;
-  } else if (i < ns) {
-    const int A = P.agg[i];
-    double q[4], R[9];
-    for (int k = 0; k < 4; ++k) q[k] = P.q[nxt][k * na + A];
-    quat_rot(q, R);
-    const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
-    double d[3], wxd[3];
-    rot_apply(R, bb, d);
-    const double wa[3] = {P.wA[A], P.wA[na + A], P.wA[2 * na + A]};
-    cross3(wa, d, wxd);
-    const double mi = P.m[i];
-    double d2 = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      const double x = P.rA[nxt][k * na + A] + d[k];
-      P.r[k * ns + i] = x;
-      P.v[k * ns + i] = P.vpred[k * na + A] + wxd[k];
-      lo[k] = x;
-      hi[k] = x;
-      mom[k + 1] = mi * x;
-      d2 += (x - cref[k]) * (x - cref[k]);
-    }
-    mom[0] = mi;
-    mom[4] = mi * d2;
-  }
+  double vals[kBbox];
+  bbox_identity(vals);
+  double cref[3];
+  bbox_ref(P, cref);
+  if (i < P.ns) reconstruct_one(P, i, cref, vals);
   // block reduction (wave shuffles, then across the 4 waves through LDS)
   __shared__ double red[4][kBbox];
-  double vals[kBbox] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
-                        mom[0], mom[1], mom[2], mom[3], mom[4]};
   for (int off = 32; off > 0; off >>= 1) {
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], __shfl_xor(vals[k], off));
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
@@ -360,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
 __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, int mode,
                                                  double dt) {
   PileDev& P = piles[blockIdx.x];
-  if (P.status != 0) return;
+  if (P.status != 0 || P.fused) return;
   double vals[kBbox] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
                         0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < P.n_rblk; b += kBlock) {
@@ -388,99 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
     }
     vals[k] = x;
   }
-  Grid g;
-  bool finite = true;
-  for (int k = 0; k < kBbox; ++k) finite = finite && isfinite(vals[k]);
-  if (!finite) {
-    atomicOr(&P.status, kStUnstable);
-    return;
-  }
-  if (P.periodic) {
-    for (int k = 0; k < 3; ++k) {
-      g.nc[k] = P.n_periodic;
-      g.nbits[k] = P.bits;
-    }
-    g.lo[0] = g.lo[1] = g.lo[2] = 0.0;
-    g.cell = P.box / (double)P.n_periodic;
-  } else {
-    // cube cells; the key's 3 * bits bits go one at a time to the axis whose
-    // cells are currently the longest, so an elongated pile (a tall box)
-    // gets more cells along its long axis
-    double ext[3];
-    int b[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k) {
-      g.lo[k] = vals[k];
-      ext[k] = vals[3 + k] - vals[k];
-    }
-    for (int t = 0; t < 3 * P.bits; ++t) {
-      if (P.tree) {                      // the tree's pyramid needs a cubic code
-        b[t % 3]++;
-        continue;
-      }
-      int a = -1;
-      double best = -1.0;
-      for (int k = 0; k < 3; ++k) {
-        const double len = ldexp(ext[k], -b[k]);
-        if (b[k] < 10 && len > best) {
-          best = len;
-          a = k;
-        }
-      }
-      ++b[a];
-    }
-    double fit = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      g.nbits[k] = b[k];
-      g.nc[k] = 1 << b[k];
-      fit = fmax(fit, ldexp(ext[k] * (1.0 + 1e-12), -b[k]));
-    }
-    g.cell = fmax(P.cell_min, fit + 1e-300);
-  }
-  g.inv_cell = 1.0 / g.cell;
-  for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
-  // bulk radius from the second moment about aggregate 0's centre c:
-  // <|r - com|^2>_m = <|r - c|^2>_m - |com - c|^2
-  {
-    double c[3] = {0.0, 0.0, 0.0};
-    const int na = P.na, nxt = P.parity ^ 1;
-    if (na > 0 && !P.given)
-      for (int k = 0; k < 3; ++k) c[k] = P.rA[nxt][k * na];
-    double s2 = vals[10] / vals[6];
-    for (int k = 0; k < 3; ++k) s2 -= (g.com[k] - c[k]) * (g.com[k] - c[k]);
-    g.R_bulk = sqrt(fmax(s2, 0.0) * (5.0 / 3.0));
-  }
-  if (P.stop_growth > 0.0) {
-    // the stop rule: the first evaluation sets the reference radius; an
-    // evaluation at or beyond stop_growth times it stops the pile (its step
-    // is not committed, like a failure)
-    if (!(P.R0 > 0.0)) {
-      P.R0 = g.R_bulk;
-    } else if (g.R_bulk >= P.stop_growth * P.R0) {
-      atomicOr(&P.status, kStStopped);
-    }
-  }
-  // time of this evaluation: the end of the step being taken, or the
-  // current time for an evaluation in place; walls displaced rigidly by
-  // A sin(omega t + phase), moving at A omega cos(omega t + phase)
-  g.t = (double)(P.step + (mode == kModeStep ? 1 : 0)) * dt;
-  for (int w = 0; w < 6; ++w) {
-    g.wall_d[w] = 0.0;
-    for (int k = 0; k < 3; ++k) g.wall_v[w][k] = 0.0;
-  }
-  if (P.n_walls > 0) {
-    const double ph = __dadd_rn(__dmul_rn(P.wall_omega, g.t), P.wall_phase);
-    double sn, cs;
-    sincos(ph, &sn, &cs);
-    for (int w = 0; w < P.n_walls; ++w) {
-      const double* n = P.wall[w];
-      const double* A = P.wall_amp[w];
-      const double shift =
-          __dadd_rn(__dadd_rn(__dmul_rn(n[0], A[0]), __dmul_rn(n[1], A[1])), __dmul_rn(n[2], A[2]));
-      g.wall_d[w] = __dadd_rn(n[3], __dmul_rn(shift, sn));
-      for (int k = 0; k < 3; ++k) g.wall_v[w][k] = __dmul_rn(__dmul_rn(A[k], P.wall_omega), cs);
-    }
-  }
-  *P.grid = g;
+  grid_from_vals(P, vals, mode, dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -496,46 +265,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ p
   const PileDev& P = piles[w.pile];
   const int i = w.base + threadIdx.x;
   if (i >= P.ns || P.status != 0) return;
-  const int ns = P.ns, nxt = P.parity ^ 1;
-  const int cap = P.cap_pairs;
-  const uint32_t* __restrict__ up_off = P.up_off[nxt];
-  double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
-  // unrolled so that two contacts' loads are in flight (same order of sums)
-#pragma unroll 2
-  for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
-    const uint32_t p = P.lo_pair[e];
-    for (int k = 0; k < 3; ++k) {
-      f[k] -= P.pF[k * cap + p];
-      t[k] += P.pTj[k * cap + p];
-    }
-  }
-#pragma unroll 2
-  for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
-    for (int k = 0; k < 3; ++k) {
-      f[k] += P.pF[k * cap + p];
-      t[k] += P.pTi[k * cap + p];
-    }
-  }
-  if (P.G != 0.0)
-    for (int k = 0; k < 3; ++k) f[k] += P.gacc[k * ns + i];
-  for (int k = 0; k < 3; ++k) {
-    P.F[k * ns + i] = f[k];
-    P.tau[k * ns + i] = t[k];
-  }
+  gather_one(P, i);
 }
 
-// One member's share of F_A and N_A: f_i and (R b_i) x f_i + tau_i.
-__device__ __forceinline__ void add_member(const double R[9], const double f[3],
-                                           const double bb[3], const double tau[3], double FA[3],
-                                           double NA[3]) {
-  double d[3], dxf[3];
-  rot_apply(R, bb, d);
-  cross3(d, f, dxf);
-  for (int k = 0; k < 3; ++k) {
-    FA[k] += f[k];
-    NA[k] += dxf[k] + tau[k];
-  }
-}
 
 // One thread per aggregate: F_A = sum F_i, a_A = F_A / M + g,
 // N_A = sum [ (R b_i) x F_i + tau_i ] over the members in order, and in step
@@ -573,24 +305,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
   if (P.member_scan != 0) {
     // ablation of the paper's original routines: every sphere of the pile
     // tested for membership, in order
-    if (own)
-      for (int i = 0; i < ns; ++i) {
-        if (P.agg[i] != A) continue;
-        const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
-        const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
-        const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
-        add_member(R, f, bb, tau, FA, NA);
-      }
+    if (own) reduce_members_scan(P, A, R, FA, NA);
   } else if (P.member_read == 1 || (P.member_read == 0 && !stage)) {
-    // unrolled so that two members' loads are in flight (same order of sums)
-    if (own)
-#pragma unroll 2
-      for (int i = P.first[A], i1 = i + P.count[A]; i < i1; ++i) {
-        const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
-        const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
-        const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
-        add_member(R, f, bb, tau, FA, NA);
-      }
+    if (own) reduce_members_direct(P, A, R, FA, NA);
   } else {
     const int a_last = min(a0 + 64, na) - 1;
     const int s0 = P.first[a0], s1 = P.first[a_last] + P.count[a_last];
@@ -632,31 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
     }
   }
   if (!own) return;
-  const double M = P.M[A];
-  double a[3];
-  for (int k = 0; k < 3; ++k) {
-    a[k] = FA[k] / M + P.gfield[k];      // a uniform field adds no torque
-    P.aA[nxt][k * na + A] = a[k];
-    P.NA[nxt][k * na + A] = NA[k];
-  }
-  if (mode == kModeStep) {
-    double v[3];
-    for (int k = 0; k < 3; ++k) v[k] = P.vA[nxt][k * na + A] + 0.5 * cp.dt * a[k];
-    if (P.spin_dw != 0.0) {
-      // spin-up: w += dw z-hat about the pile's centre of mass
-      const Grid g = *P.grid;
-      const double dw = P.spin_dw;
-      const double rel[3] = {P.rA[nxt][A] - g.com[0], P.rA[nxt][na + A] - g.com[1],
-                             P.rA[nxt][2 * na + A] - g.com[2]};
-      const double z[3] = {0.0, 0.0, dw};
-      double dv[3], dwb[3];
-      cross3(z, rel, dv);
-      for (int k = 0; k < 3; ++k) v[k] += dv[k];
-      rot_apply_T(R, z, dwb);
-      for (int k = 0; k < 3; ++k) P.wb[nxt][k * na + A] += dwb[k];
-    }
-    for (int k = 0; k < 3; ++k) P.vA[nxt][k * na + A] = v[k];
-  }
+  reduce_tail(P, A, R, FA, NA, cp, mode);
 }
 
 // One thread per pile: commit the step (flip the ping-pong halves) unless
@@ -666,26 +359,8 @@ __global__ void k_finish(PileDev* __restrict__ piles, int n_piles, int mode, dou
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_piles) return;
   PileDev& P = piles[p];
-  if (P.status != 0) {
-    if (P.fail_step < 0) P.fail_step = P.step;
-    return;
-  }
-  const int nxt = P.parity ^ 1;
-  if (P.pert_on) {
-    // reaction on the perturber: minus the pull on every sphere, summed over
-    // the per-block partials in block order; then its closing half kick
-    double f[3] = {0.0, 0.0, 0.0};
-    for (int b = 0; b < P.n_rblk; ++b)
-      for (int k = 0; k < 3; ++k) f[k] += P.ppart[b * 3 + k];
-    for (int k = 0; k < 3; ++k) {
-      const double a = -f[k] / P.pert_M;
-      P.pert_a[nxt][k] = a;
-      if (mode == kModeStep) P.pert_v[nxt][k] += 0.5 * dt * a;
-    }
-  }
-  P.n_pairs = P.up_off[nxt][P.ns];
-  P.parity = nxt;
-  if (mode == kModeStep) P.step += 1;
+  if (P.fused) return;                       // k_fused finishes it
+  finish_one(P, mode, dt);
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
