@@ -205,14 +205,9 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
   L.add(&h.lo_off, ns + 1);
   L.add(&h.pair_j[0], cap);
   L.add(&h.pair_j[1], cap);
-  L.add(&h.pair_i, cap);
   L.add(&h.hist[0], kHist * cap);
   L.add(&h.hist[1], kHist * cap);
   L.add(&h.lo_nbr, cap);
-  L.add(&h.lo_pair, cap);
-  L.add(&h.pF, 3 * cap);
-  L.add(&h.pTi, 3 * cap);
-  L.add(&h.pTj, 3 * cap);
 }
 
 double dashpot_factor(double eps) {
@@ -490,13 +485,13 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
 }
 
 // Kernel families of one step, in launch order (profiling names).
-constexpr int kNumStages = 17;
+constexpr int kNumStages = 16;
 constexpr int kStageGravity = 11;
-constexpr int kStageFusedA = 15;           // k_fused parts 1 and 3
-constexpr int kStageFusedB = 16;           // k_fused part 2
+constexpr int kStageFusedA = 14;           // k_fused parts 1 and 3
+constexpr int kStageFusedB = 15;           // k_fused part 2
 const char* const kStageNames =
     "integrate;reconstruct;grid;bin;scan_cells;scatter;cell_sort;search_count;"
-    "scan_pairs;search_write;pairs;gravity;gather;reduce;finish;fused_a;fused_b";
+    "scan_pairs;search_write;forces;gravity;reduce;finish;fused_a;fused_b";
 
 // Second stream and fork/join events of a batch (default priority).
 hipError_t ensure_side(Batch& b) {
@@ -518,7 +513,7 @@ void release_side(Batch& b) {
 // Enqueue one pass of the step (mode kModeStep or kModeInit) for a batch.
 // mark(k, stream, begin) is called before (begin) and after each stage k on
 // the stream that runs it.  Gravity depends only on the sorted copies of the
-// cell sort and is read only by the gather, so with `overlap` it runs on the
+// cell sort and is read only by the member reduction, so with `overlap` it runs on the
 // batch's second stream beside the search, scan and force kernels (the
 // captured step); without, every stage runs in order on one stream (the
 // t0 evaluation, the stateless hooks, and the profiled passes, whose event
@@ -584,18 +579,17 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark, bool ove
     if (b.n_big_blk) launch_search_big(s, b.d_table, b.wl_big, b.n_big_blk, 1);
   });
   stage(10, st, staged, [&](hipStream_t s) {
-    launch_pairs(s, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
+    launch_forces(s, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   });
   if (fork) (void)hipStreamWaitEvent(st, b.join_ev, 0);
   else stage(kStageGravity, st, b.any_grav, gravity);
   stage(kStageFusedB, st, b.n_fused_g > 0, [&](hipStream_t s) {
     launch_fused(s, b.d_table, b.pl_fused_g, b.n_fused_g, b.cp, mode, 2, b.precision);
   });
-  stage(12, st, staged, [&](hipStream_t s) { launch_gather(s, b.d_table, b.wl_sph, b.n_sph_blk); });
-  stage(13, st, staged, [&](hipStream_t s) {
+  stage(12, st, staged, [&](hipStream_t s) {
     launch_reduce(s, b.d_table, b.wl_agg, b.n_agg_blk, b.cp, mode, b.reduce_stage);
   });
-  stage(14, st, staged, [&](hipStream_t s) { launch_finish(s, b.d_table, np, mode, b.cp.dt); });
+  stage(13, st, staged, [&](hipStream_t s) { launch_finish(s, b.d_table, np, mode, b.cp.dt); });
 }
 
 void enqueue_pass(Batch& b, hipStream_t st, int mode, bool overlap = false) {
@@ -1008,7 +1002,6 @@ NoAllocPlan plan_noalloc(char* base, int64_t n, PileDev& h) {
   h.lo_off = L.take<uint32_t>(n + 1);
   h.pair_j[0] = L.take<uint32_t>(kNoAllocMaxPairs);
   h.pair_j[1] = L.take<uint32_t>(kNoAllocMaxPairs);
-  h.pair_i = L.take<uint32_t>(kNoAllocMaxPairs);
   h.lo_nbr = L.take<uint32_t>(kNoAllocMaxPairs);
   q.bytes = L.off;
   return q;
@@ -1264,6 +1257,14 @@ dem_status dem_read_state(dem_sim* s, dem_state* out) {
   rows(h.tau, 3, ns, out->sph_torque);
   rows(h.b, 3, ns, out->sph_body);
   if (r != DEM_OK) return r;
+  if (out->sph_force && h.G != 0.0) {
+    // the device keeps the contact force; the gravity force is added after
+    // it, in the order (and so with the rounding) of the member reduction
+    std::vector<double> ga(3 * ns);
+    r = fetch_rows(s, h.gacc, 3, ns, ga.data(), st);
+    if (r != DEM_OK) return r;
+    for (int64_t k = 0; k < 3 * ns; ++k) out->sph_force[k] += ga[k];
+  }
   if (out->agg_spin) {
     // space-frame spin R(q) w_b of the current state
     std::vector<double> q(4 * na), wb(3 * na);
@@ -1875,8 +1876,7 @@ dem_status dem_contact_forces(const dem_params* params, int64_t n, const double*
               b.max_items_pairs);
   launch_search(st, b.d_table, b.wl_sph, b.n_sph_blk, 1);
   if (b.n_big_blk) launch_search_big(st, b.d_table, b.wl_big, b.n_big_blk, 1);
-  launch_pairs(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
-  launch_gather(st, b.d_table, b.wl_sph, b.n_sph_blk);
+  launch_forces(st, b.d_table, b.wl_sph, b.n_sph_blk, b.cp, b.precision);
   HIPCHK(s, hipGetLastError());
   PileDev tmp;
   HIPCHK(s, hipMemcpyAsync(&tmp, b.d_table, sizeof(PileDev), hipMemcpyDeviceToHost, st));

@@ -156,8 +156,8 @@ struct PileDev {
   // sphere per-step
   double* r;                 // [3][ns]
   double* v;                 // [3][ns]
-  double* F;                 // [3][ns]
-  double* tau;               // [3][ns]
+  double* F;                 // [3][ns] contact force (gravity is added by the reduction)
+  double* tau;               // [3][ns] contact torque about the centre
   uint32_t* key;             // [ns] Morton cell code
   uint32_t* sidx;            // [ns] sphere at sorted slot
   uint32_t* sidx_raw;        // [ns] sphere at slot, in atomic arrival order
@@ -179,13 +179,8 @@ struct PileDev {
   uint32_t* up_off[2];       // [ns + 1] CSR of contacts (i, j>i) by i
   uint32_t* lo_off;          // [ns + 1] CSR of contacts (j<i, i) by i
   uint32_t* pair_j[2];       // [cap]
-  uint32_t* pair_i;          // [cap] owner i of each contact of the current upper list
   double* hist[2];           // [kHist][cap]
   uint32_t* lo_nbr;          // [cap] lower neighbour ids
-  uint32_t* lo_pair;         // [cap] index of (j, i) in the upper list
-  double* pF;                // [3][cap] force on i of contact (i, j)
-  double* pTi;               // [3][cap] torque on i about its centre
-  double* pTj;               // [3][cap] torque on j about its centre
 };
 
 // One block of a per-element kernel: pile p, elements base .. base+255.
@@ -234,8 +229,8 @@ void launch_cell_sort(hipStream_t st, const PileDev* piles, const WorkItem* wl, 
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write);
 void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                        int write);
-void launch_pairs(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
-                  ContactParams cp, int precision);
+void launch_forces(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
+                   ContactParams cp, int precision);
 // Gravity: records and the per-slot combine cover every pile; the tile-pair
 // kernel runs once per tile size present in the batch.
 void launch_gravity_records(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
@@ -246,7 +241,6 @@ void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem
                             int precision);
 // Supported tile sizes for a precision (default first); returns the count.
 int gravity_tiles(int precision, int* tiles);
-void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk);
 // Aggregates in one launch from which the member reduction stages its
 // members through LDS (below it, direct member reads are faster: few waves,
 // and the members stay in L2 between a wave's member iterations).
@@ -367,6 +361,18 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
 }
 
+// A product and a sum, each rounded on its own: compiled without
+// contraction, so no fused multiply-add forms across them where they are
+// inlined (a plain a * b + c may become one).
+__device__ __forceinline__ double rn_mul(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ double rn_add(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
 // Signed distance of a point from wall w at the evaluation time (plane
 // offset d_t = Grid::wall_d[w]), rounded step by step (no fused
 // multiply-add) so that the contact decision is reproducible:
@@ -374,8 +380,8 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 __device__ __forceinline__ double wall_gap(const PileDev& P, int w, double d_t, double x, double y,
                                            double z) {
   const double* n = P.wall[w];
-  const double s = __dadd_rn(__dadd_rn(__dmul_rn(n[0], x), __dmul_rn(n[1], y)), __dmul_rn(n[2], z));
-  return __dadd_rn(s, -d_t);
+  const double s = rn_add(rn_add(rn_mul(n[0], x), rn_mul(n[1], y)), rn_mul(n[2], z));
+  return rn_add(s, -d_t);
 }
 
 }  // namespace dem

@@ -256,20 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
 // GetAccelAndTorque (Eqs. 5-7, 9) and the closing half kick
 // ---------------------------------------------------------------------------
 
-// One thread per sphere: its contact force and torque gathered in canonical
-// contact order -- contacts (j, i) with j < i by increasing j, then (i, j) by
-// increasing j (walls last) -- plus its gravity force.
-__global__ __launch_bounds__(kBlock) void k_gather(const PileDev* __restrict__ piles,
-                                                   const WorkItem* __restrict__ wl) {
-  const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];
-  const PileDev& P = piles[w.pile];
-  const int i = w.base + threadIdx.x;
-  if (i >= P.ns || P.status != 0) return;
-  gather_one(P, i);
-}
-
-
-// One thread per aggregate: F_A = sum F_i, a_A = F_A / M + g,
+// One thread per aggregate: F_A = sum F_i (F_i a member's contact force,
+// plus its gravity force in a pile with gravity), a_A = F_A / M + g,
 // N_A = sum [ (R b_i) x F_i + tau_i ] over the members in order, and in step
 // mode v_A += h/2 a_A followed by the spin-up increment about +z through the
 // pile's centre.  Members are added in member order, read in one of two
@@ -317,12 +305,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const PileDev* __restrict__ p
     // next slice's nine loads are in flight while the lanes add this one.
     typedef const __attribute__((address_space(1))) double* GlobalD;
     const GlobalD gF = (GlobalD)P.F, gb = (GlobalD)P.b, gt = (GlobalD)P.tau;
+    const GlobalD gg = (GlobalD)P.gacc;
+    const bool grav = P.G != 0.0;
     double v[9];
     auto fetch = [&](int c) {
       const int t = c + lane;
       if (t < s1)
         for (int k = 0; k < 3; ++k) {
           v[k] = gF[k * ns + t];
+          if (grav) v[k] += gg[k * ns + t];     // gravity after the contacts
           v[3 + k] = gb[k * ns + t];
           v[6 + k] = gt[k * ns + t];
         }
@@ -388,10 +379,6 @@ void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl
 void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, double dt) {
   hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), mode,
                      dt);
-}
-
-void launch_gather(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk) {
-  hipLaunchKernelGGL(k_gather, dim3(nblk), dim3(kBlock), 0, st, piles, wl);
 }
 
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,

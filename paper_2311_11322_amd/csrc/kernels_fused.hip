@@ -4,8 +4,8 @@
 // over every pile of a batch) is bound by launch latency, one workgroup of
 // kFusedThreads threads runs every stage of its pile in order, separated by
 // workgroup barriers: kick/drift/rotate, member reconstruction, cell grid,
-// binning and counting sort, contact search, contact forces, per-sphere
-// gather, member reduction and end-of-step bookkeeping.  Many piles run as
+// binning and counting sort, contact search, per-sphere contact forces,
+// member reduction and end-of-step bookkeeping.  Many piles run as
 // many workgroups of one launch.  Gravity, when the pile has it, stays with
 // the batched tile kernels (it would not fit one compute unit): the launch
 // then covers the stages before gravity (part 1) and a second launch those
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(PileDev* __restrict__ p
       // contact forces with the spring history
       const PairCtx<T> c = pair_ctx<T>(P, cp);
       bool bad = false;
-      for (uint32_t p = tid; p < c.n_pairs; p += kFusedThreads) pair_one<T>(P, c, cp, p, bad);
+      for (int i = tid; i < P.ns; i += kFusedThreads) forces_one<T>(P, c, cp, (uint32_t)i, bad);
       if (bad) atomicOr(&P.status, kStUnstable);
       stage_sync();
       ok = status_of(P) == 0;
@@ -164,8 +164,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(PileDev* __restrict__ p
   }
   if (part & 2) {
     if (ok) {
-      for (int i = tid; i < P.ns; i += kFusedThreads) gather_one(P, i);
-      stage_sync();
       const int na = P.na, nxt = P.parity ^ 1;
       for (int A = tid; A < na; A += kFusedThreads) {
         double q[4], R[9];

@@ -542,13 +542,13 @@ __global__ __launch_bounds__(64) void k_tree_walk(const PileDev* __restrict__ pi
         const uint32_t ix[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
         double dd[3];
         for (int a = 0; a < 3; ++a) {
-          const double ctr = __dadd_rn(g.lo[a], __dmul_rn((double)ix[a] + 0.5, side));
-          dd[a] = fmax(fmax(__dadd_rn(bmin[a], -ctr), __dadd_rn(ctr, -bmax[a])), 0.0);
+          const double ctr = rn_add(g.lo[a], rn_mul((double)ix[a] + 0.5, side));
+          dd[a] = fmax(fmax(rn_add(bmin[a], -ctr), rn_add(ctr, -bmax[a])), 0.0);
         }
-        const double dist2 = __dadd_rn(__dadd_rn(__dmul_rn(dd[0], dd[0]), __dmul_rn(dd[1], dd[1])),
-                                       __dmul_rn(dd[2], dd[2]));
+        const double dist2 = rn_add(rn_add(rn_mul(dd[0], dd[0]), rn_mul(dd[1], dd[1])),
+                                       rn_mul(dd[2], dd[2]));
         const double thr = side / theta;
-        if (dist2 > __dmul_rn(thr, thr)) kind = 1;
+        if (dist2 > rn_mul(thr, thr)) kind = 1;
         else if (t1 - t0 <= (uint32_t)P.tree_leaf || l == L) kind = 2;
         else kind = 3;
       }

@@ -280,51 +280,28 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
     for (int k = 0; k < 3; ++k) g.wall_v[w][k] = 0.0;
   }
   if (P.n_walls > 0) {
-    const double ph = __dadd_rn(__dmul_rn(P.wall_omega, g.t), P.wall_phase);
+    const double ph = rn_add(rn_mul(P.wall_omega, g.t), P.wall_phase);
     double sn, cs;
     sincos(ph, &sn, &cs);
     for (int w = 0; w < P.n_walls; ++w) {
       const double* n = P.wall[w];
       const double* A = P.wall_amp[w];
       const double shift =
-          __dadd_rn(__dadd_rn(__dmul_rn(n[0], A[0]), __dmul_rn(n[1], A[1])), __dmul_rn(n[2], A[2]));
-      g.wall_d[w] = __dadd_rn(n[3], __dmul_rn(shift, sn));
-      for (int k = 0; k < 3; ++k) g.wall_v[w][k] = __dmul_rn(__dmul_rn(A[k], P.wall_omega), cs);
+          rn_add(rn_add(rn_mul(n[0], A[0]), rn_mul(n[1], A[1])), rn_mul(n[2], A[2]));
+      g.wall_d[w] = rn_add(n[3], rn_mul(shift, sn));
+      for (int k = 0; k < 3; ++k) g.wall_v[w][k] = rn_mul(rn_mul(A[k], P.wall_omega), cs);
     }
   }
   *P.grid = g;
 }
 
-// One sphere: its contact force and torque gathered in canonical contact
-// order -- contacts (j, i) with j < i by increasing j, then (i, j) by
-// increasing j (walls last) -- plus its gravity force.
-__device__ __forceinline__ void gather_one(const PileDev& P, int i) {
-  const int ns = P.ns, nxt = P.parity ^ 1;
-  const int cap = P.cap_pairs;
-  const uint32_t* __restrict__ up_off = P.up_off[nxt];
-  double f[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
-  // unrolled so that two contacts' loads are in flight (same order of sums)
-#pragma unroll 2
-  for (uint32_t e = P.lo_off[i], e1 = P.lo_off[i + 1]; e < e1; ++e) {
-    const uint32_t p = P.lo_pair[e];
-    for (int k = 0; k < 3; ++k) {
-      f[k] -= P.pF[k * cap + p];
-      t[k] += P.pTj[k * cap + p];
-    }
-  }
-#pragma unroll 2
-  for (uint32_t p = up_off[i], p1 = up_off[i + 1]; p < p1; ++p) {
-    for (int k = 0; k < 3; ++k) {
-      f[k] += P.pF[k * cap + p];
-      t[k] += P.pTi[k * cap + p];
-    }
-  }
+// Force on sphere i: its contact force plus, in a pile with gravity, its
+// gravity force (added last, after the contacts).
+__device__ __forceinline__ void sphere_force(const PileDev& P, int i, double f[3]) {
+  const int ns = P.ns;
+  for (int k = 0; k < 3; ++k) f[k] = P.F[k * ns + i];
   if (P.G != 0.0)
     for (int k = 0; k < 3; ++k) f[k] += P.gacc[k * ns + i];
-  for (int k = 0; k < 3; ++k) {
-    P.F[k * ns + i] = f[k];
-    P.tau[k * ns + i] = t[k];
-  }
 }
 
 // One member's share of F_A and N_A: f_i and (R b_i) x f_i + tau_i.
@@ -347,7 +324,8 @@ __device__ __forceinline__ void reduce_members_direct(const PileDev& P, int A, c
   // unrolled so that two members' loads are in flight (same order of sums)
 #pragma unroll 2
   for (int i = P.first[A], i1 = i + P.count[A]; i < i1; ++i) {
-    const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
+    double f[3];
+    sphere_force(P, i, f);
     const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
     const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
     add_member(R, f, bb, tau, FA, NA);
@@ -361,7 +339,8 @@ __device__ __forceinline__ void reduce_members_scan(const PileDev& P, int A, con
   const int ns = P.ns;
   for (int i = 0; i < ns; ++i) {
     if (P.agg[i] != A) continue;
-    const double f[3] = {P.F[i], P.F[ns + i], P.F[2 * ns + i]};
+    double f[3];
+    sphere_force(P, i, f);
     const double bb[3] = {P.b[i], P.b[ns + i], P.b[2 * ns + i]};
     const double tau[3] = {P.tau[i], P.tau[ns + i], P.tau[2 * ns + i]};
     add_member(R, f, bb, tau, FA, NA);

@@ -84,8 +84,8 @@ __device__ __forceinline__ bool touching(double dx, double dy, double dz, double
     if (dz > hL) dz -= L;
     else if (dz < -hL) dz += L;
   }
-  const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-  return d2 < __dmul_rn(S, S);
+  const double d2 = rn_add(rn_add(rn_mul(dx, dx), rn_mul(dy, dy)), rn_mul(dz, dz));
+  return d2 < rn_mul(S, S);
 }
 
 // Insertion sort of a short run of ids in global memory.
@@ -144,7 +144,6 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
 
   uint32_t* up_out = nullptr;
   uint32_t* lo_out = nullptr;
-  uint32_t* own_out = nullptr;
   uint32_t run_up = 0, run_lo = 0;
   if (write) {
     const uint32_t tot_up = P.up_off[nxt][ns], tot_lo = P.lo_off[ns];
@@ -154,16 +153,12 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
     }
     const uint32_t u0 = P.up_off[nxt][i], l0 = P.lo_off[i];
     up_out = P.pair_j[nxt] + u0;
-    own_out = P.pair_i + u0;
     lo_out = P.lo_nbr + l0;
     run_up = P.up_off[nxt][i + 1] - u0;
     run_lo = P.lo_off[i + 1] - l0;
     if (run_up <= (uint32_t)kRunLds && run_lo <= (uint32_t)kRunLds) {
       // the find pass kept both runs, sorted
-      for (uint32_t e = lane; e < run_up; e += kLanes) {
-        up_out[e] = cache_up[e];
-        own_out[e] = i;
-      }
+      for (uint32_t e = lane; e < run_up; e += kLanes) up_out[e] = cache_up[e];
       for (uint32_t e = lane; e < run_lo; e += kLanes) lo_out[e] = cache_lo[e];
       return;
     }
@@ -250,7 +245,6 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
   __builtin_amdgcn_wave_barrier();
   if (write) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    for (uint32_t e = lane; e < run_up; e += kLanes) own_out[e] = i;
     if (lane == 0) {
       sort_run(up_out, run_up);
       sort_run(lo_out, run_lo);
@@ -387,14 +381,12 @@ __device__ __forceinline__ void search_big_one(PileDev& P, int kb, int write, in
     return;
   }
   uint32_t* up_out = P.pair_j[nxt] + P.up_off[nxt][i];
-  uint32_t* own_out = P.pair_i + P.up_off[nxt][i];
   uint32_t* lo_out = P.lo_nbr + P.lo_off[i];
   for (uint32_t e = tid; e < run_up; e += nthreads) {
     const uint32_t v = buf_up[e];
     uint32_t r = 0;
     for (uint32_t f = 0; f < run_up; ++f) r += buf_up[f] < v;
     up_out[r] = v;
-    own_out[e] = i;
   }
   for (uint32_t e = tid; e < run_lo; e += nthreads) {
     const uint32_t v = buf_lo[e];

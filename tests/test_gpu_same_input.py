@@ -93,3 +93,39 @@ def test_contact_forces_same_input(D, kind, seed):
     e32 = {k: rel_err(g32[k], ref[k]) for k in ("F", "tau", "hist")}
     print("FP32-force same-input errors", e32, flush=True)
     assert all(v <= 1e-5 for v in e32.values()), e32
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_both_spheres_of_a_contact_see_the_same_force(D, prec):
+    """Each contact is evaluated by both of its spheres; with isolated pairs
+    (one contact per sphere) the two contact forces must be exact negatives
+    of each other, bit for bit, in both precision forms."""
+    say("isolated pairs, antisymmetry, precision", prec)
+    rng = np.random.default_rng(77 + prec)
+    n_pair = 400
+    ra = rng.uniform(0.5, 1.5, n_pair)
+    rb = rng.uniform(0.5, 1.5, n_pair)
+    u = rng.normal(size=(n_pair, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    d = (ra + rb) * rng.uniform(0.97, 0.999, n_pair)
+    base = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"),
+                    -1).reshape(-1, 3)[:n_pair] * 10.0
+    pos = np.empty((2 * n_pair, 3))
+    pos[0::2] = base
+    pos[1::2] = base + d[:, None] * u
+    radius = np.empty(2 * n_pair)
+    radius[0::2], radius[1::2] = ra, rb
+    agg = np.arange(2 * n_pair, dtype=np.int32)
+    mass = rng.uniform(0.5, 2.0, 2 * n_pair)
+    vel = rng.normal(0.0, 0.3, (2 * n_pair, 3))
+    spin = rng.normal(0.0, 0.5, (2 * n_pair, 3))
+    # previous contacts: every other pair, with a spring history
+    old = np.arange(0, n_pair, 2)
+    keys = (old * 2).astype(np.uint64) << np.uint64(32) | (old * 2 + 1).astype(np.uint64)
+    hist = rng.normal(0.0, 0.02, (old.size, 7))
+    prm = dict(W.CONTACT_PARAMS, dt=1e-4, G=0.0, soft_frac=0.5, periodic=0)
+    g = D.contact_forces(prm, pos, vel, radius, agg, mass, spin, keys, hist, precision=prec)
+    assert g["keys"].size == n_pair
+    Fa, Fb = g["F"][0::2], g["F"][1::2]
+    assert np.all(np.abs(Fa).max(axis=1) > 0)
+    assert np.array_equal(Fa, -Fb)
