@@ -40,8 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PileDev* __restrict__ 
 // Order each cell's spheres by id, independent of atomic arrival order: the
 // sphere at raw slot k goes to its cell's start plus its rank (the number of
 // smaller ids in the cell).  The same thread writes the sphere's sorted
-// copies there -- positions and radius for gravity, packed records for the
-// search -- and the inverse permutation.
+// copies there -- packed records for the search and, in a pile with
+// gravity, positions and radius for it -- and the inverse permutation.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict__ piles,
                                                       const WorkItem* __restrict__ wl) {
   const WorkItem w = wl[xcd_block(blockIdx.x, gridDim.x)];

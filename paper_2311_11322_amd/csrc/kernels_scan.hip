@@ -1,10 +1,10 @@
 // kernels_scan.hip -- batched exclusive prefix sum of uint32 arrays.
 //
 // Many independent segments (the cell counts and contact counts of every
-// pile) are scanned by the same three launches: per-chunk totals, a scan of
-// each segment's chunk totals (one block per segment), and the chunk-local
-// scans with their offsets; or, when every segment is short, by one launch
-// with a block per segment.  out[n] of each segment receives its total.
+// pile) are scanned by the same two launches: per-chunk totals, then the
+// chunk-local scans, each chunk adding up the totals before it in its
+// segment; or, when every segment is short, by one launch with a block per
+// segment.  out[n] of each segment receives its total.
 // Integer arithmetic, so the result does not depend on the order of work.
 #include "dem_internal.h"
 
@@ -95,32 +95,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const ScanSeg* __restric
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// One block per segment: exclusive scan of the segment's chunk totals in
-// place, and the segment total into out[n].
-__global__ __launch_bounds__(kBlock) void k_scan_chunks(const ScanSeg* __restrict__ segs,
-                                                        uint32_t* __restrict__ sums) {
-  const ScanSeg sg = segs[blockIdx.x];
-  uint32_t carry = 0;
-  for (int c0 = 0; c0 < sg.n_items; c0 += kBlock) {
-    const int c = c0 + threadIdx.x;
-    const uint32_t v = c < sg.n_items ? sums[sg.item0 + c] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_exclusive(v, &total);
-    if (c < sg.n_items) sums[sg.item0 + c] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) {
-    uint32_t* out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
-    out[sg.n] = carry;
-  }
-}
-
+// One block per chunk: the chunk's offset is the sum of the totals of the
+// segment's earlier chunks (read by the whole block), then the chunk-local
+// scan; the segment's last chunk also writes the total into out[n].
 __global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict__ segs,
                                                       const ScanItem* __restrict__ items,
                                                       const uint32_t* __restrict__ sums) {
   const ScanItem it = items[blockIdx.x];
   const ScanSeg sg = segs[it.seg];
   uint32_t* __restrict__ out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
+  uint32_t part = 0;
+  for (int c = threadIdx.x; c < it.chunk; c += kBlock) part += sums[sg.item0 + c];
+  uint32_t offset;
+  block_exclusive(part, &offset);
   const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
   uint32_t v[kScanItems], r[kScanItems];
   load_run(sg.in, base, sg.n, v);
@@ -128,8 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict_
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) acc += v[k];
   uint32_t total;
-  run_prefix(v, block_exclusive(acc, &total) + sums[blockIdx.x], r);
+  run_prefix(v, block_exclusive(acc, &total) + offset, r);
   store_run(out, base, sg.n, r);
+  if (it.chunk == sg.n_items - 1 && threadIdx.x == 0) out[sg.n] = offset + total;
 }
 
 // One block per segment scans the whole segment chunk by chunk, carrying the
@@ -163,7 +151,6 @@ void launch_scan(hipStream_t st, const ScanSeg* segs, int n_segs, const ScanItem
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
-  hipLaunchKernelGGL(k_scan_chunks, dim3(n_segs), dim3(kBlock), 0, st, segs, item_sums);
   hipLaunchKernelGGL(k_scan_down, dim3(n_items), dim3(kBlock), 0, st, segs, items, item_sums);
 }
 

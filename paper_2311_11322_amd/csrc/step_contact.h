@@ -48,8 +48,8 @@ __device__ __forceinline__ void scatter_one(const PileDev& P, int i) {
 // Order one cell's spheres by id, independent of atomic arrival order: the
 // sphere at raw slot k goes to its cell's start plus its rank (the number of
 // smaller ids in the cell).  The same thread writes the sphere's sorted
-// copies there -- positions and radius for gravity, packed records for the
-// search -- and the inverse permutation.
+// copies there -- packed records for the search and, in a pile with
+// gravity, positions and radius for it -- and the inverse permutation.
 __device__ __forceinline__ void cell_sort_one(const PileDev& P, int k) {
   const int ns = P.ns;
   const uint32_t* __restrict__ raw = P.sidx_raw;
@@ -62,10 +62,12 @@ __device__ __forceinline__ void cell_sort_one(const PileDev& P, int k) {
   P.sidx[d] = i;
   P.slot[i] = d;
   const double x = P.r[i], y = P.r[ns + i], z = P.r[2 * ns + i], s = P.s[i];
-  P.xs[d] = x;
-  P.xs[ns + d] = y;
-  P.xs[2 * ns + d] = z;
-  P.xs[3 * ns + d] = s;
+  if (P.G != 0.0) {                          // only gravity reads these copies
+    P.xs[d] = x;
+    P.xs[ns + d] = y;
+    P.xs[2 * ns + d] = z;
+    P.xs[3 * ns + d] = s;
+  }
   P.xg[d] = SortedGeom{x, y, z, s};
   P.sid[d] = SortedId{P.agg[i], i};
 }

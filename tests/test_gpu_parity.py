@@ -31,7 +31,7 @@ def say(*a):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n_agg,periodic", [(1, False), (2, True), (150, True), (150, False),
-                                            (700, True), (700, False)])
+                                            (700, True), (700, False), (2500, True)])
 def test_find_contacts_bit_exact(D, n_agg, periodic):
     say("find_contacts", n_agg, periodic)
     w = W.periodic_box(21 + n_agg, n_agg=n_agg, contact_seeded=True)
