@@ -345,10 +345,10 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, 
     if (x >= L) x -= L;
     else if (x < 0.0) x += L;
   }
-  int c = (int)floor((x - lo) * inv_cell);
-  c = c < 0 ? 0 : c;
-  c = c > n - 1 ? n - 1 : c;
-  return c;
+  // clamped before the conversion: a sphere far outside the grid falls into
+  // its outermost cell
+  const double c = fmin(fmax(floor((x - lo) * inv_cell), 0.0), (double)(n - 1));
+  return (int)c;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own

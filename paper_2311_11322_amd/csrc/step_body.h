@@ -197,7 +197,8 @@ __device__ __forceinline__ void reconstruct_one(const PileDev& P, int i, const d
 // The pile's cell grid, centre of mass, bulk radius and stop rule, wall
 // offsets and velocities, from the reduced partials of all its spheres.
 // Cells are at least one largest-sphere diameter; an open pile's grid spans
-// its bounding box.
+// its bounding box, or only the part of it within three rms radii of the
+// centre of mass when that is smaller.
 __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], int mode,
                                                double dt) {
   Grid g;
@@ -207,6 +208,20 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
     atomicOr(&P.status, kStUnstable);
     return;
   }
+  for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
+  // second moment about the centre of mass, from the one about aggregate 0's
+  // centre c: <|r - com|^2>_m = <|r - c|^2>_m - |com - c|^2
+  double s2;
+  {
+    double c[3] = {0.0, 0.0, 0.0};
+    const int na = P.na, nxt = P.parity ^ 1;
+    if (na > 0 && !P.given)
+      for (int k = 0; k < 3; ++k) c[k] = P.rA[nxt][k * na];
+    s2 = vals[10] / vals[6];
+    for (int k = 0; k < 3; ++k) s2 -= (g.com[k] - c[k]) * (g.com[k] - c[k]);
+    s2 = fmax(s2, 0.0);
+  }
+  g.R_bulk = sqrt(s2 * (5.0 / 3.0));
   if (P.periodic) {
     for (int k = 0; k < 3; ++k) {
       g.nc[k] = P.n_periodic;
@@ -215,14 +230,32 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
     g.lo[0] = g.lo[1] = g.lo[2] = 0.0;
     g.cell = P.box / (double)P.n_periodic;
   } else {
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = vals[k];
+      hi[k] = vals[3 + k];
+    }
+    if (!P.tree && !P.given && P.na > 0) {
+      // a few spheres thrown far from the rest would make every cell of a
+      // bounding-box grid large and crowd the rest into a few cells; the
+      // grid covers three rms radii about the centre of mass instead, and a
+      // sphere beyond it falls into an outermost cell (clamping keeps two
+      // spheres in contact within one cell of each other on every axis, so
+      // the 27-cell search still finds every contact)
+      const double h = 3.0 * sqrt(s2) + P.cell_min;
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fmax(lo[k], g.com[k] - h);
+        hi[k] = fmax(lo[k], fmin(hi[k], g.com[k] + h));
+      }
+    }
     // cube cells; the key's 3 * bits bits go one at a time to the axis whose
     // cells are currently the longest, so an elongated pile (a tall box)
     // gets more cells along its long axis
     double ext[3];
     int b[3] = {0, 0, 0};
     for (int k = 0; k < 3; ++k) {
-      g.lo[k] = vals[k];
-      ext[k] = vals[3 + k] - vals[k];
+      g.lo[k] = lo[k];
+      ext[k] = hi[k] - lo[k];
     }
     for (int t = 0; t < 3 * P.bits; ++t) {
       if (P.tree) {                      // the tree's pyramid needs a cubic code
@@ -249,18 +282,6 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
     g.cell = fmax(P.cell_min, fit + 1e-300);
   }
   g.inv_cell = 1.0 / g.cell;
-  for (int k = 0; k < 3; ++k) g.com[k] = vals[7 + k] / vals[6];
-  // bulk radius from the second moment about aggregate 0's centre c:
-  // <|r - com|^2>_m = <|r - c|^2>_m - |com - c|^2
-  {
-    double c[3] = {0.0, 0.0, 0.0};
-    const int na = P.na, nxt = P.parity ^ 1;
-    if (na > 0 && !P.given)
-      for (int k = 0; k < 3; ++k) c[k] = P.rA[nxt][k * na];
-    double s2 = vals[10] / vals[6];
-    for (int k = 0; k < 3; ++k) s2 -= (g.com[k] - c[k]) * (g.com[k] - c[k]);
-    g.R_bulk = sqrt(fmax(s2, 0.0) * (5.0 / 3.0));
-  }
   if (P.stop_growth > 0.0) {
     // the stop rule: the first evaluation sets the reference radius; an
     // evaluation at or beyond stop_growth times it stops the pile (its step

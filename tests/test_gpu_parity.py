@@ -128,6 +128,39 @@ def test_step_parity_gravity_and_contacts(D):
     print("step1", e1, "\nstep4", e4)
 
 
+def test_far_outliers_parity(D):
+    """An open pile with pairs of touching spheres far outside it: the grid
+    then covers only the pile's core and the outliers fall into its
+    outermost cells; contacts (those of the outlier pairs included) and the
+    state still agree with the oracle."""
+    say("collapse cloud with far outlier pairs")
+    w = W.collapse_cloud(45, n_agg=250, contact_seeded=True, spin_sigma=0.3, vel_sigma=0.1)
+    com = (w.mass[:, None] * w.pos).sum(0) / w.mass.sum()
+    r0 = float(w.radius[0])
+    pos, rad = [], []
+    for d, u in (((1000.0, 0.0, 0.0), (0.0, 0.6, 0.8)), ((0.0, -800.0, 0.0), (1.0, 0.0, 0.0)),
+                 ((0.0, 0.0, 1500.0), (0.6, 0.0, 0.8)), ((-700.0, 600.0, -500.0), (0.0, 0.0, 1.0))):
+        a = com + np.array(d)
+        pos += [a, a + 0.99 * 2.0 * r0 * np.array(u)]
+        rad += [r0, r0]
+    pos, rad = np.array(pos), np.array(rad)
+    w = W.Workload("outliers", np.concatenate([w.counts, np.ones(8, np.int32)]),
+                   np.concatenate([w.pos, pos]), np.concatenate([w.radius, rad]),
+                   np.concatenate([w.mass, W.sphere_mass(rad)]),
+                   np.concatenate([w.agg_vel, np.zeros((8, 3))]),
+                   np.concatenate([w.agg_spin, np.zeros((8, 3))]), w.params, w.n_steps)
+    sim, o = _pair(D, w)
+    compare_states(sim, o)
+    keys = sim.read_state([], pairs=True)["pair_keys"]
+    n = w.n_sph
+    for k in range(4):
+        pair = (np.uint64(n - 8 + 2 * k) << np.uint64(32)) | np.uint64(n - 7 + 2 * k)
+        assert pair in keys
+    sim.step(3)
+    o.step(3)
+    compare_states(sim, o, tol=1e-10)
+
+
 def test_fp32_force_form_parity(D):
     """FP32 pair forces and gravity on relative coordinates: per-sphere
     force within 1e-5 of the FP64 oracle (max norm), contact list exact."""
