@@ -245,6 +245,9 @@ int gravity_tiles(int precision, int* tiles);
 // members through LDS (below it, direct member reads are faster: few waves,
 // and the members stay in L2 between a wave's member iterations).
 constexpr int64_t kReduceStageMin = 131072;
+// Spheres in one search launch from which each sphere gets four lanes
+// instead of eight.
+constexpr int64_t kSearchLargeLaunch = 32768;
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int mode, bool stage);
 void launch_finish(hipStream_t st, PileDev* piles, int n_piles, int mode, double dt);

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict_
   cell_sort_one(P, k);
 }
 
-// kLanes lanes per sorted slot.  Every lane tests the spheres of its share of
+// L lanes per sorted slot.  Every lane tests the spheres of its share of
 // the 27 neighbouring cells that belong to another aggregate, and its share
 // of the walls.
 //
@@ -60,20 +60,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(const PileDev* __restrict_
 // runs themselves sorted by id in the slot's cache.  Write mode (after the
 // scan) checks the pile's contact capacity and copies each cached run to its
 // offsets; a sphere whose runs did not fit is searched again and its runs
-// written in arrival order, then sorted in place.  Launched with kLanes
-// blocks per work item.
+// written in arrival order, then sorted in place.  Launched with L blocks
+// per work item.
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_search(PileDev* __restrict__ piles,
                                                    const WorkItem* __restrict__ wl, int write) {
+  constexpr int kGroups = SearchLanes<L>::kGroups;
   __shared__ uint32_t buf_up[kGroups][kRunLds];
   __shared__ uint32_t buf_lo[kGroups][kRunLds];
   __shared__ uint32_t fill[kGroups][2];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const WorkItem w = wl[blk / kLanes];
+  const WorkItem w = wl[blk / L];
   PileDev& P = piles[w.pile];
-  const int grp = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
-  const int k = w.base + (blk % kLanes) * kGroups + grp;
+  const int grp = threadIdx.x / L, lane = threadIdx.x % L;
+  const int k = w.base + (blk % L) * kGroups + grp;
   if (k >= P.ns || P.status != 0) return;      // uniform over the lane group
-  search_slot(P, k, lane, write, buf_up[grp], buf_lo[grp], fill[grp]);
+  search_slot<L>(P, k, lane, write, buf_up[grp], buf_lo[grp], fill[grp]);
 }
 
 // One block per big sphere (the k-th, by id, sits at slot ns - n_big + k):
@@ -109,8 +111,16 @@ void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl,
                      wl, write);
 }
 void launch_search(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk, int write) {
-  hipLaunchKernelGGL(k_search, dim3(nblk * kLanes), dim3(kBlock), 0, st, const_cast<PileDev*>(piles),
-                     wl, write);
+  // measured on MI355X: four lanes per sphere are faster from about 32k
+  // spheres in a launch (1M-sphere lattice: find pass 0.142 vs 0.173 ms),
+  // eight below it (6,400-sphere box fill: 0.009 vs 0.012 ms)
+  PileDev* p = const_cast<PileDev*>(piles);
+  if ((int64_t)nblk * kBlock >= kSearchLargeLaunch)
+    hipLaunchKernelGGL(k_search<kLanesLarge>, dim3(nblk * kLanesLarge), dim3(kBlock), 0, st, p, wl,
+                       write);
+  else
+    hipLaunchKernelGGL(k_search<kLanesSmall>, dim3(nblk * kLanesSmall), dim3(kBlock), 0, st, p, wl,
+                       write);
 }
 
 }  // namespace dem

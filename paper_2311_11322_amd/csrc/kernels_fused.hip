@@ -25,7 +25,8 @@ namespace {
 
 constexpr int kFusedThreads = 512;
 constexpr int kFusedWaves = kFusedThreads / 64;
-constexpr int kFusedGroups = kFusedThreads / kLanes;
+constexpr int kFusedLanes = kLanesSmall;          // lanes per sphere in the search
+constexpr int kFusedGroups = kFusedThreads / kFusedLanes;
 
 // The pile's status as another thread of the workgroup may have set it.
 __device__ __forceinline__ int status_of(const PileDev& P) {
@@ -79,9 +80,9 @@ __device__ void block_scan(const uint32_t* __restrict__ in, uint32_t* __restrict
 __device__ void search_all(PileDev& P, int write, uint32_t (*buf_up)[kRunLds],
                            uint32_t (*buf_lo)[kRunLds], uint32_t (*fill)[2], uint32_t* big_up,
                            uint32_t* big_lo, uint32_t* big_fill) {
-  const int tid = threadIdx.x, grp = tid / kLanes, lane = tid % kLanes;
+  const int tid = threadIdx.x, grp = tid / kFusedLanes, lane = tid % kFusedLanes;
   for (int k = grp; k < P.ns; k += kFusedGroups)
-    search_slot(P, k, lane, write, buf_up[grp], buf_lo[grp], fill[grp]);
+    search_slot<kFusedLanes>(P, k, lane, write, buf_up[grp], buf_lo[grp], fill[grp]);
   for (int kb = 0; kb < P.n_big; ++kb) {
     stage_sync();                         // runs written; the previous sphere's LDS read
     search_big_one(P, kb, write, tid, kFusedThreads, big_up, big_lo, big_fill);

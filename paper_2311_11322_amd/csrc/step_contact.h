@@ -103,25 +103,30 @@ __device__ __forceinline__ void sort_run(uint32_t* __restrict__ a, uint32_t n) {
   }
 }
 
-// The search gives each sphere a group of kLanes lanes of one wave; the
-// lanes split the 27 neighbouring cells (and the walls) between them, so a
-// sphere's dependent cell-range and candidate loads run kLanes-wide.
-constexpr int kLanes = 8;
-constexpr int kGroups = kBlock / kLanes;   // spheres per block
+// The search gives each sphere a group of L lanes of one wave; the lanes
+// split the 27 neighbouring cells (and the walls) between them, so a
+// sphere's dependent cell-range and candidate loads run L-wide.  Eight lanes
+// keep the dependent chains short where few spheres cannot fill the chip;
+// four lanes issue fewer instructions per sphere (the per-lane work of a
+// sphere is shared by fewer lanes) where many can.
+template <int L>
+struct SearchLanes {
+  static constexpr int kGroups = kBlock / L;   // spheres per block
+  // neighbour cells per lane (d = lane, lane + L, ... < 27), and the lane
+  // whose last slot is free for the big spheres' cell
+  static constexpr int kSlots = (27 + L - 1) / L;
+  static constexpr int kBigLane = 27 - (kSlots - 1) * L;
+  static_assert(kBigLane > 0 && kBigLane < L, "one lane needs a free last slot");
+};
+constexpr int kLanesSmall = 8;            // launches of few spheres
+constexpr int kLanesLarge = 4;            // launches of many
 // Runs of up to this many contacts per sphere are gathered in LDS and
 // rank-sorted into a per-slot cache by the find pass; longer runs are found
 // again by the write pass, written in arrival order and sorted in place by
 // the group's first lane.
 constexpr int kRunLds = kRunCache;
 
-__device__ __forceinline__ uint32_t group_sum(uint32_t v) {
-  v += __shfl_xor(v, 1, kLanes);
-  v += __shfl_xor(v, 2, kLanes);
-  v += __shfl_xor(v, 4, kLanes);
-  return v;
-}
-
-// The search of the sphere at sorted slot k by its group of kLanes lanes
+// The search of the sphere at sorted slot k by its group of L lanes
 // (lane = this lane's index in the group; the group's LDS: buf_up, buf_lo of
 // kRunLds entries and fill[2]).  Every lane tests the spheres of its share
 // of the 27 neighbouring cells that belong to another aggregate, and its
@@ -133,8 +138,12 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v) {
 // scan) checks the pile's contact capacity and copies each cached run to its
 // offsets; a sphere whose runs did not fit is searched again and its runs
 // written in arrival order, then sorted in place.
+template <int Lanes>
 __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int write,
                                             uint32_t* buf_up, uint32_t* buf_lo, uint32_t* fill) {
+  constexpr int kLanes = Lanes;
+  constexpr int kSlots = SearchLanes<Lanes>::kSlots;
+  constexpr int kBigLane = SearchLanes<Lanes>::kBigLane;
   const int ns = P.ns, nxt = P.parity ^ 1;
   const SortedGeom* __restrict__ xg = P.xg;
   const SortedId* __restrict__ sid = P.sid;
@@ -186,9 +195,9 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
   // periodic axis has fewer than three (so no cell is visited twice)
   const bool all = periodic && n < 3;
   // this lane's cells: d = lane, lane + kLanes, ... (d < 27)
-  uint32_t rs[4], re[4];
+  uint32_t rs[kSlots], re[kSlots];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSlots; ++q) {
     const int d = lane + q * kLanes;
     const int ox = d % 3, oy = (d / 3) % 3, oz = d / 9;
     int cx, cy, cz;
@@ -216,10 +225,10 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
     rs[q] = ok ? cstart[key] : 0u;
     re[q] = ok ? cstart[key + 1] : 0u;
   }
-  if (lane == 3 && P.n_big > 0) {           // a free slot: the big spheres' cell
+  if (lane == kBigLane && P.n_big > 0) {    // a free slot: the big spheres' cell
     const uint32_t bk = 1u << (3 * P.bits);
-    rs[3] = cstart[bk];
-    re[3] = cstart[bk + 1];
+    rs[kSlots - 1] = cstart[bk];
+    re[kSlots - 1] = cstart[bk + 1];
   }
   // find mode keeps the first kRunLds ids of each run in LDS; write mode
   // (runs too long for the cache) writes them straight to the runs
@@ -230,7 +239,7 @@ __device__ __forceinline__ void search_slot(PileDev& P, int k, int lane, int wri
     else if (pos < (uint32_t)kRunLds) (up ? buf_up : buf_lo)[pos] = j;
   };
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSlots; ++q) {
     for (uint32_t t = rs[q]; t < re[q]; ++t) {
       const SortedId o = sid[t];
       if (o.agg == ai) continue;          // same aggregate (includes t == k)
