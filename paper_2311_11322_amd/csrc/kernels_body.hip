@@ -224,6 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
   if (P.status != 0 || P.fused) return;
   double vals[kBbox] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
                         0.0, 0.0, 0.0, 0.0, 0.0};
+  // unrolled so that several partials' loads are in flight (same order)
+#pragma unroll 4
   for (int b = threadIdx.x; b < P.n_rblk; b += kBlock) {
     const double* p = P.bpart + (size_t)b * kBbox;
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], p[k]);
