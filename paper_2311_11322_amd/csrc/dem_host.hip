@@ -268,7 +268,7 @@ struct Batch {
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   // gravity runs on a second stream beside the contact search and forces
-  // (fork after the cell sort, join before the per-sphere gather)
+  // (fork after the cell sort, join before the member reduction)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool dirty = true;

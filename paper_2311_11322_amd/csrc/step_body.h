@@ -1,8 +1,8 @@
 // step_body.h -- per-element device functions of the rigid-body part of a
 // step: the fifth-order rotation step, kick/drift/rotate of one aggregate,
 // member reconstruction, the per-pile cell grid from reduced partials, the
-// per-sphere gather, the member reduction (GetAccelAndTorque) and the
-// end-of-step bookkeeping.  Included by the staged kernels and by the fused
+// member reduction (GetAccelAndTorque, which adds each sphere's gravity force
+// to its contact force) and the end-of-step bookkeeping.  Included by the staged kernels and by the fused
 // per-pile step, so both do the same arithmetic.
 //
 // Paper references: leapfrog for centres of mass and a fifth-order
