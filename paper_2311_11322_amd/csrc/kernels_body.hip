@@ -215,18 +215,20 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const PileDev* __restric
   }
 }
 
-// One block per pile: combine the block partials into the cell grid and the
-// pile's centre of mass.  Cells are at least one largest-sphere diameter;
-// an open pile's grid spans its bounding box with (1 << bits) cells per axis.
-__global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, int mode,
-                                                 double dt) {
+// One block of kGridThreads per pile: the reconstruction's block partials
+// combined (each thread its share in block order, then across the block)
+// into the pile's bounding box and mass moments, and from them the cell grid,
+// centre of mass and bulk radius (grid_from_vals).
+constexpr int kGridThreads = 256;
+__global__ __launch_bounds__(kGridThreads) void k_grid(PileDev* __restrict__ piles, int mode,
+                                                       double dt) {
   PileDev& P = piles[blockIdx.x];
   if (P.status != 0 || P.fused) return;
   double vals[kBbox] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
                         0.0, 0.0, 0.0, 0.0, 0.0};
   // unrolled so that several partials' loads are in flight (same order)
 #pragma unroll 4
-  for (int b = threadIdx.x; b < P.n_rblk; b += kBlock) {
+  for (int b = threadIdx.x; b < P.n_rblk; b += kGridThreads) {
     const double* p = P.bpart + (size_t)b * kBbox;
     for (int k = 0; k < 3; ++k) vals[k] = fmin(vals[k], p[k]);
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], p[k]);
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
     for (int k = 3; k < 6; ++k) vals[k] = fmax(vals[k], __shfl_xor(vals[k], off));
     for (int k = 6; k < kBbox; ++k) vals[k] += __shfl_xor(vals[k], off);
   }
-  __shared__ double red[4][kBbox];
+  __shared__ double red[kGridThreads / 64][kBbox];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
     for (int k = 0; k < kBbox; ++k) red[wave][k] = vals[k];
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(PileDev* __restrict__ piles, in
   if (threadIdx.x != 0) return;
   for (int k = 0; k < kBbox; ++k) {
     double x = red[0][k];
-    for (int j = 1; j < 4; ++j) {
+    for (int j = 1; j < kGridThreads / 64; ++j) {
       const double y = red[j][k];
       x = (k < 3) ? fmin(x, y) : (k < 6 ? fmax(x, y) : x + y);
     }
@@ -379,8 +381,8 @@ void launch_reconstruct(hipStream_t st, const PileDev* piles, const WorkItem* wl
 }
 
 void launch_grid(hipStream_t st, const PileDev* piles, int n_piles, int mode, double dt) {
-  hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kBlock), 0, st, const_cast<PileDev*>(piles), mode,
-                     dt);
+  hipLaunchKernelGGL(k_grid, dim3(n_piles), dim3(kGridThreads), 0, st, const_cast<PileDev*>(piles),
+                     mode, dt);
 }
 
 void launch_reduce(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,

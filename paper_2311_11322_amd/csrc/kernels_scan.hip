@@ -104,13 +104,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const ScanSeg* __restrict_
   const ScanItem it = items[blockIdx.x];
   const ScanSeg sg = segs[it.seg];
   uint32_t* __restrict__ out = sg.parity ? sg.out_pp[*sg.parity ^ 1] : sg.out_pp[0];
+  // the chunk's elements and the earlier chunks' totals are loaded before
+  // the first barrier, so the two loads are in flight together
+  const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], r[kScanItems];
+  load_run(sg.in, base, sg.n, v);
   uint32_t part = 0;
   for (int c = threadIdx.x; c < it.chunk; c += kBlock) part += sums[sg.item0 + c];
   uint32_t offset;
   block_exclusive(part, &offset);
-  const int64_t base = (int64_t)it.chunk * kScanChunk + threadIdx.x * kScanItems;
-  uint32_t v[kScanItems], r[kScanItems];
-  load_run(sg.in, base, sg.n, v);
   uint32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) acc += v[k];
