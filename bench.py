@@ -179,6 +179,9 @@ def prepare_inputs(args, workers, sections):
             fut["ablation"] = ex.submit(W.collapse_cloud, seed=5, n_agg=4444, cmin=1, cmax=8)
         if "contact_path" in sections:
             fut["lattices"] = [ex.submit(W.dense_lattice, n_side=n) for n in args.lattice_sides]
+            if not args.no_lattice_morton:
+                fut["lattices"].append(ex.submit(W.dense_lattice, n_side=max(args.lattice_sides),
+                                                 order="morton"))
         if "walled" in sections:
             fut["fills"] = {sh: ex.submit(W.box_fill, seed=8, shape=sh)
                             for sh in ("sphere", "dumbbell", "cube", "mixed")}
@@ -231,6 +234,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--lattice-sides", type=int, nargs="+", default=[50, 100],
                     help="lattice edge lengths of the contact-path runs (n^3 spheres)")
+    ap.add_argument("--no-lattice-morton", action="store_true",
+                    help="skip the largest lattice with its aggregates in Morton order")
     ap.add_argument("--fill-steps", type=int, default=10000,
                     help="steps of the box-filling runs (the paper profiles 10^4)")
     ap.add_argument("--box-batch", type=int, default=64, help="box fills batched in one engine")
@@ -456,7 +461,9 @@ def contact_path_run(args, inp, out):
         gbs = bytes_per_sphere * wl.n_sph / (contact_ms * 1e-3) / 1e9
         res.append({
             "workload": f"periodic lattice of {wl.n_sph} unit spheres (dumbbells + lone), "
-                        f"{n_pairs} contacts (z = {zbar:.2f}), FP64, no gravity",
+                        f"{n_pairs} contacts (z = {zbar:.2f}), FP64, no gravity"
+                        + (", aggregates in Morton order of their cells"
+                           if wl.notes.endswith("morton order") else ""),
             "value": round(wl.n_sph * args.steps / wall, 1), "unit": "sphere-steps/s",
             "ms_per_step": round(1e3 * wall / args.steps, 4),
             "kernel_ms_per_step": {k: round(v, 4) for k, v in kms.items()},

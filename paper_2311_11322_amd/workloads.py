@@ -580,20 +580,36 @@ def flyby_orbit(M_pile: float, M_pert: float, periapsis: float, ecc: float = 2.0
     return pos, vel
 
 
+def _spread3(v: np.ndarray) -> np.ndarray:
+    """Bits of v (< 2^10) moved to every third position."""
+    v = v.astype(np.uint64) & np.uint64(0x3FF)
+    out = np.zeros_like(v)
+    for b in range(10):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+    return out
+
+
 def dense_lattice(seed: int = 6, n_side: int = 50, spacing: float = 1.999,
                   jitter: float = 2e-4, dt: float = 1e-4, vel_sigma: float = 0.01,
-                  n_steps: int = 100) -> Workload:
+                  n_steps: int = 100, order: str = "slices") -> Workload:
     """Contact-dense periodic workload: unit spheres on a jittered cubic
     lattice whose spacing is slightly below a diameter, so every sphere
     overlaps its six neighbours; lattice neighbours along x are bonded in
     pairs (dumbbells), the rest are lone spheres.  Used to measure the
-    contact path, where memory traffic rather than arithmetic dominates."""
+    contact path, where memory traffic rather than arithmetic dominates.
+
+    ``order`` numbers the aggregates: "slices" pairs x-slice a with a + 1
+    and goes through them slice pair by slice pair (a sphere's x-neighbours
+    are then n_side^2 ids away); "morton" lists the same aggregates in
+    Morton order of their lattice cells, as a spatially sorted input would
+    be."""
     rng = np.random.default_rng(seed)
     g = np.arange(n_side) * spacing
     p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     p = p + rng.uniform(-jitter, jitter, p.shape) + 0.5 * spacing
     ix = np.arange(n_side)
     # pair (x even, x odd) into dumbbells when n_side is even; lone otherwise
+    order_kind = order
     counts, order = [], []
     idx = np.arange(p.shape[0]).reshape(n_side, n_side, n_side)
     for a in range(0, n_side - 1, 2):
@@ -603,16 +619,28 @@ def dense_lattice(seed: int = 6, n_side: int = 50, spacing: float = 1.999,
     if n_side % 2:
         order.append(idx[n_side - 1].ravel())
         counts += [1] * (n_side * n_side)
+    counts = np.asarray(counts, dtype=np.int32)
+    if order_kind == "morton":
+        first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        flat = np.concatenate(order)
+        c = np.stack(np.unravel_index(flat[first], (n_side, n_side, n_side)), 1)
+        key = _spread3(c[:, 0]) | (_spread3(c[:, 1]) << np.uint64(1)) | (_spread3(c[:, 2]) << np.uint64(2))
+        agg_order = np.argsort(key, kind="stable")
+        order = [flat[first[a]:first[a] + counts[a]] for a in agg_order]
+        counts = counts[agg_order]
+    elif order_kind != "slices":
+        raise ValueError(f"unknown order {order_kind!r}")
     order = np.concatenate(order)
     pos = p[order]
     radius = np.ones(pos.shape[0])
     n_agg = len(counts)
     L = n_side * spacing
     params = dict(CONTACT_PARAMS, dt=dt, G=0.0, soft_frac=0.5, periodic=1, box=(L, L, L))
-    return Workload("dense_lattice", np.asarray(counts, dtype=np.int32), pos, radius,
+    return Workload("dense_lattice", counts, pos, radius,
                     sphere_mass(radius), rng.normal(0.0, vel_sigma, (n_agg, 3)),
                     np.zeros((n_agg, 3)), params, n_steps,
-                    notes=f"periodic lattice {n_side}^3 spacing {spacing}, seed {seed}")
+                    notes=f"periodic lattice {n_side}^3 spacing {spacing}, seed {seed}, "
+                          f"{order_kind} order")
 
 
 def subset(w: Workload, n_agg: int) -> Workload:
