@@ -201,7 +201,9 @@ __device__ __forceinline__ void reconstruct_one(const PileDev& P, int i, const d
 // centre of mass when that is smaller.
 __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], int mode,
                                                double dt) {
-  Grid g;
+  // written in place: a local Grid (its wall arrays indexed by a count
+  // known only at run time) would live in scratch memory
+  Grid& g = *P.grid;
   bool finite = true;
   for (int k = 0; k < kBbox; ++k) finite = finite && isfinite(vals[k]);
   if (!finite) {
@@ -252,27 +254,40 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
     // cells are currently the longest, so an elongated pile (a tall box)
     // gets more cells along its long axis
     double ext[3];
-    int b[3] = {0, 0, 0};
     for (int k = 0; k < 3; ++k) {
       g.lo[k] = lo[k];
       ext[k] = hi[k] - lo[k];
     }
+    // per-axis bit counts kept in scalars (an array indexed by the chosen
+    // axis would live in scratch memory)
+    int b0 = 0, b1 = 0, b2 = 0;
     for (int t = 0; t < 3 * P.bits; ++t) {
       if (P.tree) {                      // the tree's pyramid needs a cubic code
-        b[t % 3]++;
+        const int a = t % 3;
+        b0 += a == 0;
+        b1 += a == 1;
+        b2 += a == 2;
         continue;
       }
+      // the axis with the longest cells among those below 10 bits (the
+      // first one on a tie)
       int a = -1;
       double best = -1.0;
-      for (int k = 0; k < 3; ++k) {
-        const double len = ldexp(ext[k], -b[k]);
-        if (b[k] < 10 && len > best) {
-          best = len;
-          a = k;
-        }
+      const double l0 = ldexp(ext[0], -b0), l1 = ldexp(ext[1], -b1), l2 = ldexp(ext[2], -b2);
+      if (b0 < 10 && l0 > best) {
+        best = l0;
+        a = 0;
       }
-      ++b[a];
+      if (b1 < 10 && l1 > best) {
+        best = l1;
+        a = 1;
+      }
+      if (b2 < 10 && l2 > best) a = 2;
+      b0 += a == 0;
+      b1 += a == 1;
+      b2 += a == 2;
     }
+    const int b[3] = {b0, b1, b2};
     double fit = 0.0;
     for (int k = 0; k < 3; ++k) {
       g.nbits[k] = b[k];
@@ -313,7 +328,6 @@ __device__ __forceinline__ void grid_from_vals(PileDev& P, double vals[kBbox], i
       for (int k = 0; k < 3; ++k) g.wall_v[w][k] = rn_mul(rn_mul(A[k], P.wall_omega), cs);
     }
   }
-  *P.grid = g;
 }
 
 // Force on sphere i: its contact force plus, in a pile with gravity, its
