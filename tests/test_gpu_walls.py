@@ -269,3 +269,38 @@ def test_walled_capacity_overflow_then_reserve(D):
     assert a["n_pairs"] > 2 * w.n_sph
     for f in ("agg_pos", "agg_vel", "pair_keys", "pair_hist", "sph_force"):
         assert np.array_equal(a[f], b[f]), f
+
+
+def test_search_lane_counts_agree(D):
+    """The contact search gives each sphere eight lanes in launches of few
+    spheres and four in launches of many: a Brazil-nut set-up (big intruder
+    searched apart, shaken walls) alone, and together with eight more in one
+    engine (36k spheres), gives the same state, contacts and history bit for
+    bit (grains seeded on the floor, so contacts and wall contacts exist
+    from the start)."""
+    say("Brazil nut alone (8 lanes) vs in a 36k-sphere engine (4 lanes)")
+    w = W.brazil_nut(seed=7, floor_seeded=0.3)
+    s = D.Sim(w.params)
+    s.add_workload(w)
+    s.step(30)
+    alone = s.read_state(pairs=True)
+    s.close()
+    assert alone["pair_keys"].size > 0
+    others = [W.brazil_nut(seed=20 + k, floor_seeded=0.3) for k in range(8)]
+    assert w.n_sph + sum(o.n_sph for o in others) >= 32768
+    eng = D.Engine(1 << 34)
+    sims = []
+    for x in [w] + others:
+        t = D.Sim(x.params)
+        t.add_workload(x)
+        eng.attach(t)
+        sims.append(t)
+    assert eng.step(30) == D.DEM_OK
+    for t in list(eng.sims):
+        eng.detach(t)
+    got = sims[0].read_state(pairs=True)
+    for t in sims:
+        t.close()
+    for f in ("agg_pos", "agg_vel", "agg_quat", "agg_spin_body", "pair_keys", "pair_hist",
+              "sph_force", "sph_torque"):
+        assert np.array_equal(got[f], alone[f]), f
