@@ -336,6 +336,13 @@ typedef struct {
                                   (one launch per stage).  Never with tree gravity.  The same
                                   arithmetic per element; the centre of mass and bulk radius
                                   are summed in another order (spin-up, stop rule). */
+    int32_t gravity_form;      /* form of the exact softened sum (Eq. 4): 0 automatic --
+                                  tile pairs unless their partial sums would exceed 64 GiB;
+                                  1 tile pairs: each unordered pair once, one partial sum per
+                                  sphere and tile (memory N^2 / gravity_tile); 2 per target:
+                                  each ordered pair from its target's side, one partial per
+                                  sphere and source split (16 splits; memory O(N)), about
+                                  1.4x the work.  Same sum in another order (rounding). */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them

@@ -56,7 +56,8 @@ int ceil_log2(uint64_t v) {
 
 // Device footprint of one system, byte for byte what alloc_pile allocates.
 struct Sizes {
-  int64_t na, ns, cap, cells, g_tile, g_nt, n_rblk;
+  int64_t na, ns, cap, cells, g_tile, g_nt, g_np, n_rblk;
+  int g_form;                // 1 tile pairs, 2 per-target
   bool grav;
   bool tree;
   int64_t tree_nodes;        // all levels of the pyramid
@@ -117,7 +118,8 @@ bool tile_supported(int precision, int tile) {
   return false;
 }
 
-Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int tile) {
+Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int tile,
+                 int form = 0) {
   Sizes z;
   z.na = na;
   z.ns = ns;
@@ -129,6 +131,16 @@ Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int til
   z.precision = p.precision;
   z.g_tile = tile > 0 ? tile : default_tile(p.precision);
   z.g_nt = (ns + z.g_tile - 1) / z.g_tile;
+  // the exact sum's form: tile pairs (partials per tile) unless asked
+  // otherwise or their partials would exceed kSymPartialMax bytes
+  const int64_t part_bytes = z.g_nt * 3 * ns * (p.precision == 1 ? 4 : 8);
+  z.g_form = form != 0 ? form : (part_bytes > kSymPartialMax ? 2 : 1);
+  if (z.g_form == 2) {
+    const int64_t span = (z.g_nt + kGravSplits - 1) / kGravSplits;
+    z.g_np = (z.g_nt + span - 1) / span;
+  } else {
+    z.g_np = z.g_nt;
+  }
   z.n_rblk = (ns + kBlock - 1) / kBlock;
   return z;
 }
@@ -186,8 +198,8 @@ void plan_pile(PileDev& h, const Sizes& z, BufList& L) {
       L.add(&h.tpart, 64 * 3 * ns);
       L.add(&h.tbox, 6 * ((ns + 63) / 64));
     } else {
-      // per-tile partials: g_nt x 3 x ns values (FP64, or FP32 in the FP32-force form)
-      const int64_t part_vals = z.g_nt * 3 * ns;
+      // partials: g_np x 3 x ns values (FP64, or FP32 in the FP32-force form)
+      const int64_t part_vals = z.g_np * 3 * ns;
       L.add(&h.ganchor, 4 * z.g_nt);
       L.add(reinterpret_cast<double**>(&h.gpart), z.precision == 1 ? (part_vals + 1) / 2 : part_vals);
     }
@@ -240,6 +252,9 @@ struct Batch {
   // gravity tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
   int n_grav[3] = {0, 0, 0};
+  // per-target form: (target tile, source split) items, same grouping
+  GravItem* gs[3] = {nullptr, nullptr, nullptr};
+  int n_gsplit[3] = {0, 0, 0};
   int grav_tile[3] = {0, 0, 0};
   int n_grav_groups = 0;
   bool any_grav = false;
@@ -371,7 +386,7 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
   std::vector<WorkItem> wa, wsph, wbig, wtree[11], wgrav, wall;
   std::vector<int32_t> pfg, pfng;
-  std::vector<GravItem> glg[3];
+  std::vector<GravItem> glg[3], gsg[3];
   int tiles[3] = {0, 0, 0};
   int n_groups = 0;
   std::vector<ScanSeg> sc, sp;
@@ -417,8 +432,13 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       int g = 0;
       while (g < n_groups && tiles[g] != h.g_tile) ++g;
       if (g == n_groups) tiles[n_groups++] = h.g_tile;
-      for (int ti = 0; ti < h.g_nt; ++ti)
-        for (int tj = ti; tj < h.g_nt; ++tj) glg[g].push_back({p, ti, tj, 0});
+      if (h.g_form == 2) {
+        for (int ti = 0; ti < h.g_nt; ++ti)
+          for (int sp = 0; sp < h.g_np; ++sp) gsg[g].push_back({p, ti, sp, 0});
+      } else {
+        for (int ti = 0; ti < h.g_nt; ++ti)
+          for (int tj = ti; tj < h.g_nt; ++tj) glg[g].push_back({p, ti, tj, 0});
+      }
     }
     // cell-count scan of this pile
     auto add_seg = [](std::vector<ScanSeg>& segs, std::vector<ScanItem>& items, const uint32_t* in,
@@ -460,6 +480,8 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   for (int g = 0; g < 3; ++g) {
     HIPCHK(errsim, upload(b, &b.gl[g], glg[g], st));
     b.n_grav[g] = (int)glg[g].size();
+    HIPCHK(errsim, upload(b, &b.gs[g], gsg[g], st));
+    b.n_gsplit[g] = (int)gsg[g].size();
     b.grav_tile[g] = tiles[g];
   }
   b.n_grav_groups = n_groups;
@@ -553,9 +575,12 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark, bool ove
   const bool fork = overlap && b.any_grav && b.side && staged;
   auto gravity = [&](hipStream_t s) {
     launch_gravity_records(s, b.d_table, b.wl_grav, b.n_grav_blk, b.precision);
-    for (int g = 0; g < b.n_grav_groups; ++g)
+    for (int g = 0; g < b.n_grav_groups; ++g) {
       launch_gravity_tiles(s, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
+      launch_gravity_split(s, b.d_table, b.gs[g], b.n_gsplit[g], b.precision, b.all_soft,
+                           b.grav_tile[g]);
+    }
     if (b.any_direct) launch_gravity_combine(s, b.d_table, b.wl_grav, b.n_grav_blk, b.precision);
     if (b.any_tree) launch_tree(s, b.d_table, b.wl_tree, b.n_tree, b.tree_leaf_levels, b.wl_sph,
                                b.n_sph_blk, b.tree_order);
@@ -722,7 +747,7 @@ void release_pile(dem_sim* s) {
 
 dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   PileDev h{};
-  s->sz = pile_sizes(s->prm, na, ns, s->c_max, s->tune.gravity_tile);
+  s->sz = pile_sizes(s->prm, na, ns, s->c_max, s->tune.gravity_tile, s->tune.gravity_form);
   BufList L;
   plan_pile(h, s->sz, L);
   for (auto& r : L.req) {
@@ -744,6 +769,8 @@ dem_status alloc_pile(dem_sim* s, int64_t na, int64_t ns) {
   h.member_read = s->tune.member_read;
   h.g_tile = (int32_t)s->sz.g_tile;
   h.g_nt = (int32_t)s->sz.g_nt;
+  h.g_form = s->sz.g_form;
+  h.g_np = (int32_t)s->sz.g_np;
   h.n_rblk = (int32_t)s->sz.n_rblk;
   h.box = s->prm.box[0];
   h.G = s->prm.G;
@@ -1525,6 +1552,8 @@ dem_status dem_set_tuning(dem_sim* s, const dem_tuning* t) {
   if (t->member_read < 0 || t->member_read > 2)
     return fail(s, DEM_ERR_INVALID_ARG, "member_read must be 0, 1 or 2");
   if (t->fused < 0 || t->fused > 2) return fail(s, DEM_ERR_INVALID_ARG, "fused must be 0, 1 or 2");
+  if (t->gravity_form < 0 || t->gravity_form > 2)
+    return fail(s, DEM_ERR_INVALID_ARG, "gravity_form must be 0, 1 or 2");
   s->tune = *t;
   return DEM_OK;
 }

@@ -80,6 +80,8 @@ struct PileDev {
   int32_t periodic;
   int32_t g_tile;            // gravity tile (slots per tile)
   int32_t g_nt;              // gravity tiles
+  int32_t g_form;            // 1: symmetric tile pairs; 2: per-target (O(N) partial sums)
+  int32_t g_np;              // partial-sum rows per sphere: g_nt, or the source splits
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
   int32_t n_periodic;        // cells per axis of a periodic pile
   int32_t member_scan;       // 1: reduction finds members by scanning all spheres
@@ -167,7 +169,7 @@ struct PileDev {
   SortedId* sid;             // [ns] sorted aggregate id and sphere id
   void* jrec;                // gravity records in sorted order (64 B FP64 / 32 B FP32)
   double* ganchor;           // [g_nt][4] FP64 anchor of each tile (relative coordinates)
-  void* gpart;               // [g_nt][3][ns] per-tile partial sums (sorted slots)
+  void* gpart;               // [g_np][3][ns] partial sums (sorted slots)
   double* gacc;              // [3][ns] gravity force G m_i sum_j (by sphere id)
   double* bpart;             // [n_rblk][kBbox] bbox min/max + mass moments
   Grid* grid;
@@ -189,7 +191,8 @@ struct WorkItem {
   int32_t base;
 };
 
-// One block of the gravity kernel: the tile pair (ti, tj), ti <= tj, of a pile.
+// One block of the gravity kernel: the tile pair (ti, tj), ti <= tj, of a
+// pile; in the per-target form, target tile ti and source split tj.
 struct GravItem {
   int32_t pile;
   int32_t ti, tj;
@@ -237,6 +240,8 @@ void launch_gravity_records(hipStream_t st, const PileDev* piles, const WorkItem
                             int precision);
 void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
                           int precision, bool softened, int tile);
+void launch_gravity_split(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
+                          int precision, bool softened, int tile);
 void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                             int precision);
 // Supported tile sizes for a precision (default first); returns the count.
@@ -245,6 +250,10 @@ int gravity_tiles(int precision, int* tiles);
 // members through LDS (below it, direct member reads are faster: few waves,
 // and the members stay in L2 between a wave's member iterations).
 constexpr int64_t kReduceStageMin = 131072;
+// Source splits of the per-target gravity form, and the size of the tile
+// pairs' partial sums above which a system takes that form by default.
+constexpr int kGravSplits = 16;
+constexpr int64_t kSymPartialMax = int64_t(64) << 30;
 // Spheres in one search launch from which each sphere gets four lanes
 // instead of eight.
 constexpr int64_t kSearchLargeLaunch = 32768;

@@ -214,8 +214,113 @@ __global__ __launch_bounds__(64) void k_grav_tiles(const PileDev* __restrict__ p
   }
 }
 
-// One thread per sorted slot: add the per-tile partials in tile order (FP64)
-// and store the gravity force G m_i sum under the sphere's id.  With a
+// The per-target form (O(N) partial sums): one wave per (target tile I,
+// source split s).  Split s covers a run of consecutive source tiles; the
+// wave's lanes hold the targets of tile I and walk every source of the run
+// by a uniform index (scalar loads), evaluating each ordered pair once from
+// the target's side, so no reaction is carried and each sphere receives one
+// partial per split.  About 1.4 times the work of the tile pairs per
+// unordered pair, for partial sums that grow as N instead of N^2 / B.
+template <typename T, int IPT, bool SOFT>
+__global__ __launch_bounds__(64) void k_grav_split(const PileDev* __restrict__ piles,
+                                                   const GravItem* __restrict__ gl) {
+  constexpr int B = 64 * IPT;
+  constexpr bool F32 = sizeof(T) == 4;
+  const GravItem it = gl[blockIdx.x];
+  const PileDev& P = piles[it.pile];
+  if (P.status != 0) return;
+  const int ns = P.ns, nt = P.g_nt, lane = threadIdx.x;
+  const int span = (nt + kGravSplits - 1) / kGravSplits;  // source tiles per split
+  const int t0 = it.tj * span, t1 = min(t0 + span, nt);
+  const int i0 = it.ti * B;
+  double c15, c1875;
+  series_coeffs(c15, c1875);
+
+  T xi[IPT], yi[IPT], zi[IPT], ei[IPT], ax[IPT], ay[IPT], az[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int k = i0 + u * 64 + lane;
+    const int kk = k < ns ? k : ns - 1;
+    if (F32) {
+      const Rec32 r = ((const Rec32*)P.jrec)[kk];
+      xi[u] = (T)r.x;
+      yi[u] = (T)r.y;
+      zi[u] = (T)r.z;
+      ei[u] = (T)r.e;
+    } else {
+      const Rec64 r = ((const Rec64*)P.jrec)[kk];
+      xi[u] = (T)r.x;
+      yi[u] = (T)r.y;
+      zi[u] = (T)r.z;
+      ei[u] = (T)r.e;
+    }
+    ax[u] = ay[u] = az[u] = (T)0;
+  }
+  for (int tj = t0; tj < t1; ++tj) {
+    // FP32 form: targets relative to source tile J's anchor,
+    // (x_i - A_I) - (A_J - A_I), the offset formed in FP64
+    T xs[IPT], ys[IPT], zs[IPT];
+    T sx = 0, sy = 0, sz = 0;
+    if (F32) {
+      const double* aI = P.ganchor + (size_t)it.ti * 4;
+      const double* aJ = P.ganchor + (size_t)tj * 4;
+      sx = (T)(aJ[0] - aI[0]);
+      sy = (T)(aJ[1] - aI[1]);
+      sz = (T)(aJ[2] - aI[2]);
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      xs[u] = xi[u] - sx;
+      ys[u] = yi[u] - sy;
+      zs[u] = zi[u] - sz;
+    }
+    const int j0 = tj * B, j1 = min(j0 + B, ns);
+    for (int j = j0; j < j1; ++j) {
+      T xj, yj, zj, mj, ej;
+      if (F32) {
+        const ConstRec32 cr = (ConstRec32)P.jrec;
+        xj = cr[j].x;
+        yj = cr[j].y;
+        zj = cr[j].z;
+        mj = cr[j].m;
+        ej = cr[j].e;
+      } else {
+        const ConstRec64 cr = (ConstRec64)P.jrec;
+        xj = (T)cr[j].x;
+        yj = (T)cr[j].y;
+        zj = (T)cr[j].z;
+        mj = (T)cr[j].m;
+        ej = (T)cr[j].e;
+      }
+      // the sphere itself contributes nothing: d = 0 (and r^-3 = 0 when
+      // unsoftened)
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const T dx = xj - xs[u], dy = yj - ys[u], dz = zj - zs[u];
+        const T t = ei[u] + ej;
+        const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
+        const T w = mj * inv_cube<SOFT>(r2, c15, c1875);
+        ax[u] = fma(w, dx, ax[u]);
+        ay[u] = fma(w, dy, ay[u]);
+        az[u] = fma(w, dz, az[u]);
+      }
+    }
+  }
+  T* __restrict__ part = (T*)P.gpart;
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int k = i0 + u * 64 + lane;
+    if (k < ns) {
+      part[((size_t)it.tj * 3 + 0) * ns + k] = ax[u];
+      part[((size_t)it.tj * 3 + 1) * ns + k] = ay[u];
+      part[((size_t)it.tj * 3 + 2) * ns + k] = az[u];
+    }
+  }
+}
+
+// One thread per sorted slot: add the partials in order -- per tile (tile
+// pairs) or per source split (per-target form) -- in FP64, and store the
+// gravity force G m_i sum under the sphere's id.  With a
 // perturber, its unsoftened pull G m_i M d/|d|^3 is added (FP64) and each
 // block stores the sum of its spheres' pulls (the reaction, reduced in block
 // order at the end of the step).
@@ -226,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_grav_combine(const PileDev* __restri
   const PileDev& P = piles[w.pile];
   if (P.status != 0 || P.G == 0.0 || P.tree) return;
   const int k = w.base + threadIdx.x;
-  const int ns = P.ns, nt = P.g_nt;
+  const int ns = P.ns, nt = P.g_np;
   double pull[3] = {0.0, 0.0, 0.0};
   if (k < ns) {
     const T* __restrict__ part = (const T*)P.gpart;
@@ -305,6 +410,29 @@ void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* 
     if (ipt == 2) tiles_launch<double, 2>(st, piles, gl, nitems, softened);
     else if (ipt == 8) tiles_launch<double, 8>(st, piles, gl, nitems, softened);
     else tiles_launch<double, 4>(st, piles, gl, nitems, softened);
+  }
+}
+
+template <typename T, int IPT>
+static void split_launch(hipStream_t st, const PileDev* piles, const GravItem* gl, int n, bool soft) {
+  if (soft)
+    hipLaunchKernelGGL((k_grav_split<T, IPT, true>), dim3(n), dim3(64), 0, st, piles, gl);
+  else
+    hipLaunchKernelGGL((k_grav_split<T, IPT, false>), dim3(n), dim3(64), 0, st, piles, gl);
+}
+
+void launch_gravity_split(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
+                          int precision, bool softened, int tile) {
+  if (nitems <= 0) return;
+  const int ipt = tile / 64;
+  if (precision == 1) {
+    if (ipt == 4) split_launch<float, 4>(st, piles, gl, nitems, softened);
+    else if (ipt == 16) split_launch<float, 16>(st, piles, gl, nitems, softened);
+    else split_launch<float, 8>(st, piles, gl, nitems, softened);
+  } else {
+    if (ipt == 2) split_launch<double, 2>(st, piles, gl, nitems, softened);
+    else if (ipt == 8) split_launch<double, 8>(st, piles, gl, nitems, softened);
+    else split_launch<double, 4>(st, piles, gl, nitems, softened);
   }
 }
 

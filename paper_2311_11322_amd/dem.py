@@ -69,7 +69,8 @@ class dem_allocator(C.Structure):
 
 class dem_tuning(C.Structure):
     _fields_ = [("gravity_tile", C.c_int32), ("cell_scale", C.c_double),
-                ("member_scan", C.c_int32), ("member_read", C.c_int32), ("fused", C.c_int32)]
+                ("member_scan", C.c_int32), ("member_read", C.c_int32), ("fused", C.c_int32),
+                ("gravity_form", C.c_int32)]
 
 
 class dem_forcing(C.Structure):
@@ -359,9 +360,9 @@ class Sim:
         return int(lib().dem_sim_status(self.h))
 
     def set_tuning(self, gravity_tile: int = 0, cell_scale: float = 1.0, member_scan: int = 0,
-                   member_read: int = 0, fused: int = 0):
+                   member_read: int = 0, fused: int = 0, gravity_form: int = 0):
         t = dem_tuning(int(gravity_tile), float(cell_scale), int(member_scan), int(member_read),
-                       int(fused))
+                       int(fused), int(gravity_form))
         _check(lib().dem_set_tuning(self.h, C.byref(t)), self.h)
 
     def set_profiling(self, on: bool):
