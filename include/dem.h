@@ -337,12 +337,13 @@ typedef struct {
                                   arithmetic per element; the centre of mass and bulk radius
                                   are summed in another order (spin-up, stop rule). */
     int32_t gravity_form;      /* form of the exact softened sum (Eq. 4): 0 automatic --
-                                  tile pairs unless their partial sums would exceed 64 GiB;
-                                  1 tile pairs: each unordered pair once, one partial sum per
-                                  sphere and tile (memory N^2 / gravity_tile); 2 per target:
-                                  each ordered pair from its target's side, one partial per
-                                  sphere and source split (16 splits; memory O(N)), about
-                                  1.4x the work.  Same sum in another order (rounding). */
+                                  pairs unless their partial sums would exceed 64 GiB;
+                                  1 pairs: each unordered pair once, on super-tiles of
+                                  ceil(tiles / 256) tiles, one partial sum per sphere and
+                                  super-tile (at most 256 x 3 values per sphere); 2 per
+                                  target: each ordered pair from its target's side, one
+                                  partial per sphere and source split (16 splits), about
+                                  1.8x the time.  Same sum in another order (rounding). */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them

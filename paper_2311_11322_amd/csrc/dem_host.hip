@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "dem.h"
@@ -57,7 +58,7 @@ int ceil_log2(uint64_t v) {
 // Device footprint of one system, byte for byte what alloc_pile allocates.
 struct Sizes {
   int64_t na, ns, cap, cells, g_tile, g_nt, g_np, n_rblk;
-  int g_form;                // 1 tile pairs, 2 per-target
+  int g_form;                // 1 super-tile pairs, 2 per-target
   bool grav;
   bool tree;
   int64_t tree_nodes;        // all levels of the pyramid
@@ -131,15 +132,17 @@ Sizes pile_sizes(const dem_params& p, int64_t na, int64_t ns, int c_max, int til
   z.precision = p.precision;
   z.g_tile = tile > 0 ? tile : default_tile(p.precision);
   z.g_nt = (ns + z.g_tile - 1) / z.g_tile;
-  // the exact sum's form: tile pairs (partials per tile) unless asked
-  // otherwise or their partials would exceed kSymPartialMax bytes
-  const int64_t part_bytes = z.g_nt * 3 * ns * (p.precision == 1 ? 4 : 8);
+  // the exact sum's form: super-tile pairs (one partial per super-tile)
+  // unless asked otherwise or their partials would exceed kSymPartialMax
+  const int64_t pair_span = (z.g_nt + kGravSlots - 1) / kGravSlots;
+  const int64_t pair_np = (z.g_nt + pair_span - 1) / pair_span;
+  const int64_t part_bytes = pair_np * 3 * ns * (p.precision == 1 ? 4 : 8);
   z.g_form = form != 0 ? form : (part_bytes > kSymPartialMax ? 2 : 1);
   if (z.g_form == 2) {
     const int64_t span = (z.g_nt + kGravSplits - 1) / kGravSplits;
     z.g_np = (z.g_nt + span - 1) / span;
   } else {
-    z.g_np = z.g_nt;
+    z.g_np = pair_np;
   }
   z.n_rblk = (ns + kBlock - 1) / kBlock;
   return z;
@@ -249,9 +252,12 @@ struct Batch {
   bool tree_order[2] = {false, false};       // some tree pile of order 2, 4
   unsigned tree_leaf_levels = 0;             // bit l: level l is some tree pile's finest
   int n_sph_blk = 0;
-  // gravity tile pairs, grouped by tile size (one launch per group)
+  // gravity super-tile pairs, grouped by tile size (one launch per group)
   GravItem* gl[3] = {nullptr, nullptr, nullptr};
   int n_grav[3] = {0, 0, 0};
+  // super-tile pairs of piles with more than kGravSlots tiles, same grouping
+  GravItem* gm[3] = {nullptr, nullptr, nullptr};
+  int n_gmulti[3] = {0, 0, 0};
   // per-target form: (target tile, source split) items, same grouping
   GravItem* gs[3] = {nullptr, nullptr, nullptr};
   int n_gsplit[3] = {0, 0, 0};
@@ -386,7 +392,8 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   free_meta(b);
   std::vector<WorkItem> wa, wsph, wbig, wtree[11], wgrav, wall;
   std::vector<int32_t> pfg, pfng;
-  std::vector<GravItem> glg[3], gsg[3];
+  std::vector<GravItem> glg[3], gmg[3], gsg[3];
+  std::vector<std::pair<int64_t, GravItem>> gmw[3];
   int tiles[3] = {0, 0, 0};
   int n_groups = 0;
   std::vector<ScanSeg> sc, sp;
@@ -428,7 +435,8 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       b.any_grav = true;
       b.any_direct = true;
       if (!(h.soft_frac > 0.0)) b.all_soft = false;
-      // every tile pair (ti <= tj) of the pile: each unordered pair once
+      // every super-tile pair (si <= sj) of the pile: each unordered pair
+      // once; or every (target tile, source split) of the per-target form
       int g = 0;
       while (g < n_groups && tiles[g] != h.g_tile) ++g;
       if (g == n_groups) tiles[n_groups++] = h.g_tile;
@@ -436,8 +444,18 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
         for (int ti = 0; ti < h.g_nt; ++ti)
           for (int sp = 0; sp < h.g_np; ++sp) gsg[g].push_back({p, ti, sp, 0});
       } else {
-        for (int ti = 0; ti < h.g_nt; ++ti)
-          for (int tj = ti; tj < h.g_nt; ++tj) glg[g].push_back({p, ti, tj, 0});
+        if (h.g_np == h.g_nt) {
+          for (int si = 0; si < h.g_np; ++si)
+            for (int sj = si; sj < h.g_np; ++sj) glg[g].push_back({p, si, sj, 0});
+        } else {
+          // super-tiles of several tiles: items weighted by their tile pairs
+          const int span = (h.g_nt + kGravSlots - 1) / kGravSlots;
+          auto tiles = [&](int sp) { return (int64_t)std::min(span, h.g_nt - sp * span); };
+          for (int si = 0; si < h.g_np; ++si)
+            for (int sj = si; sj < h.g_np; ++sj)
+              gmw[g].push_back({si == sj ? tiles(si) * (tiles(si) + 1) / 2 : tiles(si) * tiles(sj),
+                                GravItem{p, si, sj, 0}});
+        }
       }
     }
     // cell-count scan of this pile
@@ -480,6 +498,13 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
   for (int g = 0; g < 3; ++g) {
     HIPCHK(errsim, upload(b, &b.gl[g], glg[g], st));
     b.n_grav[g] = (int)glg[g].size();
+    // largest items first: the blocks are handed out in launch order, so
+    // the launch ends on the smallest ones
+    std::stable_sort(gmw[g].begin(), gmw[g].end(),
+                     [](const auto& a, const auto& c) { return a.first > c.first; });
+    for (const auto& e : gmw[g]) gmg[g].push_back(e.second);
+    HIPCHK(errsim, upload(b, &b.gm[g], gmg[g], st));
+    b.n_gmulti[g] = (int)gmg[g].size();
     HIPCHK(errsim, upload(b, &b.gs[g], gsg[g], st));
     b.n_gsplit[g] = (int)gsg[g].size();
     b.grav_tile[g] = tiles[g];
@@ -577,7 +602,9 @@ void enqueue_pass_marked(Batch& b, hipStream_t st, int mode, Mark mark, bool ove
     launch_gravity_records(s, b.d_table, b.wl_grav, b.n_grav_blk, b.precision);
     for (int g = 0; g < b.n_grav_groups; ++g) {
       launch_gravity_tiles(s, b.d_table, b.gl[g], b.n_grav[g], b.precision, b.all_soft,
-                           b.grav_tile[g]);
+                           b.grav_tile[g], false);
+      launch_gravity_tiles(s, b.d_table, b.gm[g], b.n_gmulti[g], b.precision, b.all_soft,
+                           b.grav_tile[g], true);
       launch_gravity_split(s, b.d_table, b.gs[g], b.n_gsplit[g], b.precision, b.all_soft,
                            b.grav_tile[g]);
     }

@@ -80,8 +80,8 @@ struct PileDev {
   int32_t periodic;
   int32_t g_tile;            // gravity tile (slots per tile)
   int32_t g_nt;              // gravity tiles
-  int32_t g_form;            // 1: symmetric tile pairs; 2: per-target (O(N) partial sums)
-  int32_t g_np;              // partial-sum rows per sphere: g_nt, or the source splits
+  int32_t g_form;            // 1: symmetric super-tile pairs; 2: per-target
+  int32_t g_np;              // partial-sum rows per sphere: super-tiles, or source splits
   int32_t n_rblk;            // reconstruct blocks (bbox partials)
   int32_t n_periodic;        // cells per axis of a periodic pile
   int32_t member_scan;       // 1: reduction finds members by scanning all spheres
@@ -191,8 +191,8 @@ struct WorkItem {
   int32_t base;
 };
 
-// One block of the gravity kernel: the tile pair (ti, tj), ti <= tj, of a
-// pile; in the per-target form, target tile ti and source split tj.
+// One block of the gravity kernel: the super-tile pair (ti, tj), ti <= tj,
+// of a pile; in the per-target form, target tile ti and source split tj.
 struct GravItem {
   int32_t pile;
   int32_t ti, tj;
@@ -234,12 +234,14 @@ void launch_search_big(hipStream_t st, const PileDev* piles, const WorkItem* wl,
                        int write);
 void launch_forces(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                    ContactParams cp, int precision);
-// Gravity: records and the per-slot combine cover every pile; the tile-pair
-// kernel runs once per tile size present in the batch.
+// Gravity: records and the per-slot combine cover every pile; the pair and
+// per-target kernels run once per tile size present in the batch.
 void launch_gravity_records(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                             int precision);
+// multi: the items' piles have more tiles than kGravSlots (super-tiles of
+// several tiles); otherwise every item is one tile pair.
 void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
-                          int precision, bool softened, int tile);
+                          int precision, bool softened, int tile, bool multi);
 void launch_gravity_split(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
                           int precision, bool softened, int tile);
 void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
@@ -250,8 +252,11 @@ int gravity_tiles(int precision, int* tiles);
 // members through LDS (below it, direct member reads are faster: few waves,
 // and the members stay in L2 between a wave's member iterations).
 constexpr int64_t kReduceStageMin = 131072;
-// Source splits of the per-target gravity form, and the size of the tile
-// pairs' partial sums above which a system takes that form by default.
+// Super-tiles of the pair form of the exact gravity sum (at most this many
+// partial sums per sphere: a super-tile is ceil(tiles / kGravSlots) tiles),
+// source splits of the per-target form, and the size of the pair form's
+// partial sums above which a system takes the per-target form by default.
+constexpr int kGravSlots = 256;
 constexpr int kGravSplits = 16;
 constexpr int64_t kSymPartialMax = int64_t(64) << 30;
 // Spheres in one search launch from which each sphere gets four lanes

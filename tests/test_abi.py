@@ -66,6 +66,13 @@ def test_parameter_validation_on_host():
     f2 = dem.footprint_bytes(good, 2000, 9000)
     assert 0 < f1 < f2
     assert f1 > 4500 * 500
+    # with gravity the exact sum's partials are at most 256 x 3 per sphere
+    # beyond 256 tiles: the footprint grows linearly in the sphere count
+    grav = dict(good, G=1.0)
+    f3 = dem.footprint_bytes(grav, 200000, 1000000)
+    f4 = dem.footprint_bytes(grav, 400000, 2000000)
+    assert 1.9 < f4 / f3 < 2.1
+    assert f4 < 2000000 * (256 * 3 * 8 + 4000)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB) or os.path.exists("/dev/kfd"),

@@ -1,12 +1,13 @@
 """The two forms of the exact softened gravity sum (Eq. 4) against the
 oracle and against each other (needs an MI355X).
 
-Tile pairs evaluate each unordered pair once and keep one partial sum per
-sphere and tile (memory N^2 / tile); the per-target form evaluates each
-ordered pair from its target's side and keeps one partial per sphere and
-source split (memory O(N)).  Both are the same sum in another order, so
-each is compared with the oracle at the FP64 parity bar, and a pile's result
-must not depend on the form of the other piles in its engine.
+The pair form evaluates each unordered pair once, a wave per pair of
+super-tiles (runs of ceil(tiles / 256) tiles), and keeps one partial sum per
+sphere and super-tile; the per-target form evaluates each ordered pair from
+its target's side and keeps one partial per sphere and source split (16).
+Both are the same sum in another order, so each is compared with the oracle
+at the FP64 parity bar, and a pile's result must not depend on the form of
+the other piles in its engine.
 """
 import sys
 
@@ -115,3 +116,25 @@ def test_forms_agree_and_mix_in_an_engine(D):
         s.close()
         for f in ("agg_pos", "agg_vel", "agg_quat", "pair_keys", "sph_force"):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
+
+
+@pytest.mark.parametrize("n_agg,tile,prec", [(7000, 128, 0), (14000, 128, 0), (14000, 256, 1)])
+def test_super_tiles_sampled(D, n_agg, tile, prec):
+    """More tiles than super-tiles (35k and 70k spheres in tiles of 128: two
+    and three tiles per super-tile, the last one short): sampled spheres
+    against the oracle's exact sum, both forms."""
+    w = W.collapse_cloud(50 + n_agg // 7000, n_agg=n_agg)
+    idx = np.sort(np.random.default_rng(5).choice(w.n_sph, 160, replace=False))
+    o = O.Oracle(w.params).add_workload(w, evaluate=False)
+    F, _ = o.eval_subset(idx)
+    nt = -(-w.n_sph // tile)
+    span = -(-nt // 256)
+    assert span >= 2
+    for form in (1, 2):
+        say("super-tiles", w.n_sph, "spheres, tile", tile, "span", span, "form", form, "prec", prec)
+        sim = D.Sim(w.params, precision=prec)
+        sim.set_tuning(gravity_tile=tile, gravity_form=form)
+        sim.add_workload(w)
+        g = sim.read_state(["sph_force"])["sph_force"]
+        sim.close()
+        assert rel_err(g[idx], F) <= (1e-12 if prec == 0 else 1e-5), form

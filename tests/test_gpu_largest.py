@@ -1,7 +1,8 @@
 """The largest workloads the benchmark times.
 
 * The collapse of 100,000 aggregates of 2-8 spheres (499,762 spheres),
-  seed 2, in the plain FP64 form, the FP32-force form and with tree gravity.
+  seed 2, in the plain FP64 form (pair and per-target forms of the exact
+  sum), the FP32-force form and with tree gravity.
   At this size the oracle evaluates sampled spheres one at a time
   (brute-force contacts and the exact direct sum over all sources).
 * The 256 spin-up piles (1.31M spheres) in one engine, FP32-force, with the
@@ -68,6 +69,19 @@ def test_largest_collapse_fp64_sampled(D, collapse500k, sampled):
     g, t = _forces(D, w, w.params, D.PREC_FP64)
     assert rel_err(g[idx], F) <= 1e-12
     assert np.abs(t[idx] - T).max() <= 1e-12 * max(np.abs(F).max(), 1.0)
+
+
+def test_largest_collapse_per_target_sampled(D, collapse500k, sampled):
+    """The per-target form of the exact sum (16 source splits) at full size."""
+    w = collapse500k
+    say("largest collapse, per-target gravity form", w.n_sph)
+    idx, F, _ = sampled
+    sim = D.Sim(w.params, precision=D.PREC_FP64)
+    sim.set_tuning(gravity_form=2)
+    sim.add_workload(w)
+    g = sim.read_state(["sph_force"])["sph_force"]
+    sim.close()
+    assert rel_err(g[idx], F) <= 1e-12
 
 
 def test_largest_collapse_fp32_force_sampled(D, collapse500k, sampled):
