@@ -22,12 +22,12 @@
 // partial sums take at most kGravSlots x 3 values per sphere.  With no more
 // tiles than kGravSlots a super-tile is one tile.
 //
-// FP64 form: rsqrt from the hardware estimate y0 and one third-order
-// correction folded into the cube: r^-3 = y0^3 (1 + 3e/2 + 15e^2/8),
-// e = 1 - r^2 y0^2.  FP32-force form: coordinates relative to an FP64 anchor
-// per tile (the first sphere of the tile); the anchor offset of a tile pair,
-// formed in FP64, moves one tile into the other's frame; FP32 partial sums
-// per super-tile, FP64 across them.
+// FP64 form: rsqrt from the hardware estimate y0 and one first-order
+// correction folded into the cube: r^-3 = y0^3 (1 + 3e/2), e = 1 - r^2 y0^2.
+// FP32-force form: coordinates relative to an FP64 anchor per tile (the
+// first sphere of the tile); the anchor offset of a tile pair, formed in
+// FP64, moves one tile into the other's frame; FP32 partial sums per
+// super-tile, FP64 across them.
 #include "gravity_common.h"
 
 namespace dem {
@@ -97,8 +97,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
   const int I0 = si * span, I1 = MULTI ? min(I0 + span, nt) : I0 + 1;
   const int J0 = sj * span, J1 = MULTI ? min(J0 + span, nt) : J0 + 1;
   const bool diag_item = si == sj;
-  double c15, c1875;
-  series_coeffs(c15, c1875);
+  double c15;
+  series_coeffs(c15);
   T* __restrict__ part = (T*)P.gpart;
 
   for (int I = I0; I < I1; ++I) {
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
             const T dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
             const T t = ei[u] + ej;
             const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
-            const T w = mj * inv_cube<SOFT>(r2, c15, c1875);
+            const T w = mj * inv_cube<SOFT>(r2, c15);
             ax[u] = fma(w, dx, ax[u]);
             ay[u] = fma(w, dy, ay[u]);
             az[u] = fma(w, dz, az[u]);
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
             const T dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
             const T t = ei[u] + ej;
             const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
-            const T c3 = inv_cube<SOFT>(r2, c15, c1875);
+            const T c3 = inv_cube<SOFT>(r2, c15);
             const T wi = mj * c3, wj = mi[u] * c3;
             ax[u] = fma(wi, dx, ax[u]);
             ay[u] = fma(wi, dy, ay[u]);
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(64) void k_grav_split(const PileDev* __restrict__ p
   const int span = (nt + kGravSplits - 1) / kGravSplits;  // source tiles per split
   const int t0 = it.tj * span, t1 = min(t0 + span, nt);
   const int i0 = it.ti * B;
-  double c15, c1875;
-  series_coeffs(c15, c1875);
+  double c15;
+  series_coeffs(c15);
 
   T xi[IPT], yi[IPT], zi[IPT], ei[IPT], ax[IPT], ay[IPT], az[IPT];
 #pragma unroll
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(64) void k_grav_split(const PileDev* __restrict__ p
         const T dx = xj - xs[u], dy = yj - ys[u], dz = zj - zs[u];
         const T t = ei[u] + ej;
         const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, t * t)));
-        const T w = mj * inv_cube<SOFT>(r2, c15, c1875);
+        const T w = mj * inv_cube<SOFT>(r2, c15);
         ax[u] = fma(w, dx, ax[u]);
         ay[u] = fma(w, dy, ay[u]);
         az[u] = fma(w, dz, az[u]);

@@ -436,7 +436,7 @@ __device__ __forceinline__ void leaf_pairs(ConstRec64 rec, uint32_t t, double x,
     const bool self = t + u == (uint32_t)k;
     const double dx = sx[u] - x, dy = sy[u] - y, dz = sz[u] - z, e = ei + se[u];
     const double r2 = dx * dx + dy * dy + dz * dz + e * e;
-    const double c3 = (self ? 0.0 : sm[u]) * inv_cube<true>(self ? 1.0 : r2, c15, c1875);
+    const double c3 = (self ? 0.0 : sm[u]) * inv_cube<true>(self ? 1.0 : r2, c15);
     acc[0] += c3 * dx;
     acc[1] += c3 * dy;
     acc[2] += c3 * dz;
