@@ -42,8 +42,8 @@ CONTACT_BYTES_PER_CONTACT = 64
 # profile summaries); valid only for the gravity source it was measured on.
 MEASURED_TRAFFIC = {
     # (precision, spheres, default tile): (bytes per launch, source_hash("kernels_gravity.hip"))
-    ("fp64", 124958, 512): (2299.3e6, "4819b4985e946fcb"),
-    ("fp32", 124958, 1024): (539.8e6, "4819b4985e946fcb"),
+    ("fp64", 124958, 512): (2299.0e6, "f8d183b18bbd6b95"),
+    ("fp32", 124958, 1024): (539.5e6, "f8d183b18bbd6b95"),
 }
 
 
@@ -52,8 +52,8 @@ MEASURED_TRAFFIC = {
 # gravity source it was measured on.
 MEASURED_TREE_FLOP = {
     # (spheres, opening angle, leaf, order): (FLOP per launch, source_hash("kernels_tree.hip"))
-    (124958, 0.5, 32, 4): (3.665e10, "823728918897e80c"),
-    (999660, 0.5, 32, 4): (3.844e11, "823728918897e80c"),
+    (124958, 0.5, 32, 4): (3.609e10, "471bb11951ce97d0"),
+    (999660, 0.5, 32, 4): (3.797e11, "471bb11951ce97d0"),
 }
 
 
