@@ -73,12 +73,21 @@ def log(*a):
 
 
 def _cpu_model():
+    """The host CPU's model name with its family, model and stepping numbers
+    (a virtual machine may report only a generic name)."""
     try:
         with open("/proc/cpuinfo") as f:
-            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                        "")
+            first = f.read().split("\n\n", 1)[0]
     except OSError:
         return ""
+    fields = {}
+    for ln in first.splitlines():
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            fields.setdefault(k.strip(), v.strip())
+    name = fields.get("model name", "")
+    ids = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def cpu_baseline(inp, n_sample, seconds_cap):
