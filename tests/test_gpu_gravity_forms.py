@@ -118,12 +118,15 @@ def test_forms_agree_and_mix_in_an_engine(D):
             assert np.array_equal(got[f], alone[k][f]), (k, f)
 
 
-@pytest.mark.parametrize("n_agg,tile,prec", [(7000, 128, 0), (14000, 128, 0), (14000, 256, 1)])
-def test_super_tiles_sampled(D, n_agg, tile, prec):
+@pytest.mark.parametrize("n_agg,tile,prec,soft", [(7000, 128, 0, 0.5), (14000, 128, 0, 0.5),
+                                                   (14000, 256, 1, 0.5), (7000, 128, 0, 0.0),
+                                                   (14000, 256, 1, 0.0)])
+def test_super_tiles_sampled(D, n_agg, tile, prec, soft):
     """More tiles than super-tiles (35k and 70k spheres in tiles of 128: two
-    and three tiles per super-tile, the last one short): sampled spheres
-    against the oracle's exact sum, both forms."""
-    w = W.collapse_cloud(50 + n_agg // 7000, n_agg=n_agg)
+    and three tiles per super-tile, the last one short; 70k in tiles of 256:
+    two), softened and not: sampled spheres against the oracle's exact sum,
+    both forms."""
+    w = W.collapse_cloud(50 + n_agg // 7000, n_agg=n_agg, soft_frac=soft)
     idx = np.sort(np.random.default_rng(5).choice(w.n_sph, 160, replace=False))
     o = O.Oracle(w.params).add_workload(w, evaluate=False)
     F, _ = o.eval_subset(idx)
@@ -131,7 +134,8 @@ def test_super_tiles_sampled(D, n_agg, tile, prec):
     span = -(-nt // 256)
     assert span >= 2
     for form in (1, 2):
-        say("super-tiles", w.n_sph, "spheres, tile", tile, "span", span, "form", form, "prec", prec)
+        say("super-tiles", w.n_sph, "spheres, tile", tile, "span", span, "form", form, "prec", prec,
+            "soft", soft)
         sim = D.Sim(w.params, precision=prec)
         sim.set_tuning(gravity_tile=tile, gravity_form=form)
         sim.add_workload(w)
