@@ -299,9 +299,9 @@ dem_status dem_engine_step(dem_engine* eng, int64_t n_steps);
 dem_status dem_engine_detach(dem_engine* eng, dem_sim* sim);
 dem_status dem_engine_destroy(dem_engine* eng);
 /* Per-kernel timing of an engine's steps, as dem_set_profiling /
- * dem_get_profile for one system (eager launches with a HIP event between
- * consecutive kernels while enabled; totals in milliseconds in the order of
- * dem_profile_names). */
+ * dem_get_profile for one system with enabled = 1 (eager launches with a HIP
+ * event between consecutive kernels while enabled is nonzero; totals in
+ * milliseconds in the order of dem_profile_names). */
 dem_status dem_engine_set_profiling(dem_engine* eng, int32_t enabled);
 dem_status dem_engine_get_profile(const dem_engine* eng, double* kernel_ms, int32_t n_max,
                                   int64_t* n_steps);
@@ -350,12 +350,17 @@ dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
  * to tiles (default first) and returns how many there are. */
 int32_t dem_gravity_tiles(int32_t precision, int32_t* tiles, int32_t n_max);
 
-/* Per-kernel timing (measurement aid for benchmarks).  While enabled,
- * dem_step launches the step's kernels one by one (no graph) with a HIP event
- * before and after each, on the system's stream, and accumulates the elapsed
- * time of every kernel family.  dem_get_profile copies up to n_max totals in
- * milliseconds (order given by dem_profile_names, a ';'-separated list) and
- * the number of steps they cover.  Enabling or disabling clears the totals. */
+/* Per-kernel timing (measurement aid for benchmarks).  enabled = 1: dem_step
+ * launches the step's kernels one by one (no graph) with a HIP event before
+ * and after each, on the system's stream, and accumulates the elapsed time of
+ * every kernel family.  enabled = 2: dem_step launches the kernels (no graph)
+ * in the order and on the streams of the step graph -- gravity on a second
+ * stream beside the contact kernels -- with a HIP event before and after the
+ * gravity stage only, on the stream that runs it; only the gravity total is
+ * kept.  0 turns timing off; other values are INVALID_ARG.  dem_get_profile
+ * copies up to n_max totals in milliseconds (order given by
+ * dem_profile_names, a ';'-separated list) and the number of steps they
+ * cover.  Setting the mode clears the totals. */
 dem_status dem_set_profiling(dem_sim* sim, int32_t enabled);
 dem_status dem_get_profile(const dem_sim* sim, double* kernel_ms, int32_t n_max,
                            int64_t* n_steps);

@@ -317,8 +317,10 @@ struct dem_sim {
   int engine_slot = -1;
   dem_status last_status = DEM_OK;
   dem_tuning tune{0, 1.0, 0, 0, 0};
-  // per-kernel timing
-  bool profiling = false;
+  // per-kernel timing: 0 off, 1 launches one after another with events
+  // between kernels, 2 launches ordered as in the graph with events around
+  // the gravity stage only
+  int profiling = 0;
   std::vector<hipEvent_t> events;
   std::vector<double> prof_ms;
   int64_t prof_steps = 0;
@@ -698,6 +700,39 @@ dem_status profiled_passes(Batch& b, hipStream_t st, int64_t n_steps,
       HIPCHK(errsim, hipEventElapsedTime(&ms, ev[2 * m], ev[2 * m + 1]));
       prof_ms[m] += ms;
     }
+  }
+  prof_steps += n_steps;
+  return DEM_OK;
+}
+
+// Eager launches of n_steps passes as the step graph orders them (gravity on
+// the second stream beside the contact kernels), with a HIP event before and
+// after the gravity stage only, on the stream that runs it; accumulates the
+// gravity stage's milliseconds.
+dem_status gravity_timed_passes(Batch& b, hipStream_t st, int64_t n_steps,
+                                std::vector<hipEvent_t>& events, std::vector<double>& prof_ms,
+                                int64_t& prof_steps, dem_sim* errsim) {
+  HIPCHK(errsim, ensure_side(b));
+  const size_t need = size_t(2) * n_steps;
+  while (events.size() < need) {
+    hipEvent_t ev;
+    HIPCHK(errsim, hipEventCreate(&ev));
+    events.push_back(ev);
+  }
+  hipError_t rec = hipSuccess;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    hipEvent_t* ev = &events[size_t(2) * k];
+    enqueue_pass_marked(b, st, kModeStep, [&](int m, hipStream_t s, bool begin) {
+      if (m == kStageGravity && rec == hipSuccess) rec = hipEventRecord(ev[begin ? 0 : 1], s);
+    }, true);
+  }
+  HIPCHK(errsim, rec);
+  HIPCHK(errsim, hipStreamSynchronize(st));
+  prof_ms.resize(kNumStages, 0.0);
+  for (int64_t k = 0; k < n_steps; ++k) {
+    float ms = 0.f;
+    HIPCHK(errsim, hipEventElapsedTime(&ms, events[size_t(2) * k], events[size_t(2) * k + 1]));
+    prof_ms[kStageGravity] += ms;
   }
   prof_steps += n_steps;
   return DEM_OK;
@@ -1227,9 +1262,13 @@ dem_status dem_step(dem_sim* s, int64_t n_steps) {
   }
   s->stepped = true;
   if (n_steps == 0) return DEM_OK;
-  if (s->profiling) {
+  if (s->profiling == 1) {
     dem_status st = profiled_passes(s->own, s->stream, n_steps, s->events, s->prof_ms,
                                     s->prof_steps, s);
+    if (st != DEM_OK) return st;
+  } else if (s->profiling == 2) {
+    dem_status st = gravity_timed_passes(s->own, s->stream, n_steps, s->events, s->prof_ms,
+                                         s->prof_steps, s);
     if (st != DEM_OK) return st;
   } else {
     dem_status st = ensure_graph(s->own, s->stream, s);
@@ -1594,7 +1633,8 @@ int32_t dem_gravity_tiles(int32_t precision, int32_t* tiles, int32_t n_max) {
 
 dem_status dem_set_profiling(dem_sim* s, int32_t enabled) {
   if (!s) return fail(nullptr, DEM_ERR_INVALID_ARG, "sim is NULL");
-  s->profiling = enabled != 0;
+  if (enabled < 0 || enabled > 2) return fail(s, DEM_ERR_INVALID_ARG, "profiling must be 0, 1 or 2");
+  s->profiling = enabled;
   s->prof_ms.assign(kNumStages, 0.0);
   s->prof_steps = 0;
   return DEM_OK;

@@ -365,8 +365,11 @@ class Sim:
                        int(fused), int(gravity_form))
         _check(lib().dem_set_tuning(self.h, C.byref(t)), self.h)
 
-    def set_profiling(self, on: bool):
-        _check(lib().dem_set_profiling(self.h, int(bool(on))), self.h)
+    def set_profiling(self, on: bool, graph_order: bool = False):
+        """Per-kernel timing: launches one after another with events between
+        kernels, or (graph_order=True) launches ordered as in the step graph, gravity
+        beside the contact kernels, with events around the gravity stage only."""
+        _check(lib().dem_set_profiling(self.h, (2 if graph_order else 1) if on else 0), self.h)
 
     def profile(self) -> Dict[str, float]:
         """Accumulated per-kernel milliseconds and the steps they cover."""

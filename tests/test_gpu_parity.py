@@ -277,6 +277,39 @@ def test_bitwise_deterministic(D):
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
+def test_profiling_modes_do_not_change_results(D):
+    """Launches one after another with events between kernels (mode 1) and
+    launches ordered as in the step graph with events around the gravity
+    stage (mode 2) step the system exactly as the graph does; mode 2 keeps
+    only the gravity span."""
+    say("profiling modes")
+    w = W.collapse_cloud(52, n_agg=300, contact_seeded=True, spin_sigma=0.3, vel_sigma=0.1)
+    outs = []
+    profs = []
+    for mode in (0, 1, 2):
+        sim = D.Sim(w.params)
+        sim.add_workload(w)
+        if mode:
+            sim.set_profiling(True, graph_order=mode == 2)
+        sim.step(4)
+        profs.append(sim.profile())
+        sim.set_profiling(False)
+        sim.step(2)
+        outs.append(sim.read_state(pairs=True))
+        sim.close()
+    for m in (1, 2):
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], outs[m][k]), (m, k)
+    assert profs[1]["_steps"] == 4 and profs[2]["_steps"] == 4
+    assert profs[1]["gravity"] > 0 and profs[1]["forces"] > 0
+    assert profs[2]["gravity"] > 0
+    assert all(v == 0 for k, v in profs[2].items() if k not in ("gravity", "_steps"))
+    sim = D.Sim(w.params)
+    with pytest.raises(D.DemError):
+        D._check(D.lib().dem_set_profiling(sim.h, 3), sim.h)
+    sim.close()
+
+
 def test_checkpoint_restore_bit_identical(D):
     say("checkpoint/restore")
     w = W.periodic_box(61, n_agg=300, contact_seeded=True, spin_sigma=0.4, vel_sigma=0.2)
