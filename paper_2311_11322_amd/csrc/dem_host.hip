@@ -443,8 +443,10 @@ dem_status rebuild(Batch& b, hipStream_t st, dem_sim* errsim) {
       while (g < n_groups && tiles[g] != h.g_tile) ++g;
       if (g == n_groups) tiles[n_groups++] = h.g_tile;
       if (h.g_form == 2) {
-        for (int ti = 0; ti < h.g_nt; ++ti)
-          for (int sp = 0; sp < h.g_np; ++sp) gsg[g].push_back({p, ti, sp, 0});
+        const int grp = 64 * gravity_split_ipt(b.precision, h.g_tile);
+        const int n_grp = (h.ns + grp - 1) / grp;
+        for (int tg = 0; tg < n_grp; ++tg)
+          for (int sp = 0; sp < h.g_np; ++sp) gsg[g].push_back({p, tg, sp, 0});
       } else {
         if (h.g_np == h.g_nt) {
           for (int si = 0; si < h.g_np; ++si)

@@ -244,6 +244,9 @@ void launch_gravity_tiles(hipStream_t st, const PileDev* piles, const GravItem* 
                           int precision, bool softened, int tile, bool multi);
 void launch_gravity_split(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
                           int precision, bool softened, int tile);
+// Targets per lane of the per-target kernel for a precision and tile size
+// (a target group is 64 x that many slots).
+int gravity_split_ipt(int precision, int tile);
 void launch_gravity_combine(hipStream_t st, const PileDev* piles, const WorkItem* wl, int nblk,
                             int precision);
 // Supported tile sizes for a precision (default first); returns the count.
@@ -258,6 +261,10 @@ constexpr int64_t kReduceStageMin = 131072;
 // partial sums above which a system takes the per-target form by default.
 constexpr int kGravSlots = 256;
 constexpr int kGravSplits = 16;
+// Targets per lane of the per-target kernel at most (measured at 125k
+// spheres: FP64 2, 4, 8 took 10.5, 10.8, 11.0 ms; FP32 4, 8, 16 took 6.7,
+// 6.7, 6.4 ms).
+constexpr int kSplitIpt64 = 2, kSplitIpt32 = 16;
 constexpr int64_t kSymPartialMax = int64_t(64) << 30;
 // Spheres in one search launch from which each sphere gets four lanes
 // instead of eight.

@@ -254,25 +254,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// The per-target form (O(N) partial sums): one wave per (target tile I,
-// source split s).  Split s covers a run of consecutive source tiles; the
-// wave's lanes hold the targets of tile I and walk every source of the run
-// by a uniform index (scalar loads), evaluating each ordered pair once from
-// the target's side, so no reaction is carried and each sphere receives one
-// partial per split.  Twice the pair evaluations of the pair form (about
-// 1.8 times its time), for 16 partial sums per sphere.
+// The per-target form (O(N) partial sums): one wave per (target group,
+// source split s), a target group being 64 x IPT consecutive slots inside
+// one tile (IPT per lane, fewer than a tile holds, so that the launch has
+// enough waves).  Split s covers a run of consecutive source tiles; the
+// wave's lanes hold the group's targets and walk every source of the run by
+// a uniform index (scalar loads), evaluating each ordered pair once from the
+// target's side, so no reaction is carried and each sphere receives one
+// partial per split.  Twice the pair evaluations of the pair form, for 16
+// partial sums per sphere.
 template <typename T, int IPT, bool SOFT>
 __global__ __launch_bounds__(64) void k_grav_split(const PileDev* __restrict__ piles,
                                                    const GravItem* __restrict__ gl) {
-  constexpr int B = 64 * IPT;
+  constexpr int G = 64 * IPT;
   constexpr bool F32 = sizeof(T) == 4;
   const GravItem it = gl[blockIdx.x];
   const PileDev& P = piles[it.pile];
   if (P.status != 0) return;
-  const int ns = P.ns, nt = P.g_nt, lane = threadIdx.x;
+  const int ns = P.ns, nt = P.g_nt, B = P.g_tile, lane = threadIdx.x;
   const int span = (nt + kGravSplits - 1) / kGravSplits;  // source tiles per split
   const int t0 = it.tj * span, t1 = min(t0 + span, nt);
-  const int i0 = it.ti * B;
+  const int i0 = it.ti * G;
+  const int ti = i0 / B;                                   // the targets' tile
   double c15;
   series_coeffs(c15);
 
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(64) void k_grav_split(const PileDev* __restrict__ p
     T xs[IPT], ys[IPT], zs[IPT];
     T sx = 0, sy = 0, sz = 0;
     if (F32) {
-      const double* aI = P.ganchor + (size_t)it.ti * 4;
+      const double* aI = P.ganchor + (size_t)ti * 4;
       const double* aJ = P.ganchor + (size_t)tj * 4;
       sx = (T)(aJ[0] - aI[0]);
       sy = (T)(aJ[1] - aI[1]);
@@ -469,10 +472,17 @@ static void split_launch(hipStream_t st, const PileDev* piles, const GravItem* g
     hipLaunchKernelGGL((k_grav_split<T, IPT, false>), dim3(n), dim3(64), 0, st, piles, gl);
 }
 
+int gravity_split_ipt(int precision, int tile) {
+  // targets per lane of the per-target kernel: at most kSplitIpt64 (FP64) or
+  // kSplitIpt32 (FP32), and never more than one tile holds
+  const int cap = precision == 1 ? kSplitIpt32 : kSplitIpt64;
+  return std::min(tile / 64, cap);
+}
+
 void launch_gravity_split(hipStream_t st, const PileDev* piles, const GravItem* gl, int nitems,
                           int precision, bool softened, int tile) {
   if (nitems <= 0) return;
-  const int ipt = tile / 64;
+  const int ipt = gravity_split_ipt(precision, tile);
   if (precision == 1) {
     if (ipt == 4) split_launch<float, 4>(st, piles, gl, nitems, softened);
     else if (ipt == 16) split_launch<float, 16>(st, piles, gl, nitems, softened);
