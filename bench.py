@@ -42,8 +42,8 @@ CONTACT_BYTES_PER_CONTACT = 64
 # profile summaries); valid only for the gravity source it was measured on.
 MEASURED_TRAFFIC = {
     # (precision, spheres, default tile): (bytes per launch, source_hash("kernels_gravity.hip"))
-    ("fp64", 124958, 512): (2299.0e6, "f8d183b18bbd6b95"),
-    ("fp32", 124958, 1024): (539.5e6, "f8d183b18bbd6b95"),
+    ("fp64", 124958, 512): (2299.0e6, "065b5f21aae1cf9c"),
+    ("fp32", 124958, 1024): (539.8e6, "065b5f21aae1cf9c"),
 }
 
 
