@@ -41,9 +41,10 @@ CONTACT_BYTES_PER_CONTACT = 64
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (see the
 # profile summaries); valid only for the gravity source it was measured on.
 MEASURED_TRAFFIC = {
-    # (precision, spheres, default tile): (bytes per launch, source_hash("kernels_gravity.hip"))
-    ("fp64", 124958, 512): (2299.0e6, "065b5f21aae1cf9c"),
-    ("fp32", 124958, 1024): (539.8e6, "065b5f21aae1cf9c"),
+    # (precision, spheres, tile, form of the exact sum):
+    #     (bytes per launch, source_hash("kernels_gravity.hip"))
+    ("fp64", 124958, 512, 1): (2299.0e6, "065b5f21aae1cf9c"),
+    ("fp32", 124958, 1024, 1): (539.8e6, "065b5f21aae1cf9c"),
 }
 
 
@@ -224,6 +225,8 @@ def main():
                          "(opening angle 0.5, leaves of 32, FP64)")
     ap.add_argument("--n-agg", type=int, default=25000)
     ap.add_argument("--gravity-tile", type=int, default=0, help="0: library default")
+    ap.add_argument("--gravity-form", type=int, default=0, choices=[0, 1, 2],
+                    help="exact sum: 0 library choice, 1 pairs, 2 per target")
     ap.add_argument("--cell-scale", type=float, default=1.0)
     ap.add_argument("--full-run-steps", type=int, default=2000,
                     help="steps of the whole-run leg of the headline workload (0: skip)")
@@ -301,7 +304,7 @@ def main():
         w.params.update(gravity_tree=1, theta=0.5, tree_leaf=32, tree_order=4)
     alloc = dem.TorchAllocator(0)
     sim = dem.Sim(w.params, precision=prec, allocator=alloc, stream=dem.torch_stream())
-    sim.set_tuning(args.gravity_tile, args.cell_scale)
+    sim.set_tuning(args.gravity_tile, args.cell_scale, gravity_form=args.gravity_form)
     sim.add_workload(w)
     log("added; warmup", args.warmup)
     sim.step(args.warmup)
@@ -360,7 +363,7 @@ def main():
     achieved = flop / (grav_ms * 1e-3) / 1e12
     dt_key = "fp32" if prec == dem.PREC_FP32_FORCE else "fp64"
     tile = args.gravity_tile or dem.gravity_tiles(prec)[0]
-    meas = MEASURED_TRAFFIC.get((dt_key, n, tile))
+    meas = MEASURED_TRAFFIC.get((dt_key, n, tile, args.gravity_form or 1))
     traffic = (meas[0] if meas and meas[1] == source_hash("kernels_gravity.hip")
                and args.gravity == "direct"
                else None)
@@ -387,7 +390,10 @@ def main():
                                f"({w.n_sph} spheres), ball at packing 0.15, G=1, softening 0.5, "
                                f"dt=5e-4, {'plain FP64' if prec == 0 else 'FP32-force'}"
                                + (", tree gravity (opening angle 0.5, leaves of 32)"
-                                  if args.gravity == "tree" else ""),
+                                  if args.gravity == "tree" else "")
+                               + (", per-target form of the exact sum"
+                                  if args.gravity == "direct" and args.gravity_form == 2
+                                  else ""),
                    "n_spheres": w.n_sph, "n_aggregates": w.n_agg, "contacts": state["n_pairs"]},
         "graph_replay_value": round(graph_value, 1),
         "timing": ("value: K steps launched as the step graph orders them, gravity on a "
