@@ -45,6 +45,8 @@ MEASURED_TRAFFIC = {
     #     (bytes per launch, source_hash("kernels_gravity.hip"))
     ("fp64", 124958, 512, 1): (2299.0e6, "065b5f21aae1cf9c"),
     ("fp32", 124958, 1024, 1): (539.8e6, "065b5f21aae1cf9c"),
+    ("fp64", 124958, 512, 2): (196.9e6, "065b5f21aae1cf9c"),
+    ("fp64", 499845, 512, 1): (26922.6e6, "065b5f21aae1cf9c"),
 }
 
 
