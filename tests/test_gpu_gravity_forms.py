@@ -142,3 +142,54 @@ def test_super_tiles_sampled(D, n_agg, tile, prec, soft):
         g = sim.read_state(["sph_force"])["sph_force"]
         sim.close()
         assert rel_err(g[idx], F) <= (1e-12 if prec == 0 else 1e-5), form
+
+
+def test_super_tiles_default_tiles_unsoftened(D):
+    """The default tiles (512 in FP64, eight targets per lane) past 256
+    tiles, unsoftened: 140k spheres, super-tiles of two, sampled spheres
+    against the oracle's exact sum."""
+    w = W.collapse_cloud(53, n_agg=28000, soft_frac=0.0)
+    assert -(-w.n_sph // 512) > 256
+    idx = np.sort(np.random.default_rng(6).choice(w.n_sph, 128, replace=False))
+    o = O.Oracle(w.params).add_workload(w, evaluate=False)
+    F, _ = o.eval_subset(idx)
+    for prec, tile in ((0, 0), (1, 512)):
+        say("super-tiles at the default tile", w.n_sph, "spheres, unsoftened, prec", prec)
+        sim = D.Sim(w.params, precision=prec)
+        sim.set_tuning(gravity_tile=tile)
+        sim.add_workload(w)
+        g = sim.read_state(["sph_force"])["sph_force"]
+        sim.close()
+        assert rel_err(g[idx], F) <= (1e-12 if prec == 0 else 1e-5), prec
+
+
+def test_super_tile_and_tile_pair_piles_in_one_engine(D):
+    """A pile on super-tiles and a pile of single tile pairs in one engine
+    (two launches of the pair kernel for one tile size) give their runs
+    alone bit for bit."""
+    ws = [W.collapse_cloud(54, n_agg=7000), W.collapse_cloud(55, n_agg=400, contact_seeded=True)]
+    say("super-tile and tile-pair piles in one engine", [w.n_sph for w in ws])
+    alone = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.set_tuning(gravity_tile=128)
+        s.add_workload(w)
+        s.step(2)
+        alone.append(s.read_state(["agg_pos", "agg_vel", "sph_force"], pairs=True))
+        s.close()
+    eng = D.Engine(1 << 33)
+    sims = []
+    for w in ws:
+        s = D.Sim(w.params)
+        s.set_tuning(gravity_tile=128)
+        s.add_workload(w)
+        eng.attach(s)
+        sims.append(s)
+    assert eng.step(2) == D.DEM_OK
+    for s in list(eng.sims):
+        eng.detach(s)
+    for k, s in enumerate(sims):
+        got = s.read_state(["agg_pos", "agg_vel", "sph_force"], pairs=True)
+        s.close()
+        for f in ("agg_pos", "agg_vel", "pair_keys", "sph_force"):
+            assert np.array_equal(got[f], alone[k][f]), (k, f)
