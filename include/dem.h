@@ -343,7 +343,7 @@ typedef struct {
                                   super-tile (at most 256 x 3 values per sphere); 2 per
                                   target: each ordered pair from its target's side, one
                                   partial per sphere and source split (16 splits), about
-                                  1.8x the time.  Same sum in another order (rounding). */
+                                  1.7x the time.  Same sum in another order (rounding). */
 } dem_tuning;
 dem_status dem_set_tuning(dem_sim* sim, const dem_tuning* tuning);
 /* Gravity tile sizes supported for a precision: writes up to n_max of them
