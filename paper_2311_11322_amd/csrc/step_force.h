@@ -148,6 +148,35 @@ __device__ __forceinline__ void find_hist(const PairCtx<T>& c, uint32_t& o, uint
   }
 }
 
+// The same search in b's partner a's previous upper run [o, o1) when no merge
+// pointer is carried (the lower contacts): the first four keys are loaded
+// together, so the usual short run costs one round of loads, not a chain.
+template <typename T>
+__device__ __forceinline__ void find_hist_run(const PairCtx<T>& c, uint32_t o, uint32_t o1,
+                                              uint32_t b, T hs[kHist]) {
+  const uint32_t n = o1 - o;
+  uint32_t kk[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) kk[u] = (uint32_t)u < n ? c.old_j[o + u] : 0xffffffffu;
+  int pos = -1;
+#pragma unroll
+  for (int u = 3; u >= 0; --u)
+    if (kk[u] == b) pos = u;
+  uint32_t p = o + (uint32_t)pos;
+  if (pos < 0 && n > 4u) {
+    p = o + 4u;
+    while (p < o1 && c.old_j[p] < b) ++p;
+    if (!(p < o1 && c.old_j[p] == b)) p = o1;
+  } else if (pos < 0) {
+    p = o1;
+  }
+  if (p < o1) {
+    for (int k = 0; k < kHist; ++k) hs[k] = (T)c.old_h[(size_t)k * c.cap + p];
+  } else {
+    for (int k = 0; k < kHist; ++k) hs[k] = (T)0;
+  }
+}
+
 // Force on a, torques on a and b about their centres, and the new spring
 // history of one contact (a, b), a < b.
 template <typename T>
@@ -300,10 +329,10 @@ __device__ __forceinline__ void forces_one(const PileDev& P, const PairCtx<T>& c
     const Body<T> o0 = load_body<T>(P, j0, ns, na);
     const Body<T> o1 = load_body<T>(P, j1, ns, na);
     T h0[kHist], h1[kHist];
-    uint32_t a0 = c.old_off[j0], a1 = c.old_off[j1];
+    const uint32_t a0 = c.old_off[j0], a1 = c.old_off[j1];
     const uint32_t b0 = c.old_off[j0 + 1], b1 = c.old_off[j1 + 1];
-    find_hist<T>(c, a0, b0, i, h0);
-    find_hist<T>(c, a1, b1, i, h1);
+    find_hist_run<T>(c, a0, b0, i, h0);
+    find_hist_run<T>(c, a1, b1, i, h1);
     ContactOut<T> r0, r1;
     sphere_contact<T>(c, cp, o0, me, h0, r0);
     acc_lo(r0);
@@ -314,8 +343,7 @@ __device__ __forceinline__ void forces_one(const PileDev& P, const PairCtx<T>& c
     const uint32_t j = P.lo_nbr[e];
     const Body<T> o = load_body<T>(P, j, ns, na);
     T hs[kHist];
-    uint32_t q = c.old_off[j];
-    find_hist<T>(c, q, c.old_off[j + 1], i, hs);
+    find_hist_run<T>(c, c.old_off[j], c.old_off[j + 1], i, hs);
     ContactOut<T> r;
     sphere_contact<T>(c, cp, o, me, hs, r);
     acc_lo(r);
